@@ -1,0 +1,202 @@
+/*
+ * inim.h -- C ABI of the MI355X (gfx950) scatterplot regulariser built on
+ * integral images, after Rave, Molchanov and Linsen, "De-cluttering
+ * Scatterplots with Integral Images" (IEEE TVCG; arXiv 2408.06513).
+ *
+ * Conventions shared by every entry point
+ *   - A raster has res x res texels, res = 2^k with 2 <= res <= 16384 (the
+ *     paper's 2^k x 2^k textures, Sec. 3.2 and Sec. 4.1).  It is stored
+ *     row-major: texel (i, j) -- column i (x), row j (y), origin top-left
+ *     (Sec. 4.1) -- lives at index j * res + i.
+ *   - Samples are float32 pairs (x, y) in [0, 1]^2 (Sec. 4.1), array [n][2].
+ *   - Texel (i, j) stands for the point ((i + 1/2) / res, (j + 1/2) / res).
+ *   - Every pointer argument named as device memory is HIP device memory
+ *     owned by the caller.  The library never allocates, frees or synchronises
+ *     device memory; all work is enqueued on `stream` (0 = the null stream)
+ *     and runs asynchronously.  Only inim_sync_status synchronises.
+ *   - Scratch memory is the caller's `ws` buffer (device memory, 256-byte
+ *     aligned, at least the size the matching *_workspace_size call reports).
+ *     Its first 256 bytes hold a status word that the kernels of one call set
+ *     when they meet invalid data; each call clears it when it starts.  Calls
+ *     that share a workspace must not overlap in time.
+ *   - Errors found on the host are returned synchronously before anything is
+ *     enqueued; the text of the last one is available from inim_last_error()
+ *     (thread-local).
+ *
+ * Plane bits (Sec. 3.1), in this order wherever several planes are stored:
+ *   alpha   sum over i' <= i, j' <= j          beta    i' <= i, j' >  j
+ *   gamma   i' >  i, j' >  j                   delta   i' >  i, j' <= j
+ *   alpha_t i'+j' <= i+j, i'-j' >= i-j         beta_t  i'+j' <= i+j, i'-j' <  i-j
+ *   gamma_t i'+j' >  i+j, i'-j' <  i-j         delta_t i'+j' >  i+j, i'-j' >= i-j
+ *
+ * Marginals (double, device memory), layout
+ *   X[res] | Y[res] | U[2res-1] | V[2res-1] | C
+ *   X(i) = sum over i' <= i;  Y(j) = sum over j' <= j;  U(u) = sum over
+ *   i'+j' <= u;  V[k] = sum over i'-j' >= k-(res-1);  C = total (Sec. 3.1).
+ */
+#ifndef INIM_H
+#define INIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    INIM_OK = 0,
+    INIM_EINVAL = 1,     /* bad argument (size, pointer, mask, parameter) */
+    INIM_EDOMAIN = 2,    /* a sample is NaN or outside [0,1]^2 (reported by inim_sync_status) */
+    INIM_ERANGE = 3,     /* n >= 2^32 where counts are 32-bit */
+    INIM_EWORKSPACE = 4, /* ws is NULL, misaligned or smaller than required */
+    INIM_EHIP = 5        /* a HIP call failed; see inim_last_error() */
+} inim_status;
+
+enum {
+    INIM_ALPHA = 1u << 0,
+    INIM_BETA = 1u << 1,
+    INIM_GAMMA = 1u << 2,
+    INIM_DELTA = 1u << 3,
+    INIM_ALPHA_T = 1u << 4,
+    INIM_BETA_T = 1u << 5,
+    INIM_GAMMA_T = 1u << 6,
+    INIM_DELTA_T = 1u << 7,
+    INIM_MIN = INIM_ALPHA | INIM_ALPHA_T,
+    INIM_ALL = 0xFFu
+};
+
+typedef enum { INIM_U32 = 0, INIM_F32 = 1 } inim_dtype;
+
+/*
+ * Smoothing and background parameters (Sec. 4.1, eq. (dr) and eq. (d0)).
+ *   radius  Gaussian taps |m| <= radius along each axis, 0 <= radius <= 32;
+ *           0 means no smoothing (the count raster itself is the density).
+ *   sigma   Gaussian standard deviation in texels; <= 0 selects radius / 2.
+ *   d0      background density added to every texel; < 0 selects the paper's
+ *           choice n / res^2 (average samples per texel).
+ * Defaults (inim_default_params): radius 8, sigma 4 (radius / 2), d0 = -1.
+ */
+typedef struct {
+    int32_t radius;
+    float sigma;
+    double d0;
+} inim_params;
+
+void inim_default_params(inim_params* p);
+
+/* Static description of a status code; never NULL. */
+const char* inim_strerror(int status);
+
+/* Thread-local text of the last host-side error of this thread ("" if none). */
+const char* inim_last_error(void);
+
+/*
+ * Workspace for inim_rasterize, inim_advect and inim_regularize at this size:
+ * status word, count raster, density raster, deformation field and the
+ * integral-image carries.  `p` may be NULL (defaults).  EINVAL on bad sizes.
+ */
+int inim_workspace_size(int32_t res, int64_t n, const inim_params* p, size_t* bytes);
+
+/* Workspace for inim_inim_u32 / inim_inim_f32 at this size and type. */
+int inim_inim_workspace_size(int32_t res, inim_dtype dt, size_t* bytes);
+
+/*
+ * Step 1 of the algorithm (Sec. 4.3; density field of Sec. 4.1): every sample
+ * adds one to texel (min(floor(x res), res-1), min(floor(y res), res-1));
+ * then the counts are convolved with the normalised separable Gaussian of
+ * `p`, the raster continued across its border by half-sample symmetric
+ * reflection (... c b a | a b c ...).
+ *   xy       device, float [n][2], read only.
+ *   counts   device, uint32 [res*res], written (exact sample counts).
+ *   density  device, float [res*res], written with the smoothed counts; may be
+ *            NULL.  With radius 0 it receives the counts as floats.
+ * A NaN or out-of-range sample sets the status word (EDOMAIN); the counts are
+ * then incomplete.  ERANGE if n >= 2^32.
+ */
+int inim_rasterize(const float* xy, int64_t n, int32_t res, const inim_params* p,
+                   uint32_t* counts, float* density, void* ws, size_t ws_bytes,
+                   hipStream_t stream);
+
+/*
+ * Step 2 (Sec. 3.1 and Sec. 4.4): the integral images selected by `mask` of a
+ * res x res raster, plus all marginals.
+ *   img      device, uint32 or float [res*res], read only.
+ *   planes   device, [popcount(mask)][res*res] of the input's type, planes in
+ *            bit order; written.  May be NULL when mask == 0.
+ *   marg     device, double [4 res - 1], the marginals above; may be NULL.
+ * uint32: planes and marginals are exact modulo 2^32 (exact when the total is
+ * below 2^32).  float: sums are accumulated in double and rounded once; for
+ * strictly positive inputs every element is within 1e-6 relative of the exact
+ * sum, and texels whose region is empty by construction (for instance beta
+ * on the last row) are exactly 0.
+ * EINVAL for a bad size, an unknown mask bit or a NULL plane pointer with a
+ * non-zero mask; EWORKSPACE if ws is too small.
+ */
+int inim_inim_u32(const uint32_t* img, int32_t res, uint32_t mask, uint32_t* planes,
+                  double* marg, void* ws, size_t ws_bytes, hipStream_t stream);
+int inim_inim_f32(const float* img, int32_t res, uint32_t mask, float* planes,
+                  double* marg, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Step 3, per texel (Sec. 4.2 eq. (map_res) built on Sec. 3.2 eq. (map)):
+ *   T(p) = p + t(p; d_r + d0) - t(p; d0)
+ * where the eight planes of d_r are rebuilt from alpha, alpha_t and the
+ * marginals, and those of the constant d0 are exact closed forms (the defect
+ * t(p; d0) does not depend on the value of d0 > 0).
+ *   alpha, alpha_t  device planes of d_r (inim_inim_* output, type `dt`).
+ *   marg            device marginals of d_r (inim_inim_* output).
+ *   d0              background density, >= 0.
+ *   field           device, float [res*res][2] (x, y per texel); written.
+ */
+int inim_deform(const void* alpha, const void* alpha_t, inim_dtype dt, const double* marg,
+                int32_t res, double d0, float* field, hipStream_t stream);
+
+/*
+ * Step 3, per sample (Sec. 4.2): each sample takes the bilinear interpolation
+ * of `field` from the four nearest texel centres.  The cell index is clamped
+ * to [0, res-2] and the fraction is not, so border samples extrapolate
+ * linearly; the result is clamped to [0,1]^2.
+ *   field  device, float [res*res][2], read only.
+ *   xy     device, float [n][2], updated in place.
+ * If any sample is NaN or outside [0,1]^2 the status word is set (EDOMAIN) and
+ * no sample is modified.
+ */
+int inim_advect(const float* field, int32_t res, float* xy, int64_t n, void* ws,
+                size_t ws_bytes, hipStream_t stream);
+
+/*
+ * The whole algorithm (Sec. 4.3): `iters` times splat + smooth, integral
+ * images, per-texel deformation and bilinear advection, in place on xy.
+ *   xy     device, float [n][2], updated in place.
+ *   n == 0 or iters == 0 is a no-op returning INIM_OK.
+ * Device-side errors (EDOMAIN) leave xy unchanged and are reported by
+ * inim_sync_status.  ERANGE if n >= 2^32.
+ */
+int inim_regularize(float* xy, int64_t n, int32_t res, int32_t iters, const inim_params* p,
+                    void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * inim_regularize instrumented for measurement: records a HIP event before
+ * and after every stage of every iteration on `stream`, synchronises, and
+ * adds the elapsed milliseconds of each stage into stage_ms[0..5]:
+ *   0 fill+splat  1 smooth  2 integral-image carries  3 integral images +
+ *   deformation  4 advect  5 whole call.
+ * stage_ms is host memory, not cleared.  Same results as inim_regularize.
+ */
+int inim_regularize_timed(float* xy, int64_t n, int32_t res, int32_t iters, const inim_params* p,
+                          void* ws, size_t ws_bytes, hipStream_t stream, double* stage_ms);
+
+/*
+ * Waits for `stream`, returns the status word of the last call that used ws
+ * (INIM_OK or INIM_EDOMAIN) and clears it.  EHIP if the synchronisation fails.
+ */
+int inim_sync_status(void* ws, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* INIM_H */

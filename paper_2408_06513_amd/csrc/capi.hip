@@ -1,0 +1,368 @@
+// capi.hip -- the extern "C" entry points of libinim (declared in inim.h):
+// argument validation, workspace layout and the launch sequence of each call.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "inim.h"
+#include "inim_plan.h"
+#include "launch.h"
+
+using namespace inim;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    return fail(INIM_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool valid_res(int32_t res) { return res >= 2 && res <= 16384 && (res & (res - 1)) == 0; }
+
+int check_res(int32_t res) {
+    if (!valid_res(res)) return fail(INIM_EINVAL, "res=%d is not a power of two in [2, 16384]", (int)res);
+    return INIM_OK;
+}
+
+struct Params {
+    int radius;
+    double sigma;
+    double d0;  // < 0: n / res^2
+};
+
+int resolve_params(const inim_params* p, Params& out) {
+    inim_params d;
+    inim_default_params(&d);
+    if (p == nullptr) p = &d;
+    if (p->radius < 0 || p->radius > kMaxRadius)
+        return fail(INIM_EINVAL, "radius=%d outside [0, %d]", (int)p->radius, kMaxRadius);
+    if (!std::isfinite(p->sigma)) return fail(INIM_EINVAL, "sigma is not finite");
+    if (!std::isfinite(p->d0)) return fail(INIM_EINVAL, "d0 is not finite");
+    out.radius = p->radius;
+    out.sigma = p->sigma > 0.0f ? (double)p->sigma : 0.5 * (double)p->radius;
+    out.d0 = p->d0;
+    return INIM_OK;
+}
+
+// Normalised Gaussian taps exp(-m^2 / (2 sigma^2)), |m| <= r, summed in double.
+BlurTaps make_taps(int r, double sigma) {
+    BlurTaps t;
+    std::memset(&t, 0, sizeof t);
+    t.r = r;
+    if (r == 0) {
+        t.w[0] = 1.0f;
+        return t;
+    }
+    double w[2 * kMaxRadius + 1], s = 0.0;
+    for (int m = -r; m <= r; ++m) {
+        w[m + r] = std::exp(-(double)m * m / (2.0 * sigma * sigma));
+        s += w[m + r];
+    }
+    for (int k = 0; k <= 2 * r; ++k) t.w[k] = (float)(w[k] / s);
+    return t;
+}
+
+constexpr size_t kStatusBytes = 256;
+
+// Workspace of rasterize / advect / regularize.
+struct RegLayout {
+    size_t status, counts, density, field, scratch, total;
+    Geom g;
+    bool f32;  // integral images of the float density (radius > 0) or of the counts
+};
+
+RegLayout reg_layout(int32_t res, int radius) {
+    RegLayout L;
+    const size_t NN = (size_t)res * (size_t)res;
+    L.f32 = radius > 0;
+    L.g = make_geom(res, L.f32 ? 16 : 4);
+    size_t o = 0;
+    L.status = o; o += kStatusBytes;
+    L.counts = o; o += align256(NN * 4);
+    L.density = o; o += align256(NN * 4);
+    L.field = o; o += align256(NN * 8);
+    L.scratch = o; o += inim_scratch_bytes(L.g, L.f32 ? 16 : 4);
+    L.total = o;
+    return L;
+}
+
+int check_ws(const void* ws, size_t ws_bytes, size_t need) {
+    if (ws == nullptr) return fail(INIM_EWORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws & 255u) != 0) return fail(INIM_EWORKSPACE, "workspace is not 256-byte aligned");
+    if (ws_bytes < need) return fail(INIM_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    return INIM_OK;
+}
+
+int check_xy(const void* xy, int64_t n) {
+    if (n < 0) return fail(INIM_EINVAL, "n=%lld is negative", (long long)n);
+    if (n > 0 && xy == nullptr) return fail(INIM_EINVAL, "xy is NULL with n=%lld", (long long)n);
+    if (n >= ((int64_t)1 << 32)) return fail(INIM_ERANGE, "n=%lld does not fit 32-bit counts", (long long)n);
+    return INIM_OK;
+}
+
+// One iteration of Sec. 4.3 on the caller's stream; `events` (optional) gets
+// 6 events recorded at the stage boundaries.
+int enqueue_iteration(float* xy, int64_t n, int32_t res, const Params& P, double d0, const BlurTaps& taps,
+                      const RegLayout& L, char* ws, bool first, hipStream_t st, hipEvent_t* ev) {
+    int* status = reinterpret_cast<int*>(ws + L.status);
+    uint32_t* counts = reinterpret_cast<uint32_t*>(ws + L.counts);
+    float* density = reinterpret_cast<float*>(ws + L.density);
+    float2* field = reinterpret_cast<float2*>(ws + L.field);
+    void* scratch = ws + L.scratch;
+    const size_t NN = (size_t)res * res;
+    hipError_t e;
+    if (ev) (void)hipEventRecord(ev[0], st);
+    if ((e = launch_fill(counts, NN, status, first, st)) != hipSuccess) return hip_fail(e, "fill");
+    if ((e = launch_splat(reinterpret_cast<const float2*>(xy), n, res, counts, status, st)) != hipSuccess)
+        return hip_fail(e, "splat");
+    if (ev) (void)hipEventRecord(ev[1], st);
+    if (L.f32) {
+        if ((e = launch_blur(counts, density, res, taps, status, st)) != hipSuccess) return hip_fail(e, "blur");
+    }
+    if (ev) (void)hipEventRecord(ev[2], st);
+    if (L.f32)
+        e = launch_inim_carries<float>(density, L.g, scratch, status, st);
+    else
+        e = launch_inim_carries<uint32_t>(counts, L.g, scratch, status, st);
+    if (e != hipSuccess) return hip_fail(e, "integral-image carries");
+    if (ev) (void)hipEventRecord(ev[3], st);
+    if (L.f32)
+        e = launch_inim_final<float>(density, L.g, scratch, 0u, nullptr, field, d0, nullptr, status, st);
+    else
+        e = launch_inim_final<uint32_t>(counts, L.g, scratch, 0u, nullptr, field, d0, nullptr, status, st);
+    if (e != hipSuccess) return hip_fail(e, "integral images + deformation");
+    if (ev) (void)hipEventRecord(ev[4], st);
+    if ((e = launch_advect(field, res, reinterpret_cast<float2*>(xy), n, status, st)) != hipSuccess)
+        return hip_fail(e, "advect");
+    if (ev) (void)hipEventRecord(ev[5], st);
+    (void)P;
+    return INIM_OK;
+}
+
+int regularize_impl(float* xy, int64_t n, int32_t res, int32_t iters, const inim_params* p, void* ws,
+                    size_t ws_bytes, hipStream_t stream, double* stage_ms) {
+    int s;
+    if ((s = check_res(res)) != INIM_OK) return s;
+    if ((s = check_xy(xy, n)) != INIM_OK) return s;
+    if (iters < 0) return fail(INIM_EINVAL, "iters=%d is negative", (int)iters);
+    Params P;
+    if ((s = resolve_params(p, P)) != INIM_OK) return s;
+    const RegLayout L = reg_layout(res, P.radius);
+    if ((s = check_ws(ws, ws_bytes, L.total)) != INIM_OK) return s;
+    if (n == 0 || iters == 0) {
+        // nothing to do, but the call still resets the status word it reports
+        hipError_t e = launch_fill(nullptr, 0, reinterpret_cast<int*>((char*)ws + L.status), true, stream);
+        return e == hipSuccess ? INIM_OK : hip_fail(e, "fill");
+    }
+    const double d0 = P.d0 < 0.0 ? (double)n / ((double)res * (double)res) : P.d0;
+    const BlurTaps taps = make_taps(P.radius, P.sigma);
+    hipEvent_t ev[6];
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (stage_ms) {
+        for (int k = 0; k < 6; ++k)
+            if (hipEventCreate(&ev[k]) != hipSuccess) return fail(INIM_EHIP, "hipEventCreate failed");
+        if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
+            return fail(INIM_EHIP, "hipEventCreate failed");
+        (void)hipEventRecord(t0, stream);
+    }
+    for (int it = 0; it < iters; ++it) {
+        s = enqueue_iteration(xy, n, res, P, d0, taps, L, (char*)ws, it == 0, stream, stage_ms ? ev : nullptr);
+        if (s != INIM_OK) break;
+        if (stage_ms) {
+            if (hipEventSynchronize(ev[5]) != hipSuccess) { s = fail(INIM_EHIP, "hipEventSynchronize failed"); break; }
+            for (int k = 0; k < 5; ++k) {
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+                stage_ms[k] += ms;
+            }
+        }
+    }
+    if (stage_ms) {
+        (void)hipEventRecord(t1, stream);
+        if (hipEventSynchronize(t1) != hipSuccess && s == INIM_OK) s = fail(INIM_EHIP, "hipEventSynchronize failed");
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, t0, t1);
+        stage_ms[5] += ms;
+        for (int k = 0; k < 6; ++k) (void)hipEventDestroy(ev[k]);
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+    }
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+void inim_default_params(inim_params* p) {
+    if (!p) return;
+    p->radius = 8;
+    p->sigma = 4.0f;
+    p->d0 = -1.0;
+}
+
+const char* inim_strerror(int status) {
+    switch (status) {
+        case INIM_OK: return "ok";
+        case INIM_EINVAL: return "invalid argument";
+        case INIM_EDOMAIN: return "a sample is NaN or outside the unit square";
+        case INIM_ERANGE: return "sample count exceeds 32-bit counts";
+        case INIM_EWORKSPACE: return "workspace missing, misaligned or too small";
+        case INIM_EHIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char* inim_last_error(void) { return g_last_error.c_str(); }
+
+int inim_workspace_size(int32_t res, int64_t n, const inim_params* p, size_t* bytes) {
+    int s;
+    if (bytes == nullptr) return fail(INIM_EINVAL, "bytes is NULL");
+    if ((s = check_res(res)) != INIM_OK) return s;
+    if (n < 0) return fail(INIM_EINVAL, "n=%lld is negative", (long long)n);
+    Params P;
+    if ((s = resolve_params(p, P)) != INIM_OK) return s;
+    *bytes = reg_layout(res, P.radius).total;
+    return INIM_OK;
+}
+
+int inim_inim_workspace_size(int32_t res, inim_dtype dt, size_t* bytes) {
+    int s;
+    if (bytes == nullptr) return fail(INIM_EINVAL, "bytes is NULL");
+    if ((s = check_res(res)) != INIM_OK) return s;
+    if (dt != INIM_U32 && dt != INIM_F32) return fail(INIM_EINVAL, "unknown dtype %d", (int)dt);
+    *bytes = kStatusBytes + inim_scratch_bytes(make_geom(res, dt == INIM_F32 ? 16 : 4), dt == INIM_F32 ? 16 : 4);
+    return INIM_OK;
+}
+
+int inim_rasterize(const float* xy, int64_t n, int32_t res, const inim_params* p, uint32_t* counts, float* density,
+                   void* ws, size_t ws_bytes, hipStream_t stream) {
+    int s;
+    if ((s = check_res(res)) != INIM_OK) return s;
+    if ((s = check_xy(xy, n)) != INIM_OK) return s;
+    if (counts == nullptr) return fail(INIM_EINVAL, "counts is NULL");
+    Params P;
+    if ((s = resolve_params(p, P)) != INIM_OK) return s;
+    if ((s = check_ws(ws, ws_bytes, kStatusBytes)) != INIM_OK) return s;
+    int* status = reinterpret_cast<int*>(ws);
+    const size_t NN = (size_t)res * res;
+    hipError_t e;
+    if ((e = launch_fill(counts, NN, status, true, stream)) != hipSuccess) return hip_fail(e, "fill");
+    if ((e = launch_splat(reinterpret_cast<const float2*>(xy), n, res, counts, status, stream)) != hipSuccess)
+        return hip_fail(e, "splat");
+    if (density != nullptr) {
+        const BlurTaps taps = make_taps(P.radius, P.sigma);
+        if ((e = launch_blur(counts, density, res, taps, status, stream)) != hipSuccess) return hip_fail(e, "blur");
+    }
+    return INIM_OK;
+}
+
+static int inim_common(const void* img, int32_t res, uint32_t mask, const void* planes, void* ws, size_t ws_bytes,
+                       inim_dtype dt) {
+    int s;
+    if ((s = check_res(res)) != INIM_OK) return s;
+    if (img == nullptr) return fail(INIM_EINVAL, "img is NULL");
+    if (mask & ~(uint32_t)INIM_ALL) return fail(INIM_EINVAL, "mask 0x%x has unknown bits", mask);
+    if (mask != 0 && planes == nullptr) return fail(INIM_EINVAL, "planes is NULL with mask 0x%x", mask);
+    size_t need;
+    inim_inim_workspace_size(res, dt, &need);
+    return check_ws(ws, ws_bytes, need);
+}
+
+int inim_inim_u32(const uint32_t* img, int32_t res, uint32_t mask, uint32_t* planes, double* marg, void* ws,
+                  size_t ws_bytes, hipStream_t stream) {
+    int s = inim_common(img, res, mask, planes, ws, ws_bytes, INIM_U32);
+    if (s != INIM_OK) return s;
+    if (mask == 0 && marg == nullptr) return INIM_OK;
+    const Geom g = make_geom(res, 4);
+    void* scratch = (char*)ws + kStatusBytes;
+    hipError_t e = launch_inim_carries<uint32_t>(img, g, scratch, nullptr, stream);
+    if (e == hipSuccess) e = launch_inim_final<uint32_t>(img, g, scratch, mask, planes, nullptr, 0.0, marg, nullptr, stream);
+    return e == hipSuccess ? INIM_OK : hip_fail(e, "integral images");
+}
+
+int inim_inim_f32(const float* img, int32_t res, uint32_t mask, float* planes, double* marg, void* ws,
+                  size_t ws_bytes, hipStream_t stream) {
+    int s = inim_common(img, res, mask, planes, ws, ws_bytes, INIM_F32);
+    if (s != INIM_OK) return s;
+    if (mask == 0 && marg == nullptr) return INIM_OK;
+    const Geom g = make_geom(res, 16);
+    void* scratch = (char*)ws + kStatusBytes;
+    hipError_t e = launch_inim_carries<float>(img, g, scratch, nullptr, stream);
+    if (e == hipSuccess) e = launch_inim_final<float>(img, g, scratch, mask, planes, nullptr, 0.0, marg, nullptr, stream);
+    return e == hipSuccess ? INIM_OK : hip_fail(e, "integral images");
+}
+
+int inim_deform(const void* alpha, const void* alpha_t, inim_dtype dt, const double* marg, int32_t res, double d0,
+                float* field, hipStream_t stream) {
+    int s;
+    if ((s = check_res(res)) != INIM_OK) return s;
+    if (alpha == nullptr || alpha_t == nullptr || marg == nullptr || field == nullptr)
+        return fail(INIM_EINVAL, "NULL pointer argument");
+    if (dt != INIM_U32 && dt != INIM_F32) return fail(INIM_EINVAL, "unknown dtype %d", (int)dt);
+    if (!(d0 >= 0.0) || !std::isfinite(d0)) return fail(INIM_EINVAL, "d0 must be finite and >= 0");
+    hipError_t e = launch_deform_planes(alpha, alpha_t, (int)dt, marg, res, d0, reinterpret_cast<float2*>(field),
+                                        stream);
+    return e == hipSuccess ? INIM_OK : hip_fail(e, "deform");
+}
+
+int inim_advect(const float* field, int32_t res, float* xy, int64_t n, void* ws, size_t ws_bytes,
+                hipStream_t stream) {
+    int s;
+    if ((s = check_res(res)) != INIM_OK) return s;
+    if ((s = check_xy(xy, n)) != INIM_OK) return s;
+    if (field == nullptr) return fail(INIM_EINVAL, "field is NULL");
+    if ((s = check_ws(ws, ws_bytes, kStatusBytes)) != INIM_OK) return s;
+    int* status = reinterpret_cast<int*>(ws);
+    hipError_t e;
+    if ((e = launch_fill(nullptr, 0, status, true, stream)) != hipSuccess) return hip_fail(e, "fill");
+    if (n == 0) return INIM_OK;
+    if ((e = launch_validate(reinterpret_cast<const float2*>(xy), n, status, stream)) != hipSuccess)
+        return hip_fail(e, "validate");
+    if ((e = launch_advect(reinterpret_cast<const float2*>(field), res, reinterpret_cast<float2*>(xy), n, status,
+                           stream)) != hipSuccess)
+        return hip_fail(e, "advect");
+    return INIM_OK;
+}
+
+int inim_regularize(float* xy, int64_t n, int32_t res, int32_t iters, const inim_params* p, void* ws,
+                    size_t ws_bytes, hipStream_t stream) {
+    return regularize_impl(xy, n, res, iters, p, ws, ws_bytes, stream, nullptr);
+}
+
+int inim_regularize_timed(float* xy, int64_t n, int32_t res, int32_t iters, const inim_params* p, void* ws,
+                          size_t ws_bytes, hipStream_t stream, double* stage_ms) {
+    if (stage_ms == nullptr) return fail(INIM_EINVAL, "stage_ms is NULL");
+    return regularize_impl(xy, n, res, iters, p, ws, ws_bytes, stream, stage_ms);
+}
+
+int inim_sync_status(void* ws, hipStream_t stream) {
+    if (ws == nullptr) return fail(INIM_EWORKSPACE, "workspace is NULL");
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    int v = 0;
+    e = hipMemcpy(&v, ws, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(status)");
+    const int zero = 0;
+    e = hipMemcpy(ws, &zero, sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(status clear)");
+    return v == 0 ? INIM_OK : INIM_EDOMAIN;
+}
+
+}  // extern "C"

@@ -1,0 +1,273 @@
+// device_common.h -- device helpers shared by the gfx950 kernels of libinim:
+// wave64 scans, uniform broadcasts, vector loads/stores, the closed-form
+// integral images of a constant raster and the per-texel deformation map.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "inim.h"
+
+namespace inim {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- fixed point
+// Float rasters are summed exactly in 128-bit two's-complement fixed point with
+// 64 fractional bits: every float32 whose magnitude is at least 2^-64 and
+// below 2^62 converts without error (smaller magnitudes are truncated toward
+// zero, an error below 2^-64 each), integer addition is exact and associative,
+// so any sum, difference and complement of region sums is exact while the
+// total stays below 2^63 in magnitude.  Results are rounded once on output.
+typedef unsigned __int128 u128;
+
+__device__ __forceinline__ u128 fx_from_float(float f) {
+    const uint32_t bits = __float_as_uint(f);
+    const uint32_t ex = (bits >> 23) & 0xFFu;
+    uint64_t m = bits & 0x7FFFFFu;
+    int e;  // |f| = m * 2^e
+    if (ex == 0) {
+        e = -149;
+    } else {
+        m |= 0x800000u;
+        e = (int)ex - 150;
+    }
+    const int sh = e + 64;  // fixed = m * 2^(e + 64)
+    u128 v;
+    if (sh >= 0) v = (u128)m << sh;
+    else if (sh > -64) v = (u128)(m >> (-sh));
+    else v = 0;
+    return (bits >> 31) ? (u128)0 - v : v;
+}
+
+__device__ __forceinline__ double fx_to_double(u128 v) {
+    const bool neg = (int64_t)(uint64_t)(v >> 64) < 0;
+    if (neg) v = (u128)0 - v;
+    const uint64_t hi = (uint64_t)(v >> 64), lo = (uint64_t)v;
+    const double d = (double)hi + (double)lo * 0x1p-64;
+    return neg ? -d : d;
+}
+
+// ---------------------------------------------------------------- accumulators
+// uint32 rasters accumulate modulo 2^32 (exact below 2^32); float rasters in
+// the 128-bit fixed point above.
+template <typename Tin> struct AccOf;
+template <> struct AccOf<uint32_t> { using type = uint32_t; };
+template <> struct AccOf<float> { using type = u128; };
+
+template <typename Acc, typename Tin> __device__ __forceinline__ Acc to_acc(Tin v);
+template <> __device__ __forceinline__ uint32_t to_acc<uint32_t, uint32_t>(uint32_t v) { return v; }
+template <> __device__ __forceinline__ u128 to_acc<u128, float>(float v) { return fx_from_float(v); }
+
+__device__ __forceinline__ double to_f64(uint32_t a) { return (double)a; }
+__device__ __forceinline__ double to_f64(u128 a) { return fx_to_double(a); }
+
+template <typename Tout, typename Acc> __device__ __forceinline__ Tout narrow(Acc a);
+template <> __device__ __forceinline__ uint32_t narrow<uint32_t, uint32_t>(uint32_t a) { return a; }
+template <> __device__ __forceinline__ float narrow<float, u128>(u128 a) { return (float)fx_to_double(a); }
+
+// ---------------------------------------------------------------- wave64 ops
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t shfl_up(uint32_t v, int d) { return __shfl_up(v, d, kWave); }
+__device__ __forceinline__ uint32_t shfl_down(uint32_t v, int d) { return __shfl_down(v, d, kWave); }
+__device__ __forceinline__ uint32_t shfl_xor(uint32_t v, int d) { return __shfl_xor(v, d, kWave); }
+__device__ __forceinline__ u128 join(unsigned long long lo, unsigned long long hi) {
+    return ((u128)hi << 64) | (u128)lo;
+}
+__device__ __forceinline__ u128 shfl_up(u128 v, int d) {
+    return join(__shfl_up((unsigned long long)(uint64_t)v, d, kWave), __shfl_up((unsigned long long)(uint64_t)(v >> 64), d, kWave));
+}
+__device__ __forceinline__ u128 shfl_down(u128 v, int d) {
+    return join(__shfl_down((unsigned long long)(uint64_t)v, d, kWave),
+                __shfl_down((unsigned long long)(uint64_t)(v >> 64), d, kWave));
+}
+__device__ __forceinline__ u128 shfl_xor(u128 v, int d) {
+    return join(__shfl_xor((unsigned long long)(uint64_t)v, d, kWave),
+                __shfl_xor((unsigned long long)(uint64_t)(v >> 64), d, kWave));
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_up1(T v) { return shfl_up(v, 1); }
+template <typename T>
+__device__ __forceinline__ T shfl_down1(T v) { return shfl_down(v, 1); }
+
+// Inclusive Kogge-Stone scan over the 64 lanes.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        T y = shfl_up(v, off);
+        if (lane >= off) v += y;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += shfl_xor(v, off);
+    return v;
+}
+
+// Value of v in lane `src` (src uniform across the wave).
+__device__ __forceinline__ uint32_t bcast(uint32_t v, int src) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+}
+__device__ __forceinline__ u128 bcast(u128 v, int src) {
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> (32 * k)), src);
+    return ((u128)w[3] << 96) | ((u128)w[2] << 64) | ((u128)w[1] << 32) | (u128)w[0];
+}
+
+// ---------------------------------------------------------------- vector IO
+// Q adjacent 4-byte values of one lane, moved as 16-byte (or smaller) vectors.
+template <typename T, int Q>
+struct VecT {
+    typedef T type __attribute__((ext_vector_type(Q)));
+};
+template <typename T>
+struct VecT<T, 1> {
+    typedef T type;
+};
+
+template <typename T, int Q>
+__device__ __forceinline__ void load_row(const T* __restrict__ p, T (&out)[Q]) {
+    constexpr int V = (Q * sizeof(T) <= 16) ? Q : (int)(16 / sizeof(T));
+    typedef typename VecT<T, V>::type vt;
+#pragma unroll
+    for (int h = 0; h < Q; h += V) {
+        vt t = *reinterpret_cast<const vt*>(p + h);
+        if constexpr (V == 1) {
+            out[h] = t;
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) out[h + e] = t[e];
+        }
+    }
+}
+
+template <typename T, int Q>
+__device__ __forceinline__ void store_row_nt(T* __restrict__ p, const T (&in)[Q]) {
+    constexpr int V = (Q * sizeof(T) <= 16) ? Q : (int)(16 / sizeof(T));
+    typedef typename VecT<T, V>::type vt;
+#pragma unroll
+    for (int h = 0; h < Q; h += V) {
+        vt t;
+        if constexpr (V == 1) {
+            t = in[h];
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) t[e] = in[h + e];
+        }
+        __builtin_nontemporal_store(t, reinterpret_cast<vt*>(p + h));
+    }
+}
+
+// Q float2 texels as interleaved floats.
+template <int Q>
+__device__ __forceinline__ void store_field_nt(float2* __restrict__ p, const float2 (&in)[Q]) {
+    float f[2 * Q];
+#pragma unroll
+    for (int e = 0; e < Q; ++e) { f[2 * e] = in[e].x; f[2 * e + 1] = in[e].y; }
+    store_row_nt<float, 2 * Q>(reinterpret_cast<float*>(p), f);
+}
+
+// Element r (uniform) of a per-lane pair holding rows lane and lane+64.
+template <typename T>
+__device__ __forceinline__ T pick_row(const T (&v)[2], int r) { return (r < 64) ? v[0] : v[1]; }
+
+// ---------------------------------------------------------------- status word
+__device__ __forceinline__ bool failed(const int* status) {
+    return status != nullptr && __builtin_nontemporal_load(status) != 0;
+}
+
+// ---------------------------------------------------------------- constant raster
+// Integral images of the all-ones res x res raster at texel (i, j), counted
+// combinatorially; exact integers (at most res^2 <= 2^28) held in double.
+struct Planes8 {
+    double a, b, g, d, at, bt, gt, dt;
+};
+
+__device__ __forceinline__ Planes8 ones_planes(int i, int j, int N) {
+    Planes8 p;
+    const long long I = i, J = j, n = N;
+    p.a = (double)((I + 1) * (J + 1));
+    p.b = (double)((I + 1) * (n - 1 - J));
+    p.g = (double)((n - 1 - I) * (n - 1 - J));
+    p.d = (double)((n - 1 - I) * (J + 1));
+    // alpha_t: the wedge j' <= j - |i' - i| counted column by column.
+    const long long m = J + 1;
+    const long long kl = I < m ? I : m;
+    const long long kr = (n - 1 - I) < m ? (n - 1 - I) : m;
+    const long long at = m + (kl * m - kl * (kl + 1) / 2) + (kr * m - kr * (kr + 1) / 2);
+    const long long u = I + J, v = I - J;
+    const long long U = (u <= n - 1) ? (u + 1) * (u + 2) / 2 : n * n - (2 * n - 2 - u) * (2 * n - 1 - u) / 2;
+    const long long V = (v >= 0) ? (n - v) * (n - v + 1) / 2 : n * n - (n + v - 1) * (n + v) / 2;
+    p.at = (double)at;
+    p.bt = (double)(U - at);
+    p.dt = (double)(V - at);
+    p.gt = (double)(n * n - U - V + at);
+    return p;
+}
+
+// ---------------------------------------------------------------- map
+// Weighted sum S of eq. (map) at the point (x, y): the anchors q1..q4 of the
+// Molchanov-Linsen map, alpha_t paired with (x,1), beta_t with (1,y), gamma_t
+// with (x,0) and delta_t with (0,y).  t = S / (2C).
+__device__ __forceinline__ void map_sum(const Planes8& P, double x, double y, double& sx, double& sy) {
+    double q1x, q1y, q2x, q2y, q3x, q3y, q4x, q4y;
+    if (y < x) { q1x = 1.0; q1y = 1.0 + y - x; q3x = x - y; q3y = 0.0; }
+    else       { q1x = 1.0 - y + x; q1y = 1.0; q3x = 0.0; q3y = y - x; }
+    if (x + y < 1.0) { q2x = x + y; q2y = 0.0; q4x = 0.0; q4y = x + y; }
+    else             { q2x = 1.0; q2y = x + y - 1.0; q4x = x + y - 1.0; q4y = 1.0; }
+    sx = P.a * q1x + P.b * q2x + P.g * q3x + P.d * q4x + (P.at + P.gt) * x + P.bt;
+    sy = P.a * q1y + P.b * q2y + P.g * q3y + P.d * q4y + P.at + (P.bt + P.dt) * y;
+}
+
+// Deformation at texel (i, j), eq. (map_res): T = p + t(p; d_r + d0) - t(p; d0).
+// `R` holds the eight planes of d_r and `Cr` its total; the planes of the
+// constant part are d0 times the closed forms, and t(p; d0) = t(p; 1).
+__device__ __forceinline__ float2 deform_texel(const Planes8& R, double Cr, int i, int j, int N, double d0) {
+    const double x = ((double)i + 0.5) / (double)N;
+    const double y = ((double)j + 0.5) / (double)N;
+    const Planes8 O = ones_planes(i, j, N);
+    Planes8 D;
+    D.a = R.a + d0 * O.a; D.b = R.b + d0 * O.b; D.g = R.g + d0 * O.g; D.d = R.d + d0 * O.d;
+    D.at = R.at + d0 * O.at; D.bt = R.bt + d0 * O.bt; D.gt = R.gt + d0 * O.gt; D.dt = R.dt + d0 * O.dt;
+    const double NN = (double)N * (double)N;
+    const double Cd = Cr + d0 * NN;
+    double sdx, sdy, s1x, s1y;
+    map_sum(D, x, y, sdx, sdy);
+    map_sum(O, x, y, s1x, s1y);
+    const double tx = sdx / (2.0 * Cd) - s1x / (2.0 * NN);
+    const double ty = sdy / (2.0 * Cd) - s1y / (2.0 * NN);
+    return make_float2((float)(x + tx), (float)(y + ty));
+}
+
+// The six complementary planes from alpha, alpha_t and the marginals
+// (partitions of Sec. 3.1), in the accumulation type.  Regions that are empty
+// by construction (beta on the last row, delta on the last column, gamma on
+// either, beta_t on the first column, gamma_t on the last row, delta_t on the
+// last column) are set to exactly zero.
+template <typename Acc>
+struct Compl {
+    Acc b, g, d, bt, gt, dt;
+};
+
+template <typename Acc>
+__device__ __forceinline__ Compl<Acc> complements(Acc al, Acc at, Acc X, Acc Y, Acc U, Acc V, Acc C,
+                                                  int i, int j, int N) {
+    Compl<Acc> o;
+    o.b = (j == N - 1) ? Acc(0) : Acc(X - al);
+    o.d = (i == N - 1) ? Acc(0) : Acc(Y - al);
+    o.g = (i == N - 1 || j == N - 1) ? Acc(0) : Acc(C - X - Y + al);
+    o.bt = (i == 0) ? Acc(0) : Acc(U - at);
+    o.dt = (i == N - 1) ? Acc(0) : Acc(V - at);
+    o.gt = (j == N - 1) ? Acc(0) : Acc(C - U - V + at);
+    return o;
+}
+
+}  // namespace inim

@@ -1,0 +1,315 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: uint32 integral images and counts bit-exact; float32 integral images
+within 1e-6 relative per element (exact zero where the oracle is zero);
+sample positions within 1e-5 of the domain width after the iterations.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_06513_amd import datagen as dg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def note(msg: str):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2408_06513_amd import capi as c
+    c.lib()
+    return c
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return torch.device("cuda:0")
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def plane_list(mask):
+    return [k for k in range(8) if mask >> k & 1]
+
+
+# ------------------------------------------------------------------ integral images
+RES_SMALL = [2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048]
+
+
+@pytest.mark.parametrize("res", RES_SMALL + [4096])
+@pytest.mark.parametrize("mask", [0xFF, 0x11])
+def test_inim_u32_bit_exact(capi, dev, res, mask):
+    note(f"inim_u32 res={res} mask={mask:#x}")
+    img = dg.poisson_raster(res, res)
+    planes, marg = capi.inim(to_dev(img, dev), mask)
+    torch.cuda.synchronize()
+    got = planes.cpu().numpy()
+    ref, rm = oracle.planes(img.astype(np.float64), mask)
+    assert ref.max() < 2**32
+    assert np.array_equal(got.astype(np.float64), ref)
+    m = capi.split_marg(marg.cpu().numpy(), res)
+    for k in "XYUV":
+        assert np.array_equal(m[k], rm[k]), k
+    assert float(m["C"]) == rm["C"]
+
+
+def assert_rel(got, ref, rtol):
+    got = np.asarray(got, dtype=np.float64)
+    err = np.abs(got - ref)
+    bad = err > rtol * np.abs(ref)
+    if bad.any():
+        k = np.argwhere(bad)[0]
+        raise AssertionError(f"{bad.sum()} elements off; first at {tuple(k)}: got {got[tuple(k)]!r} "
+                             f"ref {ref[tuple(k)]!r} rel {err[tuple(k)] / max(abs(ref[tuple(k)]), 1e-300):.3e}")
+
+
+@pytest.mark.parametrize("res", RES_SMALL + [4096])
+@pytest.mark.parametrize("mask", [0xFF, 0x11])
+def test_inim_f32_relative(capi, dev, res, mask):
+    note(f"inim_f32 res={res} mask={mask:#x}")
+    img = dg.lognormal_raster(res, res)
+    planes, marg = capi.inim(to_dev(img, dev), mask)
+    torch.cuda.synchronize()
+    got = planes.cpu().numpy()
+    ref, rm = oracle.planes(img.astype(np.float64), mask)
+    assert_rel(got, ref, 1e-6)
+    m = capi.split_marg(marg.cpu().numpy(), res)
+    for k in "XYUV":
+        np.testing.assert_allclose(m[k], rm[k], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("which", ["ones", "spike", "row", "checker"])
+def test_inim_special_rasters(capi, dev, which):
+    res = 64
+    a = np.zeros((res, res), dtype=np.uint32)
+    if which == "ones":
+        a[:] = 1
+    elif which == "spike":
+        a[17, 40] = 7
+    elif which == "row":
+        a[5, :] = 3
+    else:
+        a[(np.add.outer(np.arange(res), np.arange(res)) % 2) == 0] = 1
+    note(f"inim special {which}")
+    for img in (a, a.astype(np.float32)):
+        planes, _ = capi.inim(to_dev(img, dev), 0xFF)
+        torch.cuda.synchronize()
+        ref, _ = oracle.planes(a.astype(np.float64), 0xFF)
+        assert np.array_equal(planes.cpu().numpy().astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("dtype", ["u32", "f32"])
+def test_inim_full_size_8192(capi, dev, dtype):
+    """The 8192 x 8192 workload in the benchmark's launch configuration,
+    all eight planes, compared element by element."""
+    res = 8192
+    note(f"inim 8192 {dtype}")
+    img = dg.poisson_raster(0, res) if dtype == "u32" else dg.lognormal_raster(0, res)
+    planes, marg = capi.inim(to_dev(img, dev), 0xFF)
+    torch.cuda.synchronize()
+    img64 = img.astype(np.float64)
+    for k in range(8):
+        ref, rm = oracle.planes(img64, 1 << k)
+        got = planes[k].cpu().numpy()
+        if dtype == "u32":
+            assert np.array_equal(got.astype(np.float64), ref[0]), oracle.PLANES[k]
+        else:
+            assert_rel(got, ref[0], 1e-6)
+        del ref
+    m = capi.split_marg(marg.cpu().numpy(), res)
+    for key in "XYUV":
+        np.testing.assert_allclose(m[key], rm[key], rtol=1e-12 if dtype == "f32" else 0, atol=0)
+
+
+# ------------------------------------------------------------------ rasterize
+@pytest.mark.parametrize("res,radius", [(2, 8), (64, 3), (256, 8), (1024, 8), (256, 0), (512, 32)])
+def test_rasterize(capi, dev, res, radius):
+    note(f"rasterize res={res} r={radius}")
+    xy = dg.plain_small(1)
+    counts, density, _ = capi.rasterize(to_dev(xy, dev), res, radius=radius)
+    torch.cuda.synchronize()
+    rc = oracle.counts(xy, res)
+    assert np.array_equal(counts.cpu().numpy().astype(np.float64), rc)
+    rd = oracle.blur(rc, radius)
+    got = density.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(got, rd, rtol=4e-6, atol=1e-6 * rd.max())
+
+
+def test_rasterize_edges_and_duplicates(capi, dev):
+    xy = np.array([[0, 0], [1, 1], [1, 0], [0, 1], [0.5, 0.5], [0.5, 0.5], [0.999999, 0.25]], np.float32)
+    counts, _, _ = capi.rasterize(to_dev(xy, dev), 4, radius=0, want_density=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(counts.cpu().numpy().astype(np.float64), oracle.counts(xy, 4))
+
+
+# ------------------------------------------------------------------ deform / advect
+@pytest.mark.parametrize("res", [2, 16, 256, 1024])
+def test_deform_from_planes(capi, dev, res):
+    note(f"deform res={res}")
+    xy = dg.plain_small(2)
+    rc = oracle.counts(xy, res)
+    dr = oracle.blur(rc, 8).astype(np.float32)
+    d0 = xy.shape[0] / res / res
+    planes, marg = capi.inim(to_dev(dr, dev), 0x11)
+    field = capi.deform(planes[0], planes[1], marg, d0)
+    torch.cuda.synchronize()
+    ref = oracle.deform(dr.astype(np.float64), d0)
+    np.testing.assert_allclose(field.cpu().numpy(), ref, rtol=0, atol=1e-6)
+    # counts (uint32 planes) as the density
+    cnt = rc.astype(np.uint32)
+    planes, marg = capi.inim(to_dev(cnt, dev), 0x11)
+    field = capi.deform(planes[0], planes[1], marg, d0)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(field.cpu().numpy(), oracle.deform(rc, d0), rtol=0, atol=1e-6)
+
+
+def test_advect(capi, dev):
+    res = 256
+    xy = dg.plain_small(3)
+    dr = oracle.blur(oracle.counts(xy, res), 8)
+    T = oracle.deform(dr, xy.shape[0] / res / res)
+    Tf = T.astype(np.float32)
+    pts = np.concatenate([xy, np.array([[0, 0], [1, 1], [0, 1], [1, 0], [0.001, 0.999]], np.float32)])
+    g = to_dev(pts, dev)
+    capi.advect(to_dev(Tf, dev), g)
+    torch.cuda.synchronize()
+    ref = oracle.advect(Tf.astype(np.float64), pts)
+    np.testing.assert_allclose(g.cpu().numpy(), ref, rtol=0, atol=2e-7)
+
+
+# ------------------------------------------------------------------ regularize
+def gpu_regularize(capi, dev, xy, res, iters, **kw):
+    g = to_dev(xy, dev)
+    capi.regularize(g, res, iters, **kw)
+    torch.cuda.synchronize()
+    return g.cpu().numpy()
+
+
+def test_regularize_small_config_parity_and_lockstep(capi, dev):
+    """20k points, 256^2, r = 8, 4 iterations: final positions within 1e-5 of
+    the oracle; each GPU iteration, restarted from the GPU's own previous
+    positions, within 1e-6 of one oracle iteration."""
+    xy = dg.plain_small(0)
+    res, iters = 256, 4
+    note("regularize C1 parity")
+    got = gpu_regularize(capi, dev, xy, res, iters)
+    ref = oracle.regularize(xy, res, iters)
+    err = np.abs(got.astype(np.float64) - ref).max()
+    note(f"C1 max|gpu-oracle| = {err:.3e}")
+    assert err <= 1e-5
+    cur = xy.copy()
+    for it in range(iters):
+        nxt = gpu_regularize(capi, dev, cur, res, 1)
+        one = oracle.regularize(cur, res, 1, d0=cur.shape[0] / res / res)
+        step_err = np.abs(nxt.astype(np.float64) - one).max()
+        assert step_err <= 1e-6, (it, step_err)
+        cur = nxt
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_regularize_small_seeds(capi, dev, seed):
+    xy = dg.plain_small(seed)
+    note(f"regularize C1 seed={seed}")
+    got = gpu_regularize(capi, dev, xy, 256, 4)
+    assert np.abs(got - oracle.regularize(xy, 256, 4)).max() <= 1e-5
+
+
+def test_regularize_large_config_parity(capi, dev):
+    """1M points (8 clusters + 5% outliers), 1024^2, r = 8, 8 iterations, in
+    the benchmark's launch configuration; every sample compared."""
+    xy = dg.plain_large(0)
+    note("regularize C2 parity (oracle takes a few seconds)")
+    got = gpu_regularize(capi, dev, xy, 1024, 8)
+    ref = oracle.regularize(xy, 1024, 8)
+    err = np.abs(got.astype(np.float64) - ref).max()
+    note(f"C2 max|gpu-oracle| = {err:.3e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("res,n,radius", [(2, 50, 8), (4, 7, 1), (64, 1, 8), (128, 3000, 0), (512, 5000, 32)])
+def test_regularize_edge_sizes(capi, dev, res, n, radius):
+    xy = dg.plain_small(4)[:n]
+    note(f"regularize edge res={res} n={n} r={radius}")
+    got = gpu_regularize(capi, dev, xy, res, 3, radius=radius)
+    ref = oracle.regularize(xy, res, 3, radius=radius)
+    assert np.abs(got - ref).max() <= 1e-5
+
+
+def test_regularize_metamorphic_bitwise(capi, dev):
+    """Duplicating every sample and permuting the input give bit-identical
+    positions on the GPU too (counts are integers; scale invariance)."""
+    xy = dg.plain_small(5)[:8000]
+    a = gpu_regularize(capi, dev, xy, 256, 3)
+    b = gpu_regularize(capi, dev, np.repeat(xy, 2, axis=0), 256, 3)
+    assert np.array_equal(np.repeat(a, 2, axis=0), b)
+    perm = dg.rng(3).permutation(xy.shape[0])
+    c = gpu_regularize(capi, dev, xy[perm], 256, 3)
+    assert np.array_equal(a[perm], c)
+    d = gpu_regularize(capi, dev, xy, 256, 3)
+    assert np.array_equal(a, d)
+
+
+def test_regularize_lattice_fixed_point(capi, dev):
+    xy = dg.lattice_points(64)
+    got = gpu_regularize(capi, dev, xy, 64, 4)
+    assert np.abs(got - xy).max() <= 1e-6
+
+
+def test_regularize_noop_and_domain_error(capi, dev):
+    empty = torch.empty((0, 2), dtype=torch.float32, device=dev)
+    capi.regularize(empty, 64, 3)
+    xy = dg.plain_small(6)[:1000].copy()
+    g0 = to_dev(xy, dev)
+    capi.regularize(g0, 64, 0)
+    assert np.array_equal(g0.cpu().numpy(), xy)
+    for bad in (np.nan, 1.5, -0.25):
+        xb = xy.copy()
+        xb[500, 1] = bad
+        g = to_dev(xb, dev)
+        with pytest.raises(capi.DomainError):
+            capi.regularize(g, 64, 3)
+        assert np.array_equal(g.cpu().numpy(), xb, equal_nan=True)
+    # the workspace recovers: a valid call after a failed one succeeds
+    ws = capi.workspace(capi.workspace_size(64, 1000), dev)
+    g = to_dev(xy, dev)
+    capi.regularize(g, 64, 2, ws=ws)
+    assert np.abs(g.cpu().numpy() - oracle.regularize(xy, 64, 2)).max() <= 1e-5
+
+
+def test_advect_domain_error_leaves_xy(capi, dev):
+    res = 16
+    T = np.zeros((res, res, 2), np.float32)
+    xy = np.array([[0.5, 0.5], [np.nan, 0.2]], np.float32)
+    g = to_dev(xy, dev)
+    ws = capi.workspace(256, dev)
+    capi.advect(to_dev(T, dev), g, ws=ws)
+    assert capi.sync_status(ws) == capi.EDOMAIN
+    assert np.array_equal(g.cpu().numpy(), xy, equal_nan=True)
+
+
+def test_host_errors_with_device_buffers(capi, dev):
+    xy = to_dev(dg.plain_small(0)[:100], dev)
+    with pytest.raises(capi.InvalidArgument):
+        capi.regularize(xy, 100, 2)
+    with pytest.raises(capi.InvalidArgument):
+        capi.regularize(xy, 64, -1)
+    with pytest.raises(capi.InvalidArgument):
+        capi.regularize(xy, 64, 2, radius=33)
+    small = capi.workspace(1024, dev)
+    with pytest.raises(capi.WorkspaceError):
+        capi.regularize(xy, 64, 2, ws=small)
+    img = torch.zeros((64, 64), dtype=torch.float32, device=dev)
+    with pytest.raises(capi.InvalidArgument):
+        capi.inim(img, 0x100)
