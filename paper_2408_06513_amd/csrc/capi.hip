@@ -84,20 +84,20 @@ constexpr size_t kStatusBytes = 256;
 struct RegLayout {
     size_t status, counts, density, field, scratch, total;
     Geom g;
-    bool f32;  // integral images of the float density (radius > 0) or of the counts
+    bool f32;  // integral images of the float density in double (radius > 0), or of the counts
 };
 
 RegLayout reg_layout(int32_t res, int radius) {
     RegLayout L;
     const size_t NN = (size_t)res * (size_t)res;
     L.f32 = radius > 0;
-    L.g = make_geom(res, L.f32 ? 16 : 4);
+    L.g = make_geom(res, L.f32 ? 8 : 4);
     size_t o = 0;
     L.status = o; o += kStatusBytes;
     L.counts = o; o += align256(NN * 4);
     L.density = o; o += align256(NN * 4);
     L.field = o; o += align256(NN * 8);
-    L.scratch = o; o += inim_scratch_bytes(L.g, L.f32 ? 16 : 4);
+    L.scratch = o; o += inim_scratch_bytes(L.g, L.f32 ? 8 : 4);
     L.total = o;
     return L;
 }
@@ -137,15 +137,15 @@ int enqueue_iteration(float* xy, int64_t n, int32_t res, const Params& P, double
     }
     if (ev) (void)hipEventRecord(ev[2], st);
     if (L.f32)
-        e = launch_inim_carries<float>(density, L.g, scratch, status, st);
+        e = launch_inim_carries<float, double>(density, L.g, scratch, status, st);
     else
-        e = launch_inim_carries<uint32_t>(counts, L.g, scratch, status, st);
+        e = launch_inim_carries<uint32_t, uint32_t>(counts, L.g, scratch, status, st);
     if (e != hipSuccess) return hip_fail(e, "integral-image carries");
     if (ev) (void)hipEventRecord(ev[3], st);
     if (L.f32)
-        e = launch_inim_final<float>(density, L.g, scratch, 0u, nullptr, field, d0, nullptr, status, st);
+        e = launch_inim_final<float, double>(density, L.g, scratch, 0u, nullptr, field, d0, nullptr, status, st);
     else
-        e = launch_inim_final<uint32_t>(counts, L.g, scratch, 0u, nullptr, field, d0, nullptr, status, st);
+        e = launch_inim_final<uint32_t, uint32_t>(counts, L.g, scratch, 0u, nullptr, field, d0, nullptr, status, st);
     if (e != hipSuccess) return hip_fail(e, "integral images + deformation");
     if (ev) (void)hipEventRecord(ev[4], st);
     if ((e = launch_advect(field, res, reinterpret_cast<float2*>(xy), n, status, st)) != hipSuccess)
@@ -292,8 +292,8 @@ int inim_inim_u32(const uint32_t* img, int32_t res, uint32_t mask, uint32_t* pla
     if (mask == 0 && marg == nullptr) return INIM_OK;
     const Geom g = make_geom(res, 4);
     void* scratch = (char*)ws + kStatusBytes;
-    hipError_t e = launch_inim_carries<uint32_t>(img, g, scratch, nullptr, stream);
-    if (e == hipSuccess) e = launch_inim_final<uint32_t>(img, g, scratch, mask, planes, nullptr, 0.0, marg, nullptr, stream);
+    hipError_t e = launch_inim_carries<uint32_t, uint32_t>(img, g, scratch, nullptr, stream);
+    if (e == hipSuccess) e = launch_inim_final<uint32_t, uint32_t>(img, g, scratch, mask, planes, nullptr, 0.0, marg, nullptr, stream);
     return e == hipSuccess ? INIM_OK : hip_fail(e, "integral images");
 }
 
@@ -304,8 +304,8 @@ int inim_inim_f32(const float* img, int32_t res, uint32_t mask, float* planes, d
     if (mask == 0 && marg == nullptr) return INIM_OK;
     const Geom g = make_geom(res, 16);
     void* scratch = (char*)ws + kStatusBytes;
-    hipError_t e = launch_inim_carries<float>(img, g, scratch, nullptr, stream);
-    if (e == hipSuccess) e = launch_inim_final<float>(img, g, scratch, mask, planes, nullptr, 0.0, marg, nullptr, stream);
+    hipError_t e = launch_inim_carries<float, u128>(img, g, scratch, nullptr, stream);
+    if (e == hipSuccess) e = launch_inim_final<float, u128>(img, g, scratch, mask, planes, nullptr, 0.0, marg, nullptr, stream);
     return e == hipSuccess ? INIM_OK : hip_fail(e, "integral images");
 }
 

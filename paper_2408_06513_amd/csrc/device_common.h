@@ -50,21 +50,22 @@ __device__ __forceinline__ double fx_to_double(u128 v) {
 
 // ---------------------------------------------------------------- accumulators
 // uint32 rasters accumulate modulo 2^32 (exact below 2^32); float rasters in
-// the 128-bit fixed point above.
-template <typename Tin> struct AccOf;
-template <> struct AccOf<uint32_t> { using type = uint32_t; };
-template <> struct AccOf<float> { using type = u128; };
+// the 128-bit fixed point above where exact planes are required, or in double
+// where the sums only feed the deformation.
 
 template <typename Acc, typename Tin> __device__ __forceinline__ Acc to_acc(Tin v);
 template <> __device__ __forceinline__ uint32_t to_acc<uint32_t, uint32_t>(uint32_t v) { return v; }
 template <> __device__ __forceinline__ u128 to_acc<u128, float>(float v) { return fx_from_float(v); }
+template <> __device__ __forceinline__ double to_acc<double, float>(float v) { return (double)v; }
 
 __device__ __forceinline__ double to_f64(uint32_t a) { return (double)a; }
 __device__ __forceinline__ double to_f64(u128 a) { return fx_to_double(a); }
+__device__ __forceinline__ double to_f64(double a) { return a; }
 
 template <typename Tout, typename Acc> __device__ __forceinline__ Tout narrow(Acc a);
 template <> __device__ __forceinline__ uint32_t narrow<uint32_t, uint32_t>(uint32_t a) { return a; }
 template <> __device__ __forceinline__ float narrow<float, u128>(u128 a) { return (float)fx_to_double(a); }
+template <> __device__ __forceinline__ float narrow<float, double>(double a) { return (float)a; }
 
 // ---------------------------------------------------------------- wave64 ops
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -72,6 +73,9 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint32_t shfl_up(uint32_t v, int d) { return __shfl_up(v, d, kWave); }
 __device__ __forceinline__ uint32_t shfl_down(uint32_t v, int d) { return __shfl_down(v, d, kWave); }
 __device__ __forceinline__ uint32_t shfl_xor(uint32_t v, int d) { return __shfl_xor(v, d, kWave); }
+__device__ __forceinline__ double shfl_up(double v, int d) { return __shfl_up(v, d, kWave); }
+__device__ __forceinline__ double shfl_down(double v, int d) { return __shfl_down(v, d, kWave); }
+__device__ __forceinline__ double shfl_xor(double v, int d) { return __shfl_xor(v, d, kWave); }
 __device__ __forceinline__ u128 join(unsigned long long lo, unsigned long long hi) {
     return ((u128)hi << 64) | (u128)lo;
 }
@@ -114,6 +118,12 @@ __device__ __forceinline__ T wave_sum(T v) {
 // Value of v in lane `src` (src uniform across the wave).
 __device__ __forceinline__ uint32_t bcast(uint32_t v, int src) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+}
+__device__ __forceinline__ double bcast(double v, int src) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 __device__ __forceinline__ u128 bcast(u128 v, int src) {
     uint32_t w[4];
@@ -186,30 +196,30 @@ __device__ __forceinline__ bool failed(const int* status) {
 
 // ---------------------------------------------------------------- constant raster
 // Integral images of the all-ones res x res raster at texel (i, j), counted
-// combinatorially; exact integers (at most res^2 <= 2^28) held in double.
+// combinatorially; exact integers (at most res^2 <= 2^28) held in double, so
+// every product and sum below is exact.
 struct Planes8 {
     double a, b, g, d, at, bt, gt, dt;
 };
 
 __device__ __forceinline__ Planes8 ones_planes(int i, int j, int N) {
     Planes8 p;
-    const long long I = i, J = j, n = N;
-    p.a = (double)((I + 1) * (J + 1));
-    p.b = (double)((I + 1) * (n - 1 - J));
-    p.g = (double)((n - 1 - I) * (n - 1 - J));
-    p.d = (double)((n - 1 - I) * (J + 1));
+    const double I = i, J = j, n = N, nn = n * n;
+    p.a = (I + 1.0) * (J + 1.0);
+    p.b = (I + 1.0) * (n - 1.0 - J);
+    p.g = (n - 1.0 - I) * (n - 1.0 - J);
+    p.d = (n - 1.0 - I) * (J + 1.0);
     // alpha_t: the wedge j' <= j - |i' - i| counted column by column.
-    const long long m = J + 1;
-    const long long kl = I < m ? I : m;
-    const long long kr = (n - 1 - I) < m ? (n - 1 - I) : m;
-    const long long at = m + (kl * m - kl * (kl + 1) / 2) + (kr * m - kr * (kr + 1) / 2);
-    const long long u = I + J, v = I - J;
-    const long long U = (u <= n - 1) ? (u + 1) * (u + 2) / 2 : n * n - (2 * n - 2 - u) * (2 * n - 1 - u) / 2;
-    const long long V = (v >= 0) ? (n - v) * (n - v + 1) / 2 : n * n - (n + v - 1) * (n + v) / 2;
-    p.at = (double)at;
-    p.bt = (double)(U - at);
-    p.dt = (double)(V - at);
-    p.gt = (double)(n * n - U - V + at);
+    const double m = J + 1.0;
+    const double kl = fmin(I, m), kr = fmin(n - 1.0 - I, m);
+    const double at = m + (kl * m - 0.5 * kl * (kl + 1.0)) + (kr * m - 0.5 * kr * (kr + 1.0));
+    const double u = I + J, v = I - J;
+    const double U = (u <= n - 1.0) ? 0.5 * (u + 1.0) * (u + 2.0) : nn - 0.5 * (2.0 * n - 2.0 - u) * (2.0 * n - 1.0 - u);
+    const double V = (v >= 0.0) ? 0.5 * (n - v) * (n - v + 1.0) : nn - 0.5 * (n + v - 1.0) * (n + v);
+    p.at = at;
+    p.bt = U - at;
+    p.dt = V - at;
+    p.gt = nn - U - V + at;
     return p;
 }
 
@@ -227,23 +237,37 @@ __device__ __forceinline__ void map_sum(const Planes8& P, double x, double y, do
     sy = P.a * q1y + P.b * q2y + P.g * q3y + P.d * q4y + P.at + (P.bt + P.dt) * y;
 }
 
+// Scale factors of the deformation: 1 / (2 C_d) with C_d = C_r + d0 res^2 the
+// total of d = d_r + d0, and 1 / (2 res^2) for the constant raster.
+struct MapScale {
+    double d0, inv2Cd, inv2NN;
+};
+
+__device__ __forceinline__ MapScale map_scale(double Cr, int N, double d0) {
+    const double NN = (double)N * (double)N;
+    MapScale s;
+    s.d0 = d0;
+    s.inv2Cd = 1.0 / (2.0 * (Cr + d0 * NN));
+    s.inv2NN = 1.0 / (2.0 * NN);
+    return s;
+}
+
 // Deformation at texel (i, j), eq. (map_res): T = p + t(p; d_r + d0) - t(p; d0).
-// `R` holds the eight planes of d_r and `Cr` its total; the planes of the
-// constant part are d0 times the closed forms, and t(p; d0) = t(p; 1).
-__device__ __forceinline__ float2 deform_texel(const Planes8& R, double Cr, int i, int j, int N, double d0) {
+// `R` holds the eight planes of d_r; the planes of the constant part are d0
+// times the closed forms, and t(p; d0) = t(p; 1).
+__device__ __forceinline__ float2 deform_texel(const Planes8& R, const MapScale& ms, int i, int j, int N) {
     const double x = ((double)i + 0.5) / (double)N;
     const double y = ((double)j + 0.5) / (double)N;
     const Planes8 O = ones_planes(i, j, N);
+    const double d0 = ms.d0;
     Planes8 D;
     D.a = R.a + d0 * O.a; D.b = R.b + d0 * O.b; D.g = R.g + d0 * O.g; D.d = R.d + d0 * O.d;
     D.at = R.at + d0 * O.at; D.bt = R.bt + d0 * O.bt; D.gt = R.gt + d0 * O.gt; D.dt = R.dt + d0 * O.dt;
-    const double NN = (double)N * (double)N;
-    const double Cd = Cr + d0 * NN;
     double sdx, sdy, s1x, s1y;
     map_sum(D, x, y, sdx, sdy);
     map_sum(O, x, y, s1x, s1y);
-    const double tx = sdx / (2.0 * Cd) - s1x / (2.0 * NN);
-    const double ty = sdy / (2.0 * Cd) - s1y / (2.0 * NN);
+    const double tx = sdx * ms.inv2Cd - s1x * ms.inv2NN;
+    const double ty = sdy * ms.inv2Cd - s1y * ms.inv2NN;
     return make_float2((float)(x + tx), (float)(y + ty));
 }
 

@@ -7,6 +7,9 @@
 
 namespace inim {
 
+// Exact 128-bit fixed-point accumulator of float rasters (see device_common.h).
+typedef unsigned __int128 u128;
+
 // A res x res raster is cut into bands of H rows and tiles of W = 64*Q columns;
 // one wave64 streams one tile top to bottom, Q adjacent columns per lane.
 struct Geom {
@@ -35,16 +38,18 @@ struct Agg {
 
 // Carries at the row above band b (b = 0..B; row B is the state after the last row):
 //   cpin[b][i] column prefix, ain[b][i] alpha, Lin[b][i] / Rin[b][i] the
-//   up-left / up-right diagonal sums of column prefixes.
+//   up-left / up-right diagonal sums of column prefixes;
+// and per band row: AC[b][c][r] = alpha(cW-1, bH+r) for c = 0..T (c = T gives
+// the row marginal Y(bH+r) = alpha(N-1, bH+r)).
 template <typename Acc>
 struct Carry {
-    Acc *cpin, *ain, *Lin, *Rin;
+    Acc *cpin, *ain, *Lin, *Rin, *AC;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// acc_bytes: 4 for uint32 rasters, 16 for float rasters (128-bit accumulators
-// need more registers per column, so float tiles are narrower).
+// acc_bytes: 4 for uint32 rasters, 8 or 16 for float rasters (wider
+// accumulators need more registers per column, so float tiles are narrower).
 inline Geom make_geom(int N, int acc_bytes = 4, int q_hint = 0, int h_hint = 0) {
     Geom g;
     g.N = N;
@@ -62,7 +67,7 @@ inline Geom make_geom(int N, int acc_bytes = 4, int q_hint = 0, int h_hint = 0) 
         Q = acc_bytes > 4 ? 2 : 4;
         H = 128;
     }
-    if (q_hint > 0) Q = q_hint;
+    if (q_hint > 0) Q = q_hint > 4 ? 4 : q_hint;
     if (h_hint > 0) H = h_hint;
     int W = 64 * Q;
     if (W > N) {
@@ -73,6 +78,7 @@ inline Geom make_geom(int N, int acc_bytes = 4, int q_hint = 0, int h_hint = 0) 
     if (H > W) H = W;
     if (H > 128) H = 128;
     if (H > N) H = N;
+    while (N / H > 128) H <<= 1;  // at most 128 bands (carry scans)
     g.Q = Q;
     g.W = W;
     g.H = H;
@@ -83,18 +89,19 @@ inline Geom make_geom(int N, int acc_bytes = 4, int q_hint = 0, int h_hint = 0) 
 }
 
 inline bool geom_ok(const Geom& g) {
-    return g.W >= g.H && g.W % g.Q == 0 && g.W / g.Q <= 64 && g.N % g.W == 0 &&
-           g.N % g.H == 0 && g.H <= 128 && (g.Q == 1 || g.Q == 2 || g.Q == 4 || g.Q == 8);
+    return g.W >= g.H && g.B <= 128 && g.W % g.Q == 0 && g.W / g.Q <= 64 && g.N % g.W == 0 &&
+           g.N % g.H == 0 && g.H <= 128 && (g.Q == 1 || g.Q == 2 || g.Q == 4);
 }
 
 // Bytes of the aggregate and carry arrays for accumulator size `acc`
-// (4 for uint32 rasters, 16 for the 128-bit fixed point of float rasters).
+// (4 for uint32 rasters; 8 (double) or 16 (128-bit fixed point) for float rasters).
 inline size_t inim_scratch_bytes(const Geom& g, size_t acc) {
     const size_t N = (size_t)g.N;
     size_t s = 0;
     s += 4 * align256((size_t)g.B * N * acc);                 // colsum tcsp tLend tRend
     s += 3 * align256((size_t)g.B * g.T * g.H * acc);         // tLedge tRedge trow
     s += 4 * align256((size_t)(g.B + 1) * N * acc);           // cpin ain Lin Rin
+    s += align256((size_t)g.B * (g.T + 1) * g.H * acc);       // AC
     return s;
 }
 
@@ -104,6 +111,7 @@ inline void carve(const Geom& g, char* base, Agg<Acc>& A, Carry<Acc>& K) {
     const size_t col = align256((size_t)g.B * N * sizeof(Acc));
     const size_t edge = align256((size_t)g.B * g.T * g.H * sizeof(Acc));
     const size_t car = align256((size_t)(g.B + 1) * N * sizeof(Acc));
+    const size_t acb = align256((size_t)g.B * (g.T + 1) * g.H * sizeof(Acc));
     char* p = base;
     A.colsum = (Acc*)p; p += col;
     A.tcsp = (Acc*)p; p += col;
@@ -116,6 +124,7 @@ inline void carve(const Geom& g, char* base, Agg<Acc>& A, Carry<Acc>& K) {
     K.ain = (Acc*)p; p += car;
     K.Lin = (Acc*)p; p += car;
     K.Rin = (Acc*)p; p += car;
+    K.AC = (Acc*)p; p += acb;
 }
 
 }  // namespace inim

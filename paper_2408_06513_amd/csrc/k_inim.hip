@@ -1,6 +1,7 @@
 // k_inim.hip -- integral images of Sec. 3.1 on gfx950.
 //
-// Decomposition (all sums exact in uint32, or in double for float rasters):
+// Decomposition (sums exact in uint32 or 128-bit fixed point; in double where
+// they only feed the deformation):
 //   cp(i,j)  column prefix   sum over j' <= j of d(i,j')
 //   alpha    row prefix of cp
 //   L(i,j)   sum of cp along the up-left diagonal,  L(i,j) = cp(i,j) + L(i-1,j-1)
@@ -12,8 +13,9 @@
 // Four passes, all fully parallel (no inter-workgroup waiting):
 //   1. aggregate  one wave per H x W tile: tile-local column prefixes, diagonal
 //                 sums and row sums;
-//   2. chain_col  per column, over bands: the column-prefix and alpha carries;
-//   3. chain_diag per diagonal, over bands: the L and R carries;
+//   2. scan_col   per column, a prefix over bands: column-prefix and alpha carries;
+//   3. scan_diag  per diagonal, a prefix over bands: the L and R carries; per
+//                 band row, a prefix over tiles: alpha at every tile's left edge;
 //   4. final      one wave per tile again: rebuilds cp, alpha, L, R with the
 //                 carries (boundary values of the neighbouring tiles come from
 //                 the partial sums) and writes the requested planes, or the
@@ -40,11 +42,9 @@ __device__ __forceinline__ void load_tile_row(const Tin* __restrict__ p, bool ac
 }
 
 // ------------------------------------------------------------------ pass 1
-template <int Q, typename Tin>
-__global__ __launch_bounds__(256) void k_inim_aggregate(const Tin* __restrict__ img, Geom g,
-                                                        Agg<typename AccOf<Tin>::type> A,
+template <int Q, typename Tin, typename Acc>
+__global__ __launch_bounds__(256) void k_inim_aggregate(const Tin* __restrict__ img, Geom g, Agg<Acc> A,
                                                         const int* status) {
-    using Acc = typename AccOf<Tin>::type;
     if (failed(status)) return;
     const int lane = lane_id();
     const int tile = blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6);
@@ -122,105 +122,165 @@ __global__ __launch_bounds__(256) void k_inim_aggregate(const Tin* __restrict__ 
     }
 }
 
-// ------------------------------------------------------------------ pass 2
-// One thread per column i: cpin[b][i] and ain[b][i] = alpha(i, bH-1).
-// alpha grows per band by the full-row prefix of the band's column sums:
-// the in-tile prefix plus the totals of the tiles to the left (a wave-wide sum;
-// tiles are at least 64 columns wide, so every lane of a wave lies in the same
-// tile, or N < 64 and there is a single tile).
+// ------------------------------------------------------------------ passes 2 and 3
+// The carries are prefix sums over bands.  Each workgroup takes 64 chains
+// (one per lane) and spreads the B bands over its waves, kScanWaves at most,
+// P = ceil(B / waves) consecutive bands per wave: every wave loads its terms
+// at once, sums them in registers, publishes its total in LDS, and adds the
+// totals of the waves above it.  One round of loads, one barrier.
+constexpr int kScanWaves = 16;
+constexpr int kScanMaxP = 8;  // B <= kScanWaves * kScanMaxP = 128
+
+__host__ __device__ inline int scan_waves(int B) { return B < kScanWaves ? B : kScanWaves; }
+__host__ __device__ inline int scan_per_wave(int B) { return (B + scan_waves(B) - 1) / scan_waves(B); }
+
+// Pass 2, per column i: cpin[b][i] = column prefix above band b,
+// ain[b][i] = alpha(i, bH-1), which grows per band by the full-row prefix of
+// the band's column sums: the in-tile prefix tcsp plus the totals of the tiles
+// to the left (a wave-wide sum; tiles are at least 64 columns wide, so all
+// lanes of a wave lie in one tile, or N < 64 and there is one tile).
 template <typename Acc>
-__global__ __launch_bounds__(256) void k_inim_chain_col(Geom g, Agg<Acc> A, Carry<Acc> K,
-                                                        const int* status) {
+__global__ __launch_bounds__(1024) void k_inim_scan_col(Geom g, Agg<Acc> A, Carry<Acc> K, const int* status) {
+    extern __shared__ unsigned char smem_raw[];
     if (failed(status)) return;
+    Acc* tot = reinterpret_cast<Acc*>(smem_raw);  // [waves][2][64]
     const int lane = lane_id();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int wave = (int)(threadIdx.x >> 6);
+    const int nw = scan_waves(g.B), P = scan_per_wave(g.B);
+    const int i = blockIdx.x * 64 + lane;
     const bool valid = i < g.N;
     const int ii = valid ? i : 0;
     const int c = ii / g.W;
     const size_t N = (size_t)g.N;
-    Acc cp = Acc(0), a = Acc(0);
-    for (int b = 0; b < g.B; ++b) {
-        Acc cs = Acc(0), ts = Acc(0), t = Acc(0);
-        if (valid) {
-            cs = A.colsum[(size_t)b * N + ii];
-            ts = A.tcsp[(size_t)b * N + ii];
+    const int b0 = wave * P;
+
+    Acc cs[kScanMaxP], da[kScanMaxP];
+#pragma unroll
+    for (int k = 0; k < kScanMaxP; ++k) {
+        cs[k] = Acc(0);
+        da[k] = Acc(0);
+        const int b = b0 + k;
+        if (k < P && b < g.B) {
+            Acc t = Acc(0);
+            for (int c0 = 0; c0 < c; c0 += 64)
+                if (c0 + lane < c) t += A.trow[((size_t)b * g.T + c0 + lane) * g.H + (g.H - 1)];
+            const Acc left = wave_sum(t);
+            if (valid) {
+                cs[k] = A.colsum[(size_t)b * N + ii];
+                da[k] = A.tcsp[(size_t)b * N + ii] + left;
+            }
         }
-        for (int c0 = 0; c0 < c; c0 += 64)
-            if (c0 + lane < c) t += A.trow[((size_t)b * g.T + c0 + lane) * g.H + (g.H - 1)];
-        const Acc left = wave_sum(t);
-        if (valid) {
-            K.cpin[(size_t)b * N + ii] = cp;
-            K.ain[(size_t)b * N + ii] = a;
-        }
-        cp += cs;
-        a += left + ts;
     }
-    if (valid) {
-        K.cpin[(size_t)g.B * N + ii] = cp;
-        K.ain[(size_t)g.B * N + ii] = a;
+    Acc rc = Acc(0), ra = Acc(0);
+#pragma unroll
+    for (int k = 0; k < kScanMaxP; ++k) { rc += cs[k]; ra += da[k]; }
+    tot[(wave * 2 + 0) * 64 + lane] = rc;
+    tot[(wave * 2 + 1) * 64 + lane] = ra;
+    __syncthreads();
+    Acc oc = Acc(0), oa = Acc(0);
+    for (int w = 0; w < wave; ++w) {
+        oc += tot[(w * 2 + 0) * 64 + lane];
+        oa += tot[(w * 2 + 1) * 64 + lane];
+    }
+    if (!valid) return;
+#pragma unroll
+    for (int k = 0; k < kScanMaxP; ++k) {
+        const int b = b0 + k;
+        if (k < P && b < g.B) {
+            K.cpin[(size_t)b * N + ii] = oc;
+            K.ain[(size_t)b * N + ii] = oa;
+            oc += cs[k];
+            oa += da[k];
+        }
+    }
+    if (wave == nw - 1) {
+        K.cpin[(size_t)g.B * N + ii] = oc;
+        K.ain[(size_t)g.B * N + ii] = oa;
     }
 }
 
-// ------------------------------------------------------------------ pass 3
-// 2N+1 threads; thread t follows the up-left chain s = t - N, i.e. texel
-// columns i = s + (b+1)H at band boundaries b+1, and the up-right chain
-// s' = t, columns i = s' - (b+1)H.
+// Pass 3.  blockIdx.y = 0 follows the up-left chains s = t - N (columns
+// i = s + (b+1)H), blockIdx.y = 1 the up-right chains s = t (columns
+// i = s - (b+1)H), t = 0..2N:
 //   Lin[b+1][i] = sum_{k<H} cp(i-k, bH+H-1-k) + Lin[b][i-H]
 //   Rin[b+1][i] = sum_{k<H} cp(i+k, bH+H-1-k) + Rin[b][i+H]
-// where inside band b, cp = cpin[b] + band-local prefix: the cpin part is a
-// window of cpin (a difference of ain), the band-local part is tLend/tRend
-// plus, near a tile edge, the neighbouring tile's edge sum.
+// Inside band b, cp = cpin[b] + the band-local prefix: the cpin part is a
+// window of cpin (a difference of ain), the band-local part is tLend / tRend
+// plus, near a tile edge, the neighbouring tile's edge sum.  Positions of a
+// chain outside the raster contribute zero, so the chain value is a plain
+// prefix sum over b.
+// blockIdx.y = 2: one thread per raster row j = bH + r accumulates over the
+// tiles of its band AC[b][c][r] = alpha(cW-1, j) = ain[b][cW-1] + sum over
+// c' < c of trow[b][c'][r], for c = 0..T.
 template <typename Acc>
-__global__ __launch_bounds__(256) void k_inim_chain_diag(Geom g, Agg<Acc> A, Carry<Acc> K,
-                                                         const int* status) {
+__global__ __launch_bounds__(1024) void k_inim_scan_diag(Geom g, Agg<Acc> A, Carry<Acc> K, const int* status) {
+    extern __shared__ unsigned char smem_raw[];
     if (failed(status)) return;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int N = g.N, H = g.H, W = g.W, T = g.T;
-    if (t > 2 * N) return;
-    if (t < N) {
-        K.Lin[t] = Acc(0);
-        K.Rin[t] = Acc(0);
-    }
-    // up-left chain
-    {
-        const int s = t - N;
-        // valid b: 0 <= s + (b+1)H <= N-1
-        int blo = 0;
-        if (s < 0) blo = (-s + H - 1) / H - 1;
-        int bhi = (N - 1 - s) / H - 1;
-        if (bhi > g.B - 1) bhi = g.B - 1;
-        Acc prev = Acc(0);
-        for (int b = blo; b <= bhi; ++b) {
-            const int i = s + (b + 1) * H;
-            const Acc* ainb = K.ain + (size_t)b * N;
-            const Acc win = ainb[i] - (i >= H ? ainb[i - H] : Acc(0));
-            const int c = i / W, x = i - c * W;
-            Acc bl = A.tLend[(size_t)b * N + i];
-            if (x < H - 1 && c > 0) bl += A.tLedge[((size_t)b * T + (c - 1)) * H + (H - 2 - x)];
-            prev = win + bl + prev;
-            K.Lin[(size_t)(b + 1) * N + i] = prev;
+    if (blockIdx.y == 2) {
+        const int j = blockIdx.x * blockDim.x + threadIdx.x;
+        if (j >= N) return;
+        const int b = j / H, r = j - b * H;
+        const Acc* ainb = K.ain + (size_t)b * N;
+        const Acc* tr = A.trow + (size_t)b * T * H + r;
+        Acc* ac = K.AC + (size_t)b * (T + 1) * H + r;
+        Acc run = Acc(0);
+        ac[0] = Acc(0);
+        for (int c = 1; c <= T; ++c) {
+            run += tr[(size_t)(c - 1) * H];
+            ac[(size_t)c * H] = ainb[c * W - 1] + run;
         }
+        return;
     }
-    // up-right chain
-    {
-        const int s = t;
-        // valid b: 0 <= s - (b+1)H <= N-1
-        int blo = 0;
-        if (s - H > N - 1) blo = (s - (N - 1) + H - 1) / H - 1;
-        int bhi = s / H - 1;
-        if (bhi > g.B - 1) bhi = g.B - 1;
-        Acc prev = Acc(0);
-        for (int b = blo; b <= bhi; ++b) {
-            const int i = s - (b + 1) * H;
-            const Acc* ainb = K.ain + (size_t)b * N;
+    Acc* tot = reinterpret_cast<Acc*>(smem_raw);  // [waves][64]
+    const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
+    const int P = scan_per_wave(g.B);
+    const int t = blockIdx.x * 64 + lane;
+    const bool left_chain = blockIdx.y == 0;
+    const bool tval = t <= 2 * N;
+    const int s = left_chain ? t - N : t;
+    const int b0 = wave * P;
+    Acc* out = left_chain ? K.Lin : K.Rin;
+    if (wave == 0 && tval && t < N) out[t] = Acc(0);
+
+    Acc term[kScanMaxP];
+    int col[kScanMaxP];
+#pragma unroll
+    for (int k = 0; k < kScanMaxP; ++k) {
+        term[k] = Acc(0);
+        col[k] = -1;
+        const int b = b0 + k;
+        if (!(tval && k < P && b < g.B)) continue;
+        const int i = left_chain ? s + (b + 1) * H : s - (b + 1) * H;
+        if (i < 0 || i >= N) continue;
+        col[k] = i;
+        const Acc* ainb = K.ain + (size_t)b * N;
+        const int c = i / W, x = i - c * W;
+        Acc v;
+        if (left_chain) {
+            v = ainb[i] - (i >= H ? ainb[i - H] : Acc(0));
+            v += A.tLend[(size_t)b * N + i];
+            if (x < H - 1 && c > 0) v += A.tLedge[((size_t)b * T + (c - 1)) * H + (H - 2 - x)];
+        } else {
             const int hi = (i + H - 1 < N - 1) ? i + H - 1 : N - 1;
-            const Acc win = ainb[hi] - (i >= 1 ? ainb[i - 1] : Acc(0));
-            const int c = i / W, x = i - c * W;
-            Acc br = A.tRend[(size_t)b * N + i];
-            if (x > W - H && c < T - 1) br += A.tRedge[((size_t)b * T + (c + 1)) * H + (H - 2 - (W - 1 - x))];
-            prev = win + br + prev;
-            K.Rin[(size_t)(b + 1) * N + i] = prev;
+            v = ainb[hi] - (i >= 1 ? ainb[i - 1] : Acc(0));
+            v += A.tRend[(size_t)b * N + i];
+            if (x > W - H && c < T - 1) v += A.tRedge[((size_t)b * T + (c + 1)) * H + (H - 2 - (W - 1 - x))];
         }
+        term[k] = v;
+    }
+    Acc run = Acc(0);
+#pragma unroll
+    for (int k = 0; k < kScanMaxP; ++k) run += term[k];
+    tot[wave * 64 + lane] = run;
+    __syncthreads();
+    Acc off = Acc(0);
+    for (int w = 0; w < wave; ++w) off += tot[w * 64 + lane];
+#pragma unroll
+    for (int k = 0; k < kScanMaxP; ++k) {
+        off += term[k];
+        if (col[k] >= 0) out[(size_t)(b0 + k + 1) * N + col[k]] = off;
     }
 }
 
@@ -258,13 +318,11 @@ __device__ __forceinline__ Acc marg_V(const Geom& g, const Agg<Acc>& A, const Ca
     return K.Lin[(size_t)g.B * N + (N - 1 + v)] + (ainB[N - 1] - ainB[N - 1 + v]);
 }
 
-// Y(j) = alpha(N-1, j) = ain[b][N-1] + sum over all tiles of trow.
+// Y(j) = alpha(N-1, j), the last entry of the band row's alpha carries.
 template <typename Acc>
-__device__ __forceinline__ Acc marg_Y(const Geom& g, const Agg<Acc>& A, const Carry<Acc>& K, int j) {
+__device__ __forceinline__ Acc marg_Y(const Geom& g, const Carry<Acc>& K, int j) {
     const int b = j / g.H, r = j - b * g.H;
-    Acc y = K.ain[(size_t)b * g.N + (g.N - 1)];
-    for (int c = 0; c < g.T; ++c) y += A.trow[((size_t)b * g.T + c) * g.H + r];
-    return y;
+    return K.AC[((size_t)b * (g.T + 1) + g.T) * g.H + r];
 }
 
 template <typename Acc>
@@ -274,7 +332,7 @@ __global__ __launch_bounds__(256) void k_inim_marg(Geom g, Agg<Acc> A, Carry<Acc
     if (o >= 2 * N + 2 * M + 1) return;
     Acc v;
     if (o < N) v = K.ain[(size_t)g.B * N + o];
-    else if (o < 2 * N) v = marg_Y(g, A, K, o - N);
+    else if (o < 2 * N) v = marg_Y(g, K, o - N);
     else if (o < 2 * N + M) v = marg_U(g, A, K, o - 2 * N);
     else if (o < 2 * N + 2 * M) v = marg_V(g, A, K, (o - 2 * N - M) - (N - 1));
     else v = K.ain[(size_t)g.B * N + (N - 1)];
@@ -284,13 +342,10 @@ __global__ __launch_bounds__(256) void k_inim_marg(Geom g, Agg<Acc> A, Carry<Acc
 // ------------------------------------------------------------------ pass 4
 enum { kModePlanes = 0, kModeDeform = 1 };
 
-template <int Q, typename Tin, int MODE>
-__global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img, Geom g,
-                                                    Agg<typename AccOf<Tin>::type> A,
-                                                    Carry<typename AccOf<Tin>::type> K, uint32_t mask,
-                                                    Tin* __restrict__ planes, float2* __restrict__ field,
-                                                    double d0, const int* status) {
-    using Acc = typename AccOf<Tin>::type;
+template <int Q, typename Tin, typename Acc, int MODE>
+__global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img, Geom g, Agg<Acc> A, Carry<Acc> K,
+                                                    uint32_t mask, Tin* __restrict__ planes,
+                                                    float2* __restrict__ field, double d0, const int* status) {
     extern __shared__ unsigned char smem_raw[];
     if (failed(status)) return;
     const int lane = lane_id();
@@ -309,7 +364,7 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
     const Acc* Rinb = K.Rin + (size_t)b * N;
 
     const bool needUV = (MODE == kModeDeform) || (mask & (INIM_BETA_T | INIM_GAMMA_T | INIM_DELTA_T));
-    const bool needXY = (MODE == kModeDeform) || (mask & (INIM_BETA | INIM_GAMMA | INIM_DELTA | INIM_GAMMA_T));
+    const bool needY = (MODE == kModeDeform) || (mask & (INIM_GAMMA | INIM_DELTA));
 
     // Per-row boundary values, row r held by lane r % 64 in slot r / 64:
     //   LB(r) = L(cW-1, bH+r), RB(r) = R(cW+W, bH+r), AC(r) = alpha(cW-1, bH+r),
@@ -321,13 +376,14 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
         Acc lb = Acc(0), rb = Acc(0), ac = Acc(0), yv = Acc(0);
         if (r < H) {
             const size_t eb = (size_t)b * T * H;
+            const Acc* acb = K.AC + (size_t)b * (T + 1) * H + r;
+            ac = acb[(size_t)c * H];
+            if (needY) yv = acb[(size_t)T * H];
             if (c > 0) {
                 const int m = cW - 2 - r;
                 lb = ainb[cW - 1] - (m >= 0 ? ainb[m] : Acc(0));
                 lb += A.tLedge[eb + (size_t)(c - 1) * H + r];
                 if (m >= 0) lb += Linb[m];
-                ac = ainb[cW - 1];
-                for (int cc = 0; cc < c; ++cc) ac += A.trow[eb + (size_t)cc * H + r];
             }
             if (c < T - 1) {
                 const int m = cW + W + r;
@@ -335,7 +391,6 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
                 rb += A.tRedge[eb + (size_t)(c + 1) * H + r];
                 if (m + 1 < N) rb += Rinb[m + 1];
             }
-            if (needXY) yv = marg_Y(g, A, K, b * H + r);
         }
         LBv[k] = lb; RBv[k] = rb; ACv[k] = ac; YVv[k] = yv;
     }
@@ -369,6 +424,8 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
     }
     Acc Lleft = (c > 0) ? Linb[cW - 1] : Acc(0);
     Acc Rright = (cW + W < N) ? Rinb[cW + W] : Acc(0);
+    MapScale ms;
+    if constexpr (MODE == kModeDeform) ms = map_scale(to_f64(Ctot), N, d0);
 
     // output slots of the requested planes
     int slot[8];
@@ -429,7 +486,7 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
                 for (int e = 0; e < Q; ++e) at[e] = (L[e] + R[e]) - cp[e];
 
                 Acc Yr = Acc(0);
-                if (needXY) Yr = bcast(pick_row(YVv, r), r & 63);
+                if (needY) Yr = bcast(pick_row(YVv, r), r & 63);
 
                 if (!act) continue;
                 if constexpr (MODE == kModePlanes) {
@@ -474,7 +531,7 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
                         Planes8 P;
                         P.a = to_f64(al[e]); P.b = to_f64(cm.b); P.g = to_f64(cm.g); P.d = to_f64(cm.d);
                         P.at = to_f64(at[e]); P.bt = to_f64(cm.bt); P.gt = to_f64(cm.gt); P.dt = to_f64(cm.dt);
-                        o[e] = deform_texel(P, to_f64(Ctot), cW + x, j, N, d0);
+                        o[e] = deform_texel(P, ms, cW + x, j, N);
                     }
                     store_field_nt<Q>(field + (size_t)j * N + col, o);
                 }
@@ -499,34 +556,34 @@ __global__ __launch_bounds__(256) void k_deform_planes(const Tin* __restrict__ a
     const Compl<double> cm = complements<double>(al, at, X, Y, U, V, C, i, j, N);
     Planes8 P;
     P.a = al; P.b = cm.b; P.g = cm.g; P.d = cm.d; P.at = at; P.bt = cm.bt; P.gt = cm.gt; P.dt = cm.dt;
-    field[k] = deform_texel(P, C, i, j, N, d0);
+    field[k] = deform_texel(P, map_scale(C, N, d0), i, j, N);
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename Tin>
+template <typename Acc>
 static size_t final_smem(const Geom& g, bool needUV) {
-    using Acc = typename AccOf<Tin>::type;
     return needUV ? (size_t)kWavesPerBlock * 2 * (g.W + g.H - 1) * sizeof(Acc) : 0;
 }
 
-template <typename Tin, int Q>
+template <typename Tin, typename Acc, int Q>
 static hipError_t launch_carries_q(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st) {
-    using Acc = typename AccOf<Tin>::type;
     Agg<Acc> A;
     Carry<Acc> K;
     carve<Acc>(g, (char*)scratch, A, K);
     const int tiles = g.B * g.T;
     const dim3 grd((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL((k_inim_aggregate<Q, Tin>), grd, dim3(64 * kWavesPerBlock), 0, st, img, g, A, status);
-    hipLaunchKernelGGL((k_inim_chain_col<Acc>), dim3((g.N + 255) / 256), dim3(256), 0, st, g, A, K, status);
-    hipLaunchKernelGGL((k_inim_chain_diag<Acc>), dim3((2 * g.N + 1 + 255) / 256), dim3(256), 0, st, g, A, K, status);
+    hipLaunchKernelGGL((k_inim_aggregate<Q, Tin, Acc>), grd, dim3(64 * kWavesPerBlock), 0, st, img, g, A, status);
+    const int nw = scan_waves(g.B);
+    hipLaunchKernelGGL((k_inim_scan_col<Acc>), dim3((g.N + 63) / 64), dim3(64 * nw), (size_t)nw * 2 * 64 * sizeof(Acc),
+                       st, g, A, K, status);
+    hipLaunchKernelGGL((k_inim_scan_diag<Acc>), dim3((2 * g.N + 1 + 63) / 64, 3), dim3(64 * nw),
+                       (size_t)nw * 64 * sizeof(Acc), st, g, A, K, status);
     return hipGetLastError();
 }
 
-template <typename Tin, int Q>
+template <typename Tin, typename Acc, int Q>
 static hipError_t launch_final_q(const Tin* img, const Geom& g, void* scratch, uint32_t mask, Tin* planes,
                                  float2* field, double d0, double* marg, const int* status, hipStream_t st) {
-    using Acc = typename AccOf<Tin>::type;
     Agg<Acc> A;
     Carry<Acc> K;
     carve<Acc>(g, (char*)scratch, A, K);
@@ -534,12 +591,12 @@ static hipError_t launch_final_q(const Tin* img, const Geom& g, void* scratch, u
     const dim3 blk(64 * kWavesPerBlock);
     const dim3 grd((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
     if (field != nullptr) {
-        hipLaunchKernelGGL((k_inim_final<Q, Tin, kModeDeform>), grd, blk, final_smem<Tin>(g, true), st, img, g, A, K,
-                           0u, (Tin*)nullptr, field, d0, status);
+        hipLaunchKernelGGL((k_inim_final<Q, Tin, Acc, kModeDeform>), grd, blk, final_smem<Acc>(g, true), st, img, g, A,
+                           K, 0u, (Tin*)nullptr, field, d0, status);
     } else if (mask != 0) {
         const bool needUV = (mask & (INIM_BETA_T | INIM_GAMMA_T | INIM_DELTA_T)) != 0;
-        hipLaunchKernelGGL((k_inim_final<Q, Tin, kModePlanes>), grd, blk, final_smem<Tin>(g, needUV), st, img, g, A, K,
-                           mask, planes, (float2*)nullptr, 0.0, status);
+        hipLaunchKernelGGL((k_inim_final<Q, Tin, Acc, kModePlanes>), grd, blk, final_smem<Acc>(g, needUV), st, img, g,
+                           A, K, mask, planes, (float2*)nullptr, 0.0, status);
     }
     if (marg != nullptr) {
         const int M = 6 * g.N - 1;
@@ -548,35 +605,35 @@ static hipError_t launch_final_q(const Tin* img, const Geom& g, void* scratch, u
     return hipGetLastError();
 }
 
-template <typename Tin>
+template <typename Tin, typename Acc>
 hipError_t launch_inim_carries(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st) {
     switch (g.Q) {
-        case 1: return launch_carries_q<Tin, 1>(img, g, scratch, status, st);
-        case 2: return launch_carries_q<Tin, 2>(img, g, scratch, status, st);
-        case 4: return launch_carries_q<Tin, 4>(img, g, scratch, status, st);
-        case 8: return launch_carries_q<Tin, 8>(img, g, scratch, status, st);
+        case 1: return launch_carries_q<Tin, Acc, 1>(img, g, scratch, status, st);
+        case 2: return launch_carries_q<Tin, Acc, 2>(img, g, scratch, status, st);
+        case 4: return launch_carries_q<Tin, Acc, 4>(img, g, scratch, status, st);
     }
     return hipErrorInvalidValue;
 }
 
-template <typename Tin>
+template <typename Tin, typename Acc>
 hipError_t launch_inim_final(const Tin* img, const Geom& g, void* scratch, uint32_t mask, Tin* planes, float2* field,
                              double d0, double* marg, const int* status, hipStream_t st) {
     switch (g.Q) {
-        case 1: return launch_final_q<Tin, 1>(img, g, scratch, mask, planes, field, d0, marg, status, st);
-        case 2: return launch_final_q<Tin, 2>(img, g, scratch, mask, planes, field, d0, marg, status, st);
-        case 4: return launch_final_q<Tin, 4>(img, g, scratch, mask, planes, field, d0, marg, status, st);
-        case 8: return launch_final_q<Tin, 8>(img, g, scratch, mask, planes, field, d0, marg, status, st);
+        case 1: return launch_final_q<Tin, Acc, 1>(img, g, scratch, mask, planes, field, d0, marg, status, st);
+        case 2: return launch_final_q<Tin, Acc, 2>(img, g, scratch, mask, planes, field, d0, marg, status, st);
+        case 4: return launch_final_q<Tin, Acc, 4>(img, g, scratch, mask, planes, field, d0, marg, status, st);
     }
     return hipErrorInvalidValue;
 }
 
-template hipError_t launch_inim_carries<uint32_t>(const uint32_t*, const Geom&, void*, const int*, hipStream_t);
-template hipError_t launch_inim_carries<float>(const float*, const Geom&, void*, const int*, hipStream_t);
-template hipError_t launch_inim_final<uint32_t>(const uint32_t*, const Geom&, void*, uint32_t, uint32_t*, float2*,
-                                                double, double*, const int*, hipStream_t);
-template hipError_t launch_inim_final<float>(const float*, const Geom&, void*, uint32_t, float*, float2*, double,
-                                             double*, const int*, hipStream_t);
+#define INIM_INSTANTIATE(TIN, ACC)                                                                                    \
+    template hipError_t launch_inim_carries<TIN, ACC>(const TIN*, const Geom&, void*, const int*, hipStream_t);      \
+    template hipError_t launch_inim_final<TIN, ACC>(const TIN*, const Geom&, void*, uint32_t, TIN*, float2*, double, \
+                                                    double*, const int*, hipStream_t);
+INIM_INSTANTIATE(uint32_t, uint32_t)
+INIM_INSTANTIATE(float, u128)
+INIM_INSTANTIATE(float, double)
+#undef INIM_INSTANTIATE
 
 hipError_t launch_deform_planes(const void* alpha, const void* alpha_t, int dt, const double* marg, int N, double d0,
                                 float2* field, hipStream_t st) {

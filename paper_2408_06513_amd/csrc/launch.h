@@ -19,9 +19,11 @@ struct BlurTaps {
 // (inim_scratch_bytes): the tile partial sums and band carries, then the final
 // pass, which writes the planes in `mask` -- or, when field != nullptr, the
 // deformation with background d0 -- and, when marg != nullptr, the marginals.
-template <typename Tin>
+// Accumulators: uint32 for uint32 rasters; for float rasters unsigned
+// __int128 (exact 128-bit fixed point) or double.
+template <typename Tin, typename Acc>
 hipError_t launch_inim_carries(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st);
-template <typename Tin>
+template <typename Tin, typename Acc>
 hipError_t launch_inim_final(const Tin* img, const Geom& g, void* scratch, uint32_t mask, Tin* planes, float2* field,
                              double d0, double* marg, const int* status, hipStream_t st);
 
