@@ -33,14 +33,12 @@ def log(msg: str):
 
 
 def stage_bytes(n: int, res: int) -> dict:
-    """Algorithmic bytes of one launch of each stage (what the method must move)."""
+    """Algorithmic bytes of one launch of each per-iteration stage (what the method must move)."""
     px = res * res
     return {
-        "splat": 8 * n + 4 * px,          # read xy, write the count raster
-        "smooth": 4 * px + 4 * px,        # read counts, write the density
-        "inim_carries": 4 * px,           # read the density once
-        "inim_deform": 4 * px + 8 * px,   # read the density, write the 2-channel field
-        "advect": 16 * n + 8 * px,        # read + write xy, read the field once
+        "smooth_aggregate": 4 * px + 4 * px + 4 * px,  # read counts, write density, clear next counts
+        "inim_deform": 4 * px + 8 * px,                # read the density, write the 2-channel field
+        "advect_splat": 16 * n + 8 * px + 4 * px,      # read + write xy, read the field, next counts
     }
 
 
@@ -87,7 +85,8 @@ def bench_regularize(args, dev):
         ms = capi.regularize_timed(xy, res, iters, radius=radius, ws=ws)
         for k, v in ms.items():
             acc[k] += v
-    stage_us = {k: 1e3 * v / (reps * iters) for k, v in acc.items() if k != "total"}
+    stage_us = {k: 1e3 * v / (reps * iters) for k, v in acc.items() if k not in ("total", "splat_prologue")}
+    stage_us["splat_prologue_per_call"] = 1e3 * acc["splat_prologue"] / reps
     stage_us["total_per_iter"] = 1e3 * acc["total"] / (reps * iters)
     sb = stage_bytes(n, res)
     dom = max(sb, key=lambda k: stage_us[k])

@@ -126,12 +126,15 @@ int inim_rasterize(const float* xy, int64_t n, int32_t res, const inim_params* p
  *   img      device, uint32 or float [res*res], read only.
  *   planes   device, [popcount(mask)][res*res] of the input's type, planes in
  *            bit order; written.  May be NULL when mask == 0.
- *   marg     device, double [4 res - 1], the marginals above; may be NULL.
+ *   marg     device, double [6 res - 1], the marginals above; may be NULL.
  * uint32: planes and marginals are exact modulo 2^32 (exact when the total is
- * below 2^32).  float: sums are accumulated in double and rounded once; for
- * strictly positive inputs every element is within 1e-6 relative of the exact
- * sum, and texels whose region is empty by construction (for instance beta
- * on the last row) are exactly 0.
+ * below 2^32).  float: every input is taken exactly as a 128-bit fixed-point
+ * number with 64 fractional bits (exact for magnitudes in [2^-64, 2^62); a
+ * smaller magnitude is truncated toward zero), all sums and complements are
+ * formed exactly in that integer format, and each output is rounded once to
+ * float (planes) or double (marginals).  Hence every plane element is the
+ * correctly rounded region sum, within one float rounding, and regions that
+ * are empty are exactly 0, provided the total magnitude stays below 2^63.
  * EINVAL for a bad size, an unknown mask bit or a NULL plane pointer with a
  * non-zero mask; EWORKSPACE if ws is too small.
  */
@@ -179,12 +182,16 @@ int inim_regularize(float* xy, int64_t n, int32_t res, int32_t iters, const inim
                     void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
- * inim_regularize instrumented for measurement: records a HIP event before
- * and after every stage of every iteration on `stream`, synchronises, and
- * adds the elapsed milliseconds of each stage into stage_ms[0..5]:
- *   0 fill+splat  1 smooth  2 integral-image carries  3 integral images +
- *   deformation  4 advect  5 whole call.
- * stage_ms is host memory, not cleared.  Same results as inim_regularize.
+ * inim_regularize instrumented for measurement: records HIP events on
+ * `stream` around the stages, synchronises after each iteration, and adds the
+ * elapsed milliseconds into stage_ms[0..5]:
+ *   0 the call's initial splat (count raster cleared, every sample splatted)
+ *   1 smoothing + tile partial sums of the integral images (per iteration)
+ *   2 integral-image carries, the band scans (per iteration)
+ *   3 integral images + per-texel deformation (per iteration)
+ *   4 advection, which also splats the moved samples for the next iteration
+ *   5 the whole call.
+ * stage_ms is host memory and is not cleared.  Same results as inim_regularize.
  */
 int inim_regularize_timed(float* xy, int64_t n, int32_t res, int32_t iters, const inim_params* p,
                           void* ws, size_t ws_bytes, hipStream_t stream, double* stage_ms);

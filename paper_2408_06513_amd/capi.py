@@ -23,7 +23,7 @@ ALPHA_T, BETA_T, GAMMA_T, DELTA_T = 16, 32, 64, 128
 MASK_MIN = ALPHA | ALPHA_T
 MASK_ALL = 0xFF
 PLANES = ("alpha", "beta", "gamma", "delta", "alpha_t", "beta_t", "gamma_t", "delta_t")
-STAGES = ("splat", "smooth", "inim_carries", "inim_deform", "advect", "total")
+STAGES = ("splat_prologue", "smooth_aggregate", "inim_scans", "inim_deform", "advect_splat", "total")
 
 EXPORTS = (
     "inim_default_params", "inim_strerror", "inim_last_error", "inim_workspace_size",

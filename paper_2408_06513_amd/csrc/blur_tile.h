@@ -1,0 +1,62 @@
+// blur_tile.h -- the separable Gaussian of Sec. 4.1 on one 64 x 16 output tile
+// (shared by the stand-alone blur and the blur fused with the integral-image
+// aggregate pass).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "launch.h"
+
+namespace inim {
+
+constexpr int kBX = 64, kBY = 16;
+
+// Half-sample symmetric continuation: index -1-t reads t, N+t reads N-1-t.
+__device__ __forceinline__ int mirror(int k, int N) {
+    const int P = 2 * N;
+    int m = k % P;
+    if (m < 0) m += P;
+    return m >= N ? P - 1 - m : m;
+}
+
+__host__ __device__ inline size_t blur_smem_floats(int r) {
+    return (size_t)(kBY + 2 * r) * (kBX + 2 * r) + (size_t)(kBY + 2 * r) * kBX;
+}
+
+// Blurs the output tile at (ox, oy) with a block of 256 threads: the
+// (16+2r) x (64+2r) window of counts is staged in `lds` as float, filtered
+// along x into a second LDS buffer, then along y; emit(row, col, value) is
+// called once for every output texel of the tile inside the raster.
+template <typename Emit>
+__device__ __forceinline__ void blur_tile(const uint32_t* __restrict__ counts, int N, const BlurTaps& taps, int ox,
+                                          int oy, float* lds, Emit emit) {
+    const int r = taps.r;
+    const int IW = kBX + 2 * r, IH = kBY + 2 * r;
+    float* in = lds;             // IH x IW
+    float* mid = lds + IH * IW;  // IH x kBX
+    for (int k = threadIdx.x; k < IH * IW; k += blockDim.x) {
+        const int row = k / IW, cc = k - row * IW;
+        const int gj = mirror(oy + row - r, N), gi = mirror(ox + cc - r, N);
+        in[k] = (float)counts[(size_t)gj * N + gi];
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < IH * kBX; k += blockDim.x) {
+        const int row = k / kBX, cc = k - row * kBX;
+        const float* s = in + row * IW + cc;
+        float a = 0.0f;
+        for (int m = 0; m <= 2 * r; ++m) a = fmaf(taps.w[m], s[m], a);
+        mid[k] = a;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kBY * kBX; k += blockDim.x) {
+        const int row = k / kBX, cc = k - row * kBX;
+        if (ox + cc >= N || oy + row >= N) continue;
+        const float* s = mid + row * kBX + cc;
+        float a = 0.0f;
+        for (int m = 0; m <= 2 * r; ++m) a = fmaf(taps.w[m], s[m * kBX], a);
+        emit(row, cc, a);
+    }
+}
+
+}  // namespace inim

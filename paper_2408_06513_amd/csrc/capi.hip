@@ -82,7 +82,7 @@ constexpr size_t kStatusBytes = 256;
 
 // Workspace of rasterize / advect / regularize.
 struct RegLayout {
-    size_t status, counts, density, field, scratch, total;
+    size_t status, counts[2], density, field, scratch, total;
     Geom g;
     bool f32;  // integral images of the float density in double (radius > 0), or of the counts
 };
@@ -94,7 +94,8 @@ RegLayout reg_layout(int32_t res, int radius) {
     L.g = make_geom(res, L.f32 ? 8 : 4);
     size_t o = 0;
     L.status = o; o += kStatusBytes;
-    L.counts = o; o += align256(NN * 4);
+    L.counts[0] = o; o += align256(NN * 4);
+    L.counts[1] = o; o += align256(NN * 4);
     L.density = o; o += align256(NN * 4);
     L.field = o; o += align256(NN * 8);
     L.scratch = o; o += inim_scratch_bytes(L.g, L.f32 ? 8 : 4);
@@ -116,42 +117,74 @@ int check_xy(const void* xy, int64_t n) {
     return INIM_OK;
 }
 
-// One iteration of Sec. 4.3 on the caller's stream; `events` (optional) gets
-// 6 events recorded at the stage boundaries.
-int enqueue_iteration(float* xy, int64_t n, int32_t res, const Params& P, double d0, const BlurTaps& taps,
-                      const RegLayout& L, char* ws, bool first, hipStream_t st, hipEvent_t* ev) {
+// Events of the timed variant: per call the splat prologue, per iteration
+// the boundaries of its four stages.
+struct StageEvents {
+    hipEvent_t pre[2];
+    hipEvent_t it[5];
+};
+
+// The whole call (Sec. 4.3) on the caller's stream.  Iteration k reads the
+// count raster counts[k % 2]; its advection splats the moved samples into
+// counts[(k+1) % 2], which the smoothing of iteration k has zeroed.
+int enqueue_regularize(float* xy, int64_t n, int32_t res, int32_t iters, double d0, const BlurTaps& taps,
+                       const RegLayout& L, char* ws, hipStream_t st, StageEvents* ev, double* stage_ms) {
     int* status = reinterpret_cast<int*>(ws + L.status);
-    uint32_t* counts = reinterpret_cast<uint32_t*>(ws + L.counts);
+    uint32_t* counts[2] = {reinterpret_cast<uint32_t*>(ws + L.counts[0]), reinterpret_cast<uint32_t*>(ws + L.counts[1])};
     float* density = reinterpret_cast<float*>(ws + L.density);
     float2* field = reinterpret_cast<float2*>(ws + L.field);
+    float2* pts = reinterpret_cast<float2*>(xy);
     void* scratch = ws + L.scratch;
     const size_t NN = (size_t)res * res;
+    const bool fused = L.f32 && blur_aggregate_fits(L.g);
     hipError_t e;
-    if (ev) (void)hipEventRecord(ev[0], st);
-    if ((e = launch_fill(counts, NN, status, first, st)) != hipSuccess) return hip_fail(e, "fill");
-    if ((e = launch_splat(reinterpret_cast<const float2*>(xy), n, res, counts, status, st)) != hipSuccess)
-        return hip_fail(e, "splat");
-    if (ev) (void)hipEventRecord(ev[1], st);
-    if (L.f32) {
-        if ((e = launch_blur(counts, density, res, taps, status, st)) != hipSuccess) return hip_fail(e, "blur");
+    if (ev) (void)hipEventRecord(ev->pre[0], st);
+    if ((e = launch_fill(counts[0], NN, status, true, st)) != hipSuccess) return hip_fail(e, "fill");
+    if ((e = launch_splat(pts, n, res, counts[0], status, st)) != hipSuccess) return hip_fail(e, "splat");
+    if (ev) {
+        (void)hipEventRecord(ev->pre[1], st);
+        if (hipEventSynchronize(ev->pre[1]) != hipSuccess) return fail(INIM_EHIP, "hipEventSynchronize failed");
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, ev->pre[0], ev->pre[1]);
+        stage_ms[0] += ms;
     }
-    if (ev) (void)hipEventRecord(ev[2], st);
-    if (L.f32)
-        e = launch_inim_carries<float, double>(density, L.g, scratch, status, st);
-    else
-        e = launch_inim_carries<uint32_t, uint32_t>(counts, L.g, scratch, status, st);
-    if (e != hipSuccess) return hip_fail(e, "integral-image carries");
-    if (ev) (void)hipEventRecord(ev[3], st);
-    if (L.f32)
-        e = launch_inim_final<float, double>(density, L.g, scratch, 0u, nullptr, field, d0, nullptr, status, st);
-    else
-        e = launch_inim_final<uint32_t, uint32_t>(counts, L.g, scratch, 0u, nullptr, field, d0, nullptr, status, st);
-    if (e != hipSuccess) return hip_fail(e, "integral images + deformation");
-    if (ev) (void)hipEventRecord(ev[4], st);
-    if ((e = launch_advect(field, res, reinterpret_cast<float2*>(xy), n, status, st)) != hipSuccess)
-        return hip_fail(e, "advect");
-    if (ev) (void)hipEventRecord(ev[5], st);
-    (void)P;
+    for (int it = 0; it < iters; ++it) {
+        uint32_t* cur = counts[it & 1];
+        uint32_t* nxt = (it + 1 < iters) ? counts[(it + 1) & 1] : nullptr;
+        if (ev) (void)hipEventRecord(ev->it[0], st);
+        if (fused) {
+            e = launch_blur_aggregate(cur, density, nxt, res, taps, L.g, scratch, status, st);
+        } else if (L.f32) {
+            e = launch_blur(cur, density, res, taps, status, st);
+            if (e == hipSuccess && nxt) e = launch_fill(nxt, NN, status, false, st);
+            if (e == hipSuccess) e = launch_inim_aggregate<float, double>(density, L.g, scratch, status, st);
+        } else {
+            e = launch_inim_aggregate<uint32_t, uint32_t>(cur, L.g, scratch, status, st);
+        }
+        if (e != hipSuccess) return hip_fail(e, "smooth + aggregate");
+        if (ev) (void)hipEventRecord(ev->it[1], st);
+        e = L.f32 ? launch_inim_scans<double>(L.g, scratch, status, st)
+                  : launch_inim_scans<uint32_t>(L.g, scratch, status, st);
+        if (e != hipSuccess) return hip_fail(e, "integral-image scans");
+        if (ev) (void)hipEventRecord(ev->it[2], st);
+        if (L.f32)
+            e = launch_inim_final<float, double>(density, L.g, scratch, 0u, nullptr, field, d0, nullptr, status, st);
+        else
+            e = launch_inim_final<uint32_t, uint32_t>(cur, L.g, scratch, 0u, nullptr, field, d0, nullptr, status, st);
+        if (e == hipSuccess && !L.f32 && nxt) e = launch_fill(nxt, NN, status, false, st);
+        if (e != hipSuccess) return hip_fail(e, "integral images + deformation");
+        if (ev) (void)hipEventRecord(ev->it[3], st);
+        if ((e = launch_advect(field, res, pts, n, nxt, status, st)) != hipSuccess) return hip_fail(e, "advect");
+        if (ev) {
+            (void)hipEventRecord(ev->it[4], st);
+            if (hipEventSynchronize(ev->it[4]) != hipSuccess) return fail(INIM_EHIP, "hipEventSynchronize failed");
+            for (int k = 0; k < 4; ++k) {
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, ev->it[k], ev->it[k + 1]);
+                stage_ms[1 + k] += ms;
+            }
+        }
+    }
     return INIM_OK;
 }
 
@@ -172,37 +205,19 @@ int regularize_impl(float* xy, int64_t n, int32_t res, int32_t iters, const inim
     }
     const double d0 = P.d0 < 0.0 ? (double)n / ((double)res * (double)res) : P.d0;
     const BlurTaps taps = make_taps(P.radius, P.sigma);
-    hipEvent_t ev[6];
-    hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (stage_ms) {
-        for (int k = 0; k < 6; ++k)
-            if (hipEventCreate(&ev[k]) != hipSuccess) return fail(INIM_EHIP, "hipEventCreate failed");
-        if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
-            return fail(INIM_EHIP, "hipEventCreate failed");
-        (void)hipEventRecord(t0, stream);
-    }
-    for (int it = 0; it < iters; ++it) {
-        s = enqueue_iteration(xy, n, res, P, d0, taps, L, (char*)ws, it == 0, stream, stage_ms ? ev : nullptr);
-        if (s != INIM_OK) break;
-        if (stage_ms) {
-            if (hipEventSynchronize(ev[5]) != hipSuccess) { s = fail(INIM_EHIP, "hipEventSynchronize failed"); break; }
-            for (int k = 0; k < 5; ++k) {
-                float ms = 0.0f;
-                (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
-                stage_ms[k] += ms;
-            }
-        }
-    }
-    if (stage_ms) {
-        (void)hipEventRecord(t1, stream);
-        if (hipEventSynchronize(t1) != hipSuccess && s == INIM_OK) s = fail(INIM_EHIP, "hipEventSynchronize failed");
+    if (stage_ms == nullptr) return enqueue_regularize(xy, n, res, iters, d0, taps, L, (char*)ws, stream, nullptr, nullptr);
+
+    StageEvents ev;
+    hipEvent_t* all[7] = {&ev.pre[0], &ev.pre[1], &ev.it[0], &ev.it[1], &ev.it[2], &ev.it[3], &ev.it[4]};
+    for (auto* h : all)
+        if (hipEventCreate(h) != hipSuccess) return fail(INIM_EHIP, "hipEventCreate failed");
+    s = enqueue_regularize(xy, n, res, iters, d0, taps, L, (char*)ws, stream, &ev, stage_ms);
+    if (s == INIM_OK) {
         float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, t0, t1);
+        (void)hipEventElapsedTime(&ms, ev.pre[0], ev.it[4]);
         stage_ms[5] += ms;
-        for (int k = 0; k < 6; ++k) (void)hipEventDestroy(ev[k]);
-        (void)hipEventDestroy(t0);
-        (void)hipEventDestroy(t1);
     }
+    for (auto* h : all) (void)hipEventDestroy(*h);
     return s;
 }
 
@@ -335,8 +350,8 @@ int inim_advect(const float* field, int32_t res, float* xy, int64_t n, void* ws,
     if (n == 0) return INIM_OK;
     if ((e = launch_validate(reinterpret_cast<const float2*>(xy), n, status, stream)) != hipSuccess)
         return hip_fail(e, "validate");
-    if ((e = launch_advect(reinterpret_cast<const float2*>(field), res, reinterpret_cast<float2*>(xy), n, status,
-                           stream)) != hipSuccess)
+    if ((e = launch_advect(reinterpret_cast<const float2*>(field), res, reinterpret_cast<float2*>(xy), n, nullptr,
+                           status, stream)) != hipSuccess)
         return hip_fail(e, "advect");
     return INIM_OK;
 }

@@ -22,6 +22,7 @@
 //                 deformation of Sec. 4.2 directly.
 #include <hip/hip_runtime.h>
 
+#include "blur_tile.h"
 #include "device_common.h"
 #include "inim_plan.h"
 #include "launch.h"
@@ -42,6 +43,65 @@ __device__ __forceinline__ void load_tile_row(const Tin* __restrict__ p, bool ac
 }
 
 // ------------------------------------------------------------------ pass 1
+// Tile-local state of the aggregate pass for one wave: per column, the band-
+// local column prefix and the up-left / up-right diagonal sums of it, with
+// zero outside the tile.  step() consumes one row of the tile.
+template <int Q, typename Acc>
+struct TileAgg {
+    Acc cp[Q], L[Q], R[Q];
+
+    __device__ __forceinline__ void init() {
+#pragma unroll
+        for (int e = 0; e < Q; ++e) cp[e] = L[e] = R[e] = Acc(0);
+    }
+
+    template <typename Tin>
+    __device__ __forceinline__ void step(const Tin (&v)[Q], int r, int lane, int lastLane, const Agg<Acc>& A,
+                                         size_t ebase) {
+#pragma unroll
+        for (int e = 0; e < Q; ++e) cp[e] += to_acc<Acc, Tin>(v[e]);
+        Acc upL = shfl_up1(L[Q - 1]);
+        Acc dnR = shfl_down1(R[0]);
+        if (lane == 0) upL = Acc(0);
+        if (lane >= lastLane) dnR = Acc(0);
+#pragma unroll
+        for (int e = Q - 1; e >= 1; --e) L[e] = cp[e] + L[e - 1];
+        L[0] = cp[0] + upL;
+#pragma unroll
+        for (int e = 0; e < Q - 1; ++e) R[e] = cp[e] + R[e + 1];
+        R[Q - 1] = cp[Q - 1] + dnR;
+        Acc s = Acc(0);
+#pragma unroll
+        for (int e = 0; e < Q; ++e) s += cp[e];
+        s = wave_sum(s);
+        if (lane == 0) {
+            A.trow[ebase + r] = s;
+            A.tRedge[ebase + r] = R[0];
+        }
+        if (lane == lastLane) A.tLedge[ebase + r] = L[Q - 1];
+    }
+
+    // band-level outputs: column sums, their in-tile prefix, diagonal sums
+    __device__ __forceinline__ void finish(int lane, bool act, const Agg<Acc>& A, size_t o) {
+        Acc pre[Q];
+        Acc run = Acc(0);
+#pragma unroll
+        for (int e = 0; e < Q; ++e) { run += cp[e]; pre[e] = run; }
+        Acc incl = wave_inclusive_scan(run);
+        Acc ex = shfl_up1(incl);
+        if (lane == 0) ex = Acc(0);
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < Q; ++e) {
+                A.colsum[o + e] = cp[e];
+                A.tcsp[o + e] = ex + pre[e];
+                A.tLend[o + e] = L[e];
+                A.tRend[o + e] = R[e];
+            }
+        }
+    }
+};
+
 template <int Q, typename Tin, typename Acc>
 __global__ __launch_bounds__(256) void k_inim_aggregate(const Tin* __restrict__ img, Geom g, Agg<Acc> A,
                                                         const int* status) {
@@ -57,10 +117,8 @@ __global__ __launch_bounds__(256) void k_inim_aggregate(const Tin* __restrict__ 
     const Tin* src = img + (size_t)b * g.H * N + col;
     const size_t ebase = ((size_t)b * g.T + c) * g.H;
 
-    Acc cp[Q], L[Q], R[Q];
-#pragma unroll
-    for (int e = 0; e < Q; ++e) cp[e] = L[e] = R[e] = Acc(0);
-
+    TileAgg<Q, Acc> st;
+    st.init();
     Tin buf[kPF][Q];
 #pragma unroll
     for (int p = 0; p < kPF; ++p)
@@ -75,51 +133,46 @@ __global__ __launch_bounds__(256) void k_inim_aggregate(const Tin* __restrict__ 
 #pragma unroll
                 for (int e = 0; e < Q; ++e) v[e] = buf[p][e];
                 if (r + kPF < g.H) load_tile_row<Tin, Q>(src + (size_t)(r + kPF) * N, act, buf[p]);
-
-#pragma unroll
-                for (int e = 0; e < Q; ++e) cp[e] += to_acc<Acc, Tin>(v[e]);
-                Acc upL = shfl_up1(L[Q - 1]);
-                Acc dnR = shfl_down1(R[0]);
-                if (lane == 0) upL = Acc(0);
-                if (lane >= g.lastLane) dnR = Acc(0);
-#pragma unroll
-                for (int e = Q - 1; e >= 1; --e) L[e] = cp[e] + L[e - 1];
-                L[0] = cp[0] + upL;
-#pragma unroll
-                for (int e = 0; e < Q - 1; ++e) R[e] = cp[e] + R[e + 1];
-                R[Q - 1] = cp[Q - 1] + dnR;
-
-                Acc s = Acc(0);
-#pragma unroll
-                for (int e = 0; e < Q; ++e) s += cp[e];
-                s = wave_sum(s);
-                if (lane == 0) {
-                    A.trow[ebase + r] = s;
-                    A.tRedge[ebase + r] = R[0];
-                }
-                if (lane == g.lastLane) A.tLedge[ebase + r] = L[Q - 1];
+                st.step(v, r, lane, g.lastLane, A, ebase);
             }
         }
     }
+    st.finish(lane, act, A, (size_t)b * N + col);
+}
 
-    // band-level outputs: column sums, their in-tile prefix, diagonal sums
-    Acc pre[Q];
-    Acc run = Acc(0);
-#pragma unroll
-    for (int e = 0; e < Q; ++e) { run += cp[e]; pre[e] = run; }
-    Acc incl = wave_inclusive_scan(run);
-    Acc ex = shfl_up1(incl);
-    if (lane == 0) ex = Acc(0);
-    if (act) {
-        const size_t o = (size_t)b * N + col;
-#pragma unroll
-        for (int e = 0; e < Q; ++e) {
-            A.colsum[o + e] = cp[e];
-            A.tcsp[o + e] = ex + pre[e];
-            A.tLend[o + e] = L[e];
-            A.tRend[o + e] = R[e];
-        }
+// Blur fused with pass 1 for 64 x 16 tiles (g.W == 64, g.H == 16, N >= 64):
+// the block blurs one tile of counts (blur_tile.h), writes the density and
+// keeps the tile in LDS, optionally zeroes the same texels of the next
+// iteration's count raster, then its first wave runs the aggregate over the
+// tile rows from LDS.
+template <typename Acc>
+__global__ __launch_bounds__(256) void k_blur_aggregate(const uint32_t* __restrict__ counts, float* __restrict__ density,
+                                                        uint32_t* __restrict__ zero_next, BlurTaps taps, Geom g,
+                                                        Agg<Acc> A, const int* status) {
+    extern __shared__ float lds[];
+    __shared__ float tile[kBY][kBX];
+    if (failed(status)) return;
+    const int N = g.N;
+    const int ox = blockIdx.x * kBX, oy = blockIdx.y * kBY;
+    blur_tile(counts, N, taps, ox, oy, lds, [&](int row, int cc, float v) {
+        const size_t k = (size_t)(oy + row) * N + ox + cc;
+        density[k] = v;
+        tile[row][cc] = v;
+        if (zero_next != nullptr) zero_next[k] = 0u;
+    });
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
+    const int lane = lane_id();
+    const int b = blockIdx.y, c = blockIdx.x;
+    const size_t ebase = ((size_t)b * g.T + c) * g.H;
+    TileAgg<1, Acc> st;
+    st.init();
+#pragma unroll 4
+    for (int r = 0; r < kBY; ++r) {
+        const float v[1] = {tile[r][lane]};
+        st.step(v, r, lane, 63, A, ebase);
     }
+    st.finish(lane, true, A, (size_t)b * N + ox + lane);
 }
 
 // ------------------------------------------------------------------ passes 2 and 3
@@ -565,20 +618,60 @@ static size_t final_smem(const Geom& g, bool needUV) {
     return needUV ? (size_t)kWavesPerBlock * 2 * (g.W + g.H - 1) * sizeof(Acc) : 0;
 }
 
-template <typename Tin, typename Acc, int Q>
-static hipError_t launch_carries_q(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st) {
+template <typename Acc>
+hipError_t launch_inim_scans(const Geom& g, void* scratch, const int* status, hipStream_t st) {
     Agg<Acc> A;
     Carry<Acc> K;
     carve<Acc>(g, (char*)scratch, A, K);
-    const int tiles = g.B * g.T;
-    const dim3 grd((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL((k_inim_aggregate<Q, Tin, Acc>), grd, dim3(64 * kWavesPerBlock), 0, st, img, g, A, status);
     const int nw = scan_waves(g.B);
     hipLaunchKernelGGL((k_inim_scan_col<Acc>), dim3((g.N + 63) / 64), dim3(64 * nw), (size_t)nw * 2 * 64 * sizeof(Acc),
                        st, g, A, K, status);
     hipLaunchKernelGGL((k_inim_scan_diag<Acc>), dim3((2 * g.N + 1 + 63) / 64, 3), dim3(64 * nw),
                        (size_t)nw * 64 * sizeof(Acc), st, g, A, K, status);
     return hipGetLastError();
+}
+
+bool blur_aggregate_fits(const Geom& g) { return g.W == kBX && g.H == kBY && g.Q == 1 && g.N >= kBX; }
+
+hipError_t launch_blur_aggregate(const uint32_t* counts, float* density, uint32_t* zero_next, int N,
+                                 const BlurTaps& taps, const Geom& g, void* scratch, const int* status,
+                                 hipStream_t st) {
+    if (!blur_aggregate_fits(g) || N != g.N) return hipErrorInvalidValue;
+    Agg<double> A;
+    Carry<double> K;
+    carve<double>(g, (char*)scratch, A, K);
+    const size_t smem = sizeof(float) * blur_smem_floats(taps.r);
+    hipLaunchKernelGGL((k_blur_aggregate<double>), dim3(N / kBX, N / kBY), dim3(256), smem, st, counts, density,
+                       zero_next, taps, g, A, status);
+    return hipGetLastError();
+}
+
+template <typename Tin, typename Acc, int Q>
+static hipError_t launch_aggregate_q(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st) {
+    Agg<Acc> A;
+    Carry<Acc> K;
+    carve<Acc>(g, (char*)scratch, A, K);
+    const int tiles = g.B * g.T;
+    const dim3 grd((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL((k_inim_aggregate<Q, Tin, Acc>), grd, dim3(64 * kWavesPerBlock), 0, st, img, g, A, status);
+    return hipGetLastError();
+}
+
+template <typename Tin, typename Acc>
+hipError_t launch_inim_aggregate(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st) {
+    switch (g.Q) {
+        case 1: return launch_aggregate_q<Tin, Acc, 1>(img, g, scratch, status, st);
+        case 2: return launch_aggregate_q<Tin, Acc, 2>(img, g, scratch, status, st);
+        case 4: return launch_aggregate_q<Tin, Acc, 4>(img, g, scratch, status, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename Tin, typename Acc>
+hipError_t launch_inim_carries(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st) {
+    hipError_t e = launch_inim_aggregate<Tin, Acc>(img, g, scratch, status, st);
+    if (e == hipSuccess) e = launch_inim_scans<Acc>(g, scratch, status, st);
+    return e;
 }
 
 template <typename Tin, typename Acc, int Q>
@@ -606,16 +699,6 @@ static hipError_t launch_final_q(const Tin* img, const Geom& g, void* scratch, u
 }
 
 template <typename Tin, typename Acc>
-hipError_t launch_inim_carries(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st) {
-    switch (g.Q) {
-        case 1: return launch_carries_q<Tin, Acc, 1>(img, g, scratch, status, st);
-        case 2: return launch_carries_q<Tin, Acc, 2>(img, g, scratch, status, st);
-        case 4: return launch_carries_q<Tin, Acc, 4>(img, g, scratch, status, st);
-    }
-    return hipErrorInvalidValue;
-}
-
-template <typename Tin, typename Acc>
 hipError_t launch_inim_final(const Tin* img, const Geom& g, void* scratch, uint32_t mask, Tin* planes, float2* field,
                              double d0, double* marg, const int* status, hipStream_t st) {
     switch (g.Q) {
@@ -628,6 +711,8 @@ hipError_t launch_inim_final(const Tin* img, const Geom& g, void* scratch, uint3
 
 #define INIM_INSTANTIATE(TIN, ACC)                                                                                    \
     template hipError_t launch_inim_carries<TIN, ACC>(const TIN*, const Geom&, void*, const int*, hipStream_t);      \
+    template hipError_t launch_inim_aggregate<TIN, ACC>(const TIN*, const Geom&, void*, const int*, hipStream_t);    \
+    template hipError_t launch_inim_scans<ACC>(const Geom&, void*, const int*, hipStream_t);                         \
     template hipError_t launch_inim_final<TIN, ACC>(const TIN*, const Geom&, void*, uint32_t, TIN*, float2*, double, \
                                                     double*, const int*, hipStream_t);
 INIM_INSTANTIATE(uint32_t, uint32_t)

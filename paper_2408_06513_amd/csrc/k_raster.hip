@@ -3,6 +3,7 @@
 // bilinear advection of Sec. 4.2, input validation and fills.
 #include <hip/hip_runtime.h>
 
+#include "blur_tile.h"
 #include "device_common.h"
 #include "launch.h"
 
@@ -59,51 +60,14 @@ __global__ __launch_bounds__(256) void k_validate(const float2* __restrict__ xy,
 }
 
 // ------------------------------------------------------------------ blur
-// Half-sample symmetric continuation: index -1-t reads t, N+t reads N-1-t.
-__device__ __forceinline__ int mirror(int k, int N) {
-    const int P = 2 * N;
-    int m = k % P;
-    if (m < 0) m += P;
-    return m >= N ? P - 1 - m : m;
-}
-
-constexpr int kBX = 64, kBY = 16;
-
-// One 64 x 16 output tile per 256-thread block: the (16+2r) x (64+2r) input
-// window is staged in LDS as float, filtered along x into a second LDS
-// buffer, then along y into global memory.
+// One 64 x 16 output tile per 256-thread block (blur_tile.h).
 __global__ __launch_bounds__(256) void k_blur(const uint32_t* __restrict__ counts, float* __restrict__ out, int N,
                                               BlurTaps taps, const int* status) {
     extern __shared__ float lds[];
     if (failed(status)) return;
-    const int r = taps.r;
-    const int IW = kBX + 2 * r, IH = kBY + 2 * r;
-    float* in = lds;            // IH x IW
-    float* mid = lds + IH * IW; // IH x kBX
     const int ox = blockIdx.x * kBX, oy = blockIdx.y * kBY;
-    for (int k = threadIdx.x; k < IH * IW; k += blockDim.x) {
-        const int row = k / IW, cc = k - row * IW;
-        const int gj = mirror(oy + row - r, N), gi = mirror(ox + cc - r, N);
-        in[k] = (float)counts[(size_t)gj * N + gi];
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < IH * kBX; k += blockDim.x) {
-        const int row = k / kBX, cc = k - row * kBX;
-        const float* s = in + row * IW + cc;
-        float a = 0.0f;
-        for (int m = 0; m <= 2 * r; ++m) a = fmaf(taps.w[m], s[m], a);
-        mid[k] = a;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < kBY * kBX; k += blockDim.x) {
-        const int row = k / kBX, cc = k - row * kBX;
-        const int gi = ox + cc, gj = oy + row;
-        if (gi >= N || gj >= N) continue;
-        const float* s = mid + row * kBX + cc;
-        float a = 0.0f;
-        for (int m = 0; m <= 2 * r; ++m) a = fmaf(taps.w[m], s[m * kBX], a);
-        out[(size_t)gj * N + gi] = a;
-    }
+    blur_tile(counts, N, taps, ox, oy, lds,
+              [&](int row, int cc, float v) { out[(size_t)(oy + row) * N + ox + cc] = v; });
 }
 
 // ------------------------------------------------------------------ advect
@@ -120,8 +84,10 @@ __device__ __forceinline__ void cell_of(float x, int N, int& k0, double& f) {
 
 __device__ __forceinline__ float clamp01(double v) { return (float)(v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v)); }
 
+// counts_next (optional): each moved sample is also splatted into it, the
+// count raster of the next iteration (Sec. 4.3, step 1 of the next round).
 __global__ __launch_bounds__(256) void k_advect(const float2* __restrict__ field, int N, float2* __restrict__ xy,
-                                                int64_t n, const int* status) {
+                                                int64_t n, uint32_t* __restrict__ counts_next, const int* status) {
     if (failed(status)) return;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
@@ -136,7 +102,11 @@ __global__ __launch_bounds__(256) void k_advect(const float2* __restrict__ field
         const double w00 = (1.0 - fx) * (1.0 - fy), w10 = fx * (1.0 - fy), w01 = (1.0 - fx) * fy, w11 = fx * fy;
         const double nx = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
         const double ny = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
-        xy[p] = make_float2(clamp01(nx), clamp01(ny));
+        const float2 o = make_float2(clamp01(nx), clamp01(ny));
+        xy[p] = o;
+        if (counts_next != nullptr)
+            __hip_atomic_fetch_add(counts_next + (size_t)texel_of(o.y, N) * N + texel_of(o.x, N), 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -165,15 +135,15 @@ hipError_t launch_validate(const float2* xy, int64_t n, int* status, hipStream_t
 
 hipError_t launch_blur(const uint32_t* counts, float* out, int N, const BlurTaps& taps, const int* status,
                        hipStream_t st) {
-    const int r = taps.r;
-    const size_t smem = sizeof(float) * ((size_t)(kBY + 2 * r) * (kBX + 2 * r) + (size_t)(kBY + 2 * r) * kBX);
+    const size_t smem = sizeof(float) * blur_smem_floats(taps.r);
     const dim3 grd((N + kBX - 1) / kBX, (N + kBY - 1) / kBY);
     hipLaunchKernelGGL(k_blur, grd, dim3(256), smem, st, counts, out, N, taps, status);
     return hipGetLastError();
 }
 
-hipError_t launch_advect(const float2* field, int N, float2* xy, int64_t n, const int* status, hipStream_t st) {
-    hipLaunchKernelGGL(k_advect, dim3(grid_for(n)), dim3(256), 0, st, field, N, xy, n, status);
+hipError_t launch_advect(const float2* field, int N, float2* xy, int64_t n, uint32_t* counts_next, const int* status,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_advect, dim3(grid_for(n)), dim3(256), 0, st, field, N, xy, n, counts_next, status);
     return hipGetLastError();
 }
 

@@ -23,6 +23,11 @@ struct BlurTaps {
 // __int128 (exact 128-bit fixed point) or double.
 template <typename Tin, typename Acc>
 hipError_t launch_inim_carries(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st);
+// The two halves of launch_inim_carries: the tile partial sums, then the band scans.
+template <typename Tin, typename Acc>
+hipError_t launch_inim_aggregate(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st);
+template <typename Acc>
+hipError_t launch_inim_scans(const Geom& g, void* scratch, const int* status, hipStream_t st);
 template <typename Tin, typename Acc>
 hipError_t launch_inim_final(const Tin* img, const Geom& g, void* scratch, uint32_t mask, Tin* planes, float2* field,
                              double d0, double* marg, const int* status, hipStream_t st);
@@ -35,6 +40,14 @@ hipError_t launch_splat(const float2* xy, int64_t n, int N, uint32_t* counts, in
 hipError_t launch_blur(const uint32_t* counts, float* out, int N, const BlurTaps& taps, const int* status,
                        hipStream_t st);
 hipError_t launch_validate(const float2* xy, int64_t n, int* status, hipStream_t st);
-hipError_t launch_advect(const float2* field, int N, float2* xy, int64_t n, const int* status, hipStream_t st);
+// counts_next != nullptr: also splat the moved samples into it (must be zero).
+hipError_t launch_advect(const float2* field, int N, float2* xy, int64_t n, uint32_t* counts_next, const int* status,
+                         hipStream_t st);
+// Blur of `counts` into `density` fused with the integral-image aggregate pass
+// of the double-accumulated deformation path (tiles of 64 x 16); zeroes
+// `zero_next` (N x N) when it is not null.  Only when blur_aggregate_fits(g).
+bool blur_aggregate_fits(const Geom& g);
+hipError_t launch_blur_aggregate(const uint32_t* counts, float* density, uint32_t* zero_next, int N,
+                                 const BlurTaps& taps, const Geom& g, void* scratch, const int* status, hipStream_t st);
 
 }  // namespace inim
