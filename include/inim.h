@@ -95,8 +95,9 @@ const char* inim_last_error(void);
 
 /*
  * Workspace for inim_rasterize, inim_advect and inim_regularize at this size:
- * status word, count raster, density raster, deformation field and the
- * integral-image carries.  `p` may be NULL (defaults).  EINVAL on bad sizes.
+ * status word, two count rasters, density raster, deformation field, the
+ * integral-image carries and a texel-ordered copy of the samples (16 bytes
+ * per sample).  `p` may be NULL (defaults).  EINVAL on bad sizes.
  */
 int inim_workspace_size(int32_t res, int64_t n, const inim_params* p, size_t* bytes);
 
@@ -185,7 +186,9 @@ int inim_regularize(float* xy, int64_t n, int32_t res, int32_t iters, const inim
  * inim_regularize instrumented for measurement: records HIP events on
  * `stream` around the stages, synchronises after each iteration, and adds the
  * elapsed milliseconds into stage_ms[0..5]:
- *   0 the call's initial splat (count raster cleared, every sample splatted)
+ *   0 once per call: sorting the samples by texel (count raster cleared,
+ *     every sample splatted with its rank, counts scanned, samples moved),
+ *     and moving the results back to the caller's order at the end
  *   1 smoothing + tile partial sums of the integral images (per iteration)
  *   2 integral-image carries, the band scans (per iteration)
  *   3 integral images + per-texel deformation (per iteration)
@@ -195,6 +198,23 @@ int inim_regularize(float* xy, int64_t n, int32_t res, int32_t iters, const inim
  */
 int inim_regularize_timed(float* xy, int64_t n, int32_t res, int32_t iters, const inim_params* p,
                           void* ws, size_t ws_bytes, hipStream_t stream, double* stage_ms);
+
+/*
+ * Graph replay of inim_regularize for callers that repeat the same call
+ * (Sec. 4.3 run many times, e.g. every frame of an interactive view).
+ * inim_graph_create makes an empty handle (host memory owned by the caller,
+ * released with inim_graph_destroy).  inim_regularize_graph behaves exactly
+ * like inim_regularize with the same arguments; the first call with a given
+ * (xy, n, res, iters, params, ws, ws_bytes) captures the whole launch
+ * sequence into a HIP graph on a private stream, and this and every later
+ * call with the same arguments launch that graph on `stream`.  Different
+ * arguments re-capture.  A handle must not be used by two threads at once.
+ * EHIP if capture or instantiation fails.
+ */
+int inim_graph_create(void** graph);
+int inim_graph_destroy(void* graph);
+int inim_regularize_graph(float* xy, int64_t n, int32_t res, int32_t iters, const inim_params* p,
+                          void* ws, size_t ws_bytes, void* graph, hipStream_t stream);
 
 /*
  * Waits for `stream`, returns the status word of the last call that used ws

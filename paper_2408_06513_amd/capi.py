@@ -23,12 +23,13 @@ ALPHA_T, BETA_T, GAMMA_T, DELTA_T = 16, 32, 64, 128
 MASK_MIN = ALPHA | ALPHA_T
 MASK_ALL = 0xFF
 PLANES = ("alpha", "beta", "gamma", "delta", "alpha_t", "beta_t", "gamma_t", "delta_t")
-STAGES = ("splat_prologue", "smooth_aggregate", "inim_scans", "inim_deform", "advect_splat", "total")
+STAGES = ("sort_unsort", "smooth_aggregate", "inim_scans", "inim_deform", "advect_splat", "total")
 
 EXPORTS = (
     "inim_default_params", "inim_strerror", "inim_last_error", "inim_workspace_size",
     "inim_inim_workspace_size", "inim_rasterize", "inim_inim_u32", "inim_inim_f32",
     "inim_deform", "inim_advect", "inim_regularize", "inim_regularize_timed", "inim_sync_status",
+    "inim_graph_create", "inim_graph_destroy", "inim_regularize_graph",
 )
 
 
@@ -97,6 +98,9 @@ def lib() -> ctypes.CDLL:
     L.inim_regularize.argtypes = [vp, i64, i32, i32, pp, vp, sz, vp]
     L.inim_regularize_timed.argtypes = [vp, i64, i32, i32, pp, vp, sz, vp, ctypes.POINTER(f64)]
     L.inim_sync_status.argtypes = [vp, vp]
+    L.inim_graph_create.argtypes = [ctypes.POINTER(vp)]
+    L.inim_graph_destroy.argtypes = [vp]
+    L.inim_regularize_graph.argtypes = [vp, i64, i32, i32, pp, vp, sz, vp, vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("inim_default_params", "inim_strerror", "inim_last_error"):
@@ -250,6 +254,38 @@ def regularize_timed(xy: torch.Tensor, res: int, iters: int, radius: int = 8, si
     _check(lib().inim_regularize_timed(_ptr(xy), n, res, iters, ctypes.byref(p), _ptr(ws), ws.numel(),
                                        _stream(xy), ms))
     return dict(zip(STAGES, list(ms)))
+
+
+class Graph:
+    """Handle of inim_regularize_graph: replays one captured regularisation."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(lib().inim_graph_create(ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().inim_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def regularize_graph(xy: torch.Tensor, res: int, iters: int, graph: Graph, ws: torch.Tensor, radius: int = 8,
+                     sigma=None, d0=None, check: bool = False) -> torch.Tensor:
+    """regularize through a captured HIP graph (same results)."""
+    n = _xy(xy)
+    p = params(radius, sigma, d0)
+    _check(lib().inim_regularize_graph(_ptr(xy), n, res, iters, ctypes.byref(p), _ptr(ws), ws.numel(),
+                                       graph.handle, _stream(xy)))
+    if check:
+        _check(sync_status(ws))
+    return xy
 
 
 def sync_status(ws: torch.Tensor) -> int:

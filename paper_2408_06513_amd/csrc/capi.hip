@@ -82,14 +82,15 @@ constexpr size_t kStatusBytes = 256;
 
 // Workspace of rasterize / advect / regularize.
 struct RegLayout {
-    size_t status, counts[2], density, field, scratch, total;
+    size_t status, counts[2], density, field, scratch, sxy, perm, rank, partial, total;
     Geom g;
     bool f32;  // integral images of the float density in double (radius > 0), or of the counts
 };
 
-RegLayout reg_layout(int32_t res, int radius) {
+RegLayout reg_layout(int32_t res, int64_t n, int radius) {
     RegLayout L;
     const size_t NN = (size_t)res * (size_t)res;
+    const size_t nn = n > 0 ? (size_t)n : 0;
     L.f32 = radius > 0;
     L.g = make_geom(res, L.f32 ? 8 : 4);
     size_t o = 0;
@@ -99,6 +100,10 @@ RegLayout reg_layout(int32_t res, int radius) {
     L.density = o; o += align256(NN * 4);
     L.field = o; o += align256(NN * 8);
     L.scratch = o; o += inim_scratch_bytes(L.g, L.f32 ? 8 : 4);
+    L.sxy = o; o += align256(nn * 8);
+    L.perm = o; o += align256(nn * 4);
+    L.rank = o; o += align256(nn * 4);
+    L.partial = o; o += align256(scan_partials(NN) * 4);
     L.total = o;
     return L;
 }
@@ -124,23 +129,30 @@ struct StageEvents {
     hipEvent_t it[5];
 };
 
-// The whole call (Sec. 4.3) on the caller's stream.  Iteration k reads the
-// count raster counts[k % 2]; its advection splats the moved samples into
-// counts[(k+1) % 2], which the smoothing of iteration k has zeroed.
+// The whole call (Sec. 4.3) on the caller's stream.  The samples are first
+// sorted by texel into the workspace (so that the splats of a wave mostly hit
+// the same few texels and the field gathers are local), the iterations run on
+// that copy, and the results are scattered back to the caller's order.
+// Iteration k reads the count raster counts[k % 2]; its advection splats the
+// moved samples into counts[(k+1) % 2], which the smoothing of iteration k has
+// zeroed.
 int enqueue_regularize(float* xy, int64_t n, int32_t res, int32_t iters, double d0, const BlurTaps& taps,
                        const RegLayout& L, char* ws, hipStream_t st, StageEvents* ev, double* stage_ms) {
     int* status = reinterpret_cast<int*>(ws + L.status);
     uint32_t* counts[2] = {reinterpret_cast<uint32_t*>(ws + L.counts[0]), reinterpret_cast<uint32_t*>(ws + L.counts[1])};
     float* density = reinterpret_cast<float*>(ws + L.density);
     float2* field = reinterpret_cast<float2*>(ws + L.field);
-    float2* pts = reinterpret_cast<float2*>(xy);
+    float2* pts = reinterpret_cast<float2*>(ws + L.sxy);
+    uint32_t* perm = reinterpret_cast<uint32_t*>(ws + L.perm);
     void* scratch = ws + L.scratch;
     const size_t NN = (size_t)res * res;
     const bool fused = L.f32 && blur_aggregate_fits(L.g);
     hipError_t e;
     if (ev) (void)hipEventRecord(ev->pre[0], st);
-    if ((e = launch_fill(counts[0], NN, status, true, st)) != hipSuccess) return hip_fail(e, "fill");
-    if ((e = launch_splat(pts, n, res, counts[0], status, st)) != hipSuccess) return hip_fail(e, "splat");
+    e = launch_sort_by_texel(reinterpret_cast<const float2*>(xy), n, res, counts[0],
+                             reinterpret_cast<uint32_t*>(ws + L.rank), counts[1],
+                             reinterpret_cast<uint32_t*>(ws + L.partial), pts, perm, status, st);
+    if (e != hipSuccess) return hip_fail(e, "sort by texel");
     if (ev) {
         (void)hipEventRecord(ev->pre[1], st);
         if (hipEventSynchronize(ev->pre[1]) != hipSuccess) return fail(INIM_EHIP, "hipEventSynchronize failed");
@@ -185,6 +197,16 @@ int enqueue_regularize(float* xy, int64_t n, int32_t res, int32_t iters, double 
             }
         }
     }
+    if (ev) (void)hipEventRecord(ev->pre[0], st);
+    if ((e = launch_unpermute(pts, perm, n, reinterpret_cast<float2*>(xy), status, st)) != hipSuccess)
+        return hip_fail(e, "unpermute");
+    if (ev) {
+        (void)hipEventRecord(ev->pre[1], st);
+        if (hipEventSynchronize(ev->pre[1]) != hipSuccess) return fail(INIM_EHIP, "hipEventSynchronize failed");
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, ev->pre[0], ev->pre[1]);
+        stage_ms[0] += ms;
+    }
     return INIM_OK;
 }
 
@@ -196,7 +218,7 @@ int regularize_impl(float* xy, int64_t n, int32_t res, int32_t iters, const inim
     if (iters < 0) return fail(INIM_EINVAL, "iters=%d is negative", (int)iters);
     Params P;
     if ((s = resolve_params(p, P)) != INIM_OK) return s;
-    const RegLayout L = reg_layout(res, P.radius);
+    const RegLayout L = reg_layout(res, n, P.radius);
     if ((s = check_ws(ws, ws_bytes, L.total)) != INIM_OK) return s;
     if (n == 0 || iters == 0) {
         // nothing to do, but the call still resets the status word it reports
@@ -208,13 +230,16 @@ int regularize_impl(float* xy, int64_t n, int32_t res, int32_t iters, const inim
     if (stage_ms == nullptr) return enqueue_regularize(xy, n, res, iters, d0, taps, L, (char*)ws, stream, nullptr, nullptr);
 
     StageEvents ev;
-    hipEvent_t* all[7] = {&ev.pre[0], &ev.pre[1], &ev.it[0], &ev.it[1], &ev.it[2], &ev.it[3], &ev.it[4]};
+    hipEvent_t t0, t1;
+    hipEvent_t* all[9] = {&ev.pre[0], &ev.pre[1], &ev.it[0], &ev.it[1], &ev.it[2], &ev.it[3], &ev.it[4], &t0, &t1};
     for (auto* h : all)
         if (hipEventCreate(h) != hipSuccess) return fail(INIM_EHIP, "hipEventCreate failed");
+    (void)hipEventRecord(t0, stream);
     s = enqueue_regularize(xy, n, res, iters, d0, taps, L, (char*)ws, stream, &ev, stage_ms);
-    if (s == INIM_OK) {
+    (void)hipEventRecord(t1, stream);
+    if (s == INIM_OK && hipEventSynchronize(t1) == hipSuccess) {
         float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, ev.pre[0], ev.it[4]);
+        (void)hipEventElapsedTime(&ms, t0, t1);
         stage_ms[5] += ms;
     }
     for (auto* h : all) (void)hipEventDestroy(*h);
@@ -253,7 +278,7 @@ int inim_workspace_size(int32_t res, int64_t n, const inim_params* p, size_t* by
     if (n < 0) return fail(INIM_EINVAL, "n=%lld is negative", (long long)n);
     Params P;
     if ((s = resolve_params(p, P)) != INIM_OK) return s;
-    *bytes = reg_layout(res, P.radius).total;
+    *bytes = reg_layout(res, n, P.radius).total;
     return INIM_OK;
 }
 
@@ -365,6 +390,87 @@ int inim_regularize_timed(float* xy, int64_t n, int32_t res, int32_t iters, cons
                           size_t ws_bytes, hipStream_t stream, double* stage_ms) {
     if (stage_ms == nullptr) return fail(INIM_EINVAL, "stage_ms is NULL");
     return regularize_impl(xy, n, res, iters, p, ws, ws_bytes, stream, stage_ms);
+}
+
+struct inim_graph_cache {
+    bool valid = false;
+    float* xy = nullptr;
+    int64_t n = 0;
+    int32_t res = 0, iters = 0;
+    Params P{};
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    void drop() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        valid = false;
+    }
+};
+
+int inim_graph_create(void** graph) {
+    if (graph == nullptr) return fail(INIM_EINVAL, "graph is NULL");
+    *graph = new inim_graph_cache();
+    return INIM_OK;
+}
+
+int inim_graph_destroy(void* graph) {
+    auto* G = static_cast<inim_graph_cache*>(graph);
+    if (G == nullptr) return INIM_OK;
+    G->drop();
+    if (G->capture) (void)hipStreamDestroy(G->capture);
+    delete G;
+    return INIM_OK;
+}
+
+int inim_regularize_graph(float* xy, int64_t n, int32_t res, int32_t iters, const inim_params* p, void* ws,
+                          size_t ws_bytes, void* graph, hipStream_t stream) {
+    auto* G = static_cast<inim_graph_cache*>(graph);
+    if (G == nullptr) return fail(INIM_EINVAL, "graph is NULL");
+    int s;
+    if ((s = check_res(res)) != INIM_OK) return s;
+    if ((s = check_xy(xy, n)) != INIM_OK) return s;
+    if (iters < 0) return fail(INIM_EINVAL, "iters=%d is negative", (int)iters);
+    Params P;
+    if ((s = resolve_params(p, P)) != INIM_OK) return s;
+    const RegLayout L = reg_layout(res, n, P.radius);
+    if ((s = check_ws(ws, ws_bytes, L.total)) != INIM_OK) return s;
+    if (n == 0 || iters == 0) return regularize_impl(xy, n, res, iters, p, ws, ws_bytes, stream, nullptr);
+    const bool same = G->valid && G->xy == xy && G->n == n && G->res == res && G->iters == iters &&
+                      G->P.radius == P.radius && G->P.sigma == P.sigma && G->P.d0 == P.d0 && G->ws == ws &&
+                      G->ws_bytes == ws_bytes;
+    if (!same) {
+        G->drop();
+        if (G->capture == nullptr && hipStreamCreateWithFlags(&G->capture, hipStreamNonBlocking) != hipSuccess)
+            return fail(INIM_EHIP, "hipStreamCreate failed");
+        const double d0 = P.d0 < 0.0 ? (double)n / ((double)res * (double)res) : P.d0;
+        const BlurTaps taps = make_taps(P.radius, P.sigma);
+        hipError_t e = hipStreamBeginCapture(G->capture, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        s = enqueue_regularize(xy, n, res, iters, d0, taps, L, (char*)ws, G->capture, nullptr, nullptr);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(G->capture, &g);
+        if (s != INIM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        G->graph = g;
+        e = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            G->drop();
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        G->valid = true;
+        G->xy = xy; G->n = n; G->res = res; G->iters = iters; G->P = P; G->ws = ws; G->ws_bytes = ws_bytes;
+    }
+    hipError_t e = hipGraphLaunch(G->exec, stream);
+    return e == hipSuccess ? INIM_OK : hip_fail(e, "hipGraphLaunch");
 }
 
 int inim_sync_status(void* ws, hipStream_t stream) {

@@ -84,30 +84,178 @@ __device__ __forceinline__ void cell_of(float x, int N, int& k0, double& f) {
 
 __device__ __forceinline__ float clamp01(double v) { return (float)(v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v)); }
 
+// Adds 1 at `key` for every lane holding a key below 0xFFFFFFFF: the 64 keys of
+// the wave are sorted (bitonic network over lane shuffles) and only the first
+// lane of every run of equal keys issues one atomic with the run length.  With
+// samples in texel order most lanes of a wave share a few texels.
+__device__ __forceinline__ void wave_count(uint32_t* __restrict__ counts, uint32_t key) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t o = (uint32_t)__shfl_xor((int)key, j, 64);
+            const bool keep_min = ((lane & k) == 0) == ((lane & j) == 0);
+            key = keep_min ? min(key, o) : max(key, o);
+        }
+    }
+    const uint32_t prev = (uint32_t)__shfl_up((int)key, 1, 64);
+    const bool head = lane == 0 || prev != key;
+    const unsigned long long heads = __ballot(head);
+    if (head && key != 0xFFFFFFFFu) {
+        const unsigned long long rest = lane == 63 ? 0ull : heads >> (lane + 1);
+        const int next = rest ? lane + __ffsll((long long)rest) : 64;
+        __hip_atomic_fetch_add(counts + key, (uint32_t)(next - lane), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // counts_next (optional): each moved sample is also splatted into it, the
 // count raster of the next iteration (Sec. 4.3, step 1 of the next round).
+// Every wave runs the same number of loop trips so that wave_count sees all
+// 64 lanes.
 __global__ __launch_bounds__(256) void k_advect(const float2* __restrict__ field, int N, float2* __restrict__ xy,
                                                 int64_t n, uint32_t* __restrict__ counts_next, const int* status) {
     if (failed(status)) return;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
+    for (int64_t base = first; base < n; base += stride) {
+        const int64_t p = base + lane_id();
+        uint32_t key = 0xFFFFFFFFu;
+        if (p < n) {
+            const float2 q = xy[p];
+            int i0, j0;
+            double fx, fy;
+            cell_of(q.x, N, i0, fx);
+            cell_of(q.y, N, j0, fy);
+            const float2* r0 = field + (size_t)j0 * N + i0;
+            const float2* r1 = r0 + N;
+            const float2 a = r0[0], b = r0[1], c = r1[0], d = r1[1];
+            const double w00 = (1.0 - fx) * (1.0 - fy), w10 = fx * (1.0 - fy), w01 = (1.0 - fx) * fy, w11 = fx * fy;
+            const double nx = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
+            const double ny = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
+            const float2 o = make_float2(clamp01(nx), clamp01(ny));
+            xy[p] = o;
+            key = (uint32_t)(texel_of(o.y, N) * N + texel_of(o.x, N));
+        }
+        if (counts_next != nullptr) wave_count(counts_next, key);
+    }
+}
+
+// ------------------------------------------------------------------ texel order
+// Splat that also returns each sample's rank among the samples of its texel
+// (the value of the count before its own increment); flags invalid samples.
+__global__ __launch_bounds__(256) void k_splat_rank(const float2* __restrict__ xy, int64_t n, int N,
+                                                    uint32_t* __restrict__ counts, uint32_t* __restrict__ rank,
+                                                    int* status) {
+    if (failed(status)) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
         const float2 q = xy[p];
-        int i0, j0;
-        double fx, fy;
-        cell_of(q.x, N, i0, fx);
-        cell_of(q.y, N, j0, fy);
-        const float2* r0 = field + (size_t)j0 * N + i0;
-        const float2* r1 = r0 + N;
-        const float2 a = r0[0], b = r0[1], c = r1[0], d = r1[1];
-        const double w00 = (1.0 - fx) * (1.0 - fy), w10 = fx * (1.0 - fy), w01 = (1.0 - fx) * fy, w11 = fx * fy;
-        const double nx = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
-        const double ny = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
-        const float2 o = make_float2(clamp01(nx), clamp01(ny));
-        xy[p] = o;
-        if (counts_next != nullptr)
-            __hip_atomic_fetch_add(counts_next + (size_t)texel_of(o.y, N) * N + texel_of(o.x, N), 1u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (!in_unit_square(q)) {
+            flag_domain(status);
+            continue;
+        }
+        const int i = texel_of(q.x, N), j = texel_of(q.y, N);
+        rank[p] = __hip_atomic_fetch_add(counts + (size_t)j * N + i, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+// Exclusive prefix of a uint32 array in three passes: per-block sums, a scan
+// of the block sums by one block, and the scan within each block.
+constexpr int kScanThreads = 1024, kScanItems = 16, kScanBlock = kScanThreads * kScanItems;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds_wave, uint32_t& total) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t incl = wave_inclusive_scan(v);
+    if (lane == 63) lds_wave[wave] = incl;
+    __syncthreads();
+    if (wave == 0) {
+        const uint32_t t = lane < nw ? lds_wave[lane] : 0u;
+        const uint32_t ti = wave_inclusive_scan(t);
+        if (lane < nw) lds_wave[lane] = ti - t;
+        if (lane == nw - 1) lds_wave[32] = ti;
+    }
+    __syncthreads();
+    total = lds_wave[32];
+    return lds_wave[wave] + incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ a, size_t m,
+                                                              uint32_t* __restrict__ partial, const int* status) {
+    __shared__ uint32_t lw[33];
+    if (failed(status)) return;
+    const size_t base = (size_t)blockIdx.x * kScanBlock + (size_t)threadIdx.x * kScanItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < m) s += a[base + k];
+    uint32_t total;
+    (void)block_exclusive_scan(s, lw, total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t* __restrict__ partial, int nb,
+                                                                const int* status) {
+    __shared__ uint32_t lw[33];
+    if (failed(status)) return;
+    const int per = (nb + kScanThreads - 1) / kScanThreads;
+    const int b0 = threadIdx.x * per;
+    uint32_t s = 0;
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < nb) s += partial[b0 + k];
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(s, lw, total);
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < nb) {
+            const uint32_t v = partial[b0 + k];
+            partial[b0 + k] = run;
+            run += v;
+        }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ a, size_t m,
+                                                            const uint32_t* __restrict__ partial,
+                                                            uint32_t* __restrict__ out, const int* status) {
+    __shared__ uint32_t lw[33];
+    if (failed(status)) return;
+    const size_t base = (size_t)blockIdx.x * kScanBlock + (size_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems], s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < m ? a[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t total;
+    uint32_t run = partial[blockIdx.x] + block_exclusive_scan(s, lw, total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < m) {
+            out[base + k] = run;
+            run += v[k];
+        }
+}
+
+// Moves every sample to slot offset[texel] + rank: texel (row-major) order.
+__global__ __launch_bounds__(256) void k_scatter_sorted(const float2* __restrict__ xy, int64_t n, int N,
+                                                        const uint32_t* __restrict__ rank,
+                                                        const uint32_t* __restrict__ offset, float2* __restrict__ sxy,
+                                                        uint32_t* __restrict__ perm, const int* status) {
+    if (failed(status)) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        const float2 q = xy[p];
+        const int i = texel_of(q.x, N), j = texel_of(q.y, N);
+        const uint32_t slot = offset[(size_t)j * N + i] + rank[p];
+        sxy[slot] = q;
+        perm[slot] = (uint32_t)p;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_unpermute(const float2* __restrict__ sxy, const uint32_t* __restrict__ perm,
+                                                   int64_t n, float2* __restrict__ xy, const int* status) {
+    if (failed(status)) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) xy[perm[q]] = sxy[q];
 }
 
 // ------------------------------------------------------------------ launchers
@@ -144,6 +292,33 @@ hipError_t launch_blur(const uint32_t* counts, float* out, int N, const BlurTaps
 hipError_t launch_advect(const float2* field, int N, float2* xy, int64_t n, uint32_t* counts_next, const int* status,
                          hipStream_t st) {
     hipLaunchKernelGGL(k_advect, dim3(grid_for(n)), dim3(256), 0, st, field, N, xy, n, counts_next, status);
+    return hipGetLastError();
+}
+
+}  // namespace inim
+
+namespace inim {
+
+size_t scan_partials(size_t m) { return (m + kScanBlock - 1) / kScanBlock; }
+
+hipError_t launch_sort_by_texel(const float2* xy, int64_t n, int N, uint32_t* counts, uint32_t* rank,
+                                uint32_t* offsets, uint32_t* partial, float2* sxy, uint32_t* perm, int* status,
+                                hipStream_t st) {
+    const size_t m = (size_t)N * N;
+    const int nb = (int)scan_partials(m);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)(m / 4 + 1), 256, 2048)), dim3(256), 0, st, counts, m, status, 1);
+    hipLaunchKernelGGL(k_splat_rank, dim3(grid_for(n)), dim3(256), 0, st, xy, n, N, counts, rank, status);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, counts, m, partial, status);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, partial, nb, status);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, st, counts, m, partial, offsets, status);
+    hipLaunchKernelGGL(k_scatter_sorted, dim3(grid_for(n)), dim3(256), 0, st, xy, n, N, rank, offsets, sxy, perm,
+                       status);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpermute(const float2* sxy, const uint32_t* perm, int64_t n, float2* xy, const int* status,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_unpermute, dim3(grid_for(n)), dim3(256), 0, st, sxy, perm, n, xy, status);
     return hipGetLastError();
 }
 

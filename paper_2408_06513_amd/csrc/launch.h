@@ -40,6 +40,19 @@ hipError_t launch_splat(const float2* xy, int64_t n, int N, uint32_t* counts, in
 hipError_t launch_blur(const uint32_t* counts, float* out, int N, const BlurTaps& taps, const int* status,
                        hipStream_t st);
 hipError_t launch_validate(const float2* xy, int64_t n, int* status, hipStream_t st);
+
+// Counting sort of the samples by texel (row-major): clears `counts` and the
+// status word, splats with ranks (flagging invalid samples), scans the counts
+// into `offsets` (using `partial`, scan_partials(N*N) words), and writes the
+// samples in texel order to sxy with perm[slot] = original index.  `counts`
+// keeps the texel counts of the input.
+size_t scan_partials(size_t m);
+hipError_t launch_sort_by_texel(const float2* xy, int64_t n, int N, uint32_t* counts, uint32_t* rank,
+                                uint32_t* offsets, uint32_t* partial, float2* sxy, uint32_t* perm, int* status,
+                                hipStream_t st);
+// xy[perm[q]] = sxy[q]
+hipError_t launch_unpermute(const float2* sxy, const uint32_t* perm, int64_t n, float2* xy, const int* status,
+                            hipStream_t st);
 // counts_next != nullptr: also splat the moved samples into it (must be zero).
 hipError_t launch_advect(const float2* field, int N, float2* xy, int64_t n, uint32_t* counts_next, const int* status,
                          hipStream_t st);

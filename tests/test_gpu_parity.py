@@ -313,3 +313,28 @@ def test_host_errors_with_device_buffers(capi, dev):
     img = torch.zeros((64, 64), dtype=torch.float32, device=dev)
     with pytest.raises(capi.InvalidArgument):
         capi.inim(img, 0x100)
+
+
+def test_graph_replay_matches_eager(capi, dev):
+    """The captured graph gives the eager result on every replay, with eager
+    work and synchronisations between replays; changed arguments re-capture."""
+    xy0 = dg.plain_small(7)
+    res, iters = 256, 3
+    eager = gpu_regularize(capi, dev, xy0, res, iters)
+    g = capi.Graph()
+    buf = to_dev(xy0, dev)
+    ws = capi.workspace(capi.workspace_size(res, xy0.shape[0]), dev)
+    for rep in range(4):
+        buf.copy_(to_dev(xy0, dev))
+        capi.regularize_graph(buf, res, iters, g, ws)
+        torch.cuda.synchronize()
+        assert capi.sync_status(ws) == capi.OK
+        assert np.array_equal(buf.cpu().numpy(), eager), rep
+        # unrelated eager work between replays
+        other = gpu_regularize(capi, dev, xy0[:5000], 64, 1)
+        assert other.shape == (5000, 2)
+    buf.copy_(to_dev(xy0, dev))
+    capi.regularize_graph(buf, res, iters + 1, g, ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(buf.cpu().numpy(), gpu_regularize(capi, dev, xy0, res, iters + 1))
+    g.close()
