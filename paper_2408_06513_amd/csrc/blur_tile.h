@@ -12,8 +12,14 @@ namespace inim {
 
 constexpr int kBX = 64, kBY = 16;
 
-// Half-sample symmetric continuation: index -1-t reads t, N+t reads N-1-t.
+// Half-sample symmetric continuation: index -1-t reads t, N+t reads N-1-t
+// (period 2N).  Indices within one raster width of the border are reflected
+// with compares only; the modulo is needed only when the kernel is wider
+// than the raster.
 __device__ __forceinline__ int mirror(int k, int N) {
+    if (k >= 0 && k < N) return k;
+    if (k < 0 && k >= -N) return -1 - k;
+    if (k >= N && k < 2 * N) return 2 * N - 1 - k;
     const int P = 2 * N;
     int m = k % P;
     if (m < 0) m += P;

@@ -82,7 +82,7 @@ constexpr size_t kStatusBytes = 256;
 
 // Workspace of rasterize / advect / regularize.
 struct RegLayout {
-    size_t status, counts[2], density, field, scratch, sxy, perm, rank, partial, total;
+    size_t status, counts[2], density, field, defect, scratch, sxy, perm, rank, partial, total;
     Geom g;
     bool f32;  // integral images of the float density in double (radius > 0), or of the counts
 };
@@ -99,6 +99,7 @@ RegLayout reg_layout(int32_t res, int64_t n, int radius) {
     L.counts[1] = o; o += align256(NN * 4);
     L.density = o; o += align256(NN * 4);
     L.field = o; o += align256(NN * 8);
+    L.defect = o; o += align256(NN * 8);
     L.scratch = o; o += inim_scratch_bytes(L.g, L.f32 ? 8 : 4);
     L.sxy = o; o += align256(nn * 8);
     L.perm = o; o += align256(nn * 4);
@@ -153,6 +154,8 @@ int enqueue_regularize(float* xy, int64_t n, int32_t res, int32_t iters, double 
                              reinterpret_cast<uint32_t*>(ws + L.rank), counts[1],
                              reinterpret_cast<uint32_t*>(ws + L.partial), pts, perm, status, st);
     if (e != hipSuccess) return hip_fail(e, "sort by texel");
+    float2* defect = reinterpret_cast<float2*>(ws + L.defect);
+    if ((e = launch_defect_field(res, defect, st)) != hipSuccess) return hip_fail(e, "defect field");
     if (ev) {
         (void)hipEventRecord(ev->pre[1], st);
         if (hipEventSynchronize(ev->pre[1]) != hipSuccess) return fail(INIM_EHIP, "hipEventSynchronize failed");
@@ -180,9 +183,11 @@ int enqueue_regularize(float* xy, int64_t n, int32_t res, int32_t iters, double 
         if (e != hipSuccess) return hip_fail(e, "integral-image scans");
         if (ev) (void)hipEventRecord(ev->it[2], st);
         if (L.f32)
-            e = launch_inim_final<float, double>(density, L.g, scratch, 0u, nullptr, field, d0, nullptr, status, st);
+            e = launch_inim_final<float, double>(density, L.g, scratch, 0u, nullptr, field, defect, d0, nullptr, status,
+                                                 st);
         else
-            e = launch_inim_final<uint32_t, uint32_t>(cur, L.g, scratch, 0u, nullptr, field, d0, nullptr, status, st);
+            e = launch_inim_final<uint32_t, uint32_t>(cur, L.g, scratch, 0u, nullptr, field, defect, d0, nullptr,
+                                                      status, st);
         if (e == hipSuccess && !L.f32 && nxt) e = launch_fill(nxt, NN, status, false, st);
         if (e != hipSuccess) return hip_fail(e, "integral images + deformation");
         if (ev) (void)hipEventRecord(ev->it[3], st);
@@ -333,7 +338,8 @@ int inim_inim_u32(const uint32_t* img, int32_t res, uint32_t mask, uint32_t* pla
     const Geom g = make_geom(res, 4);
     void* scratch = (char*)ws + kStatusBytes;
     hipError_t e = launch_inim_carries<uint32_t, uint32_t>(img, g, scratch, nullptr, stream);
-    if (e == hipSuccess) e = launch_inim_final<uint32_t, uint32_t>(img, g, scratch, mask, planes, nullptr, 0.0, marg, nullptr, stream);
+    if (e == hipSuccess) e = launch_inim_final<uint32_t, uint32_t>(img, g, scratch, mask, planes, nullptr, nullptr, 0.0, marg, nullptr,
+                                                                stream);
     return e == hipSuccess ? INIM_OK : hip_fail(e, "integral images");
 }
 
@@ -345,7 +351,8 @@ int inim_inim_f32(const float* img, int32_t res, uint32_t mask, float* planes, d
     const Geom g = make_geom(res, 16);
     void* scratch = (char*)ws + kStatusBytes;
     hipError_t e = launch_inim_carries<float, u128>(img, g, scratch, nullptr, stream);
-    if (e == hipSuccess) e = launch_inim_final<float, u128>(img, g, scratch, mask, planes, nullptr, 0.0, marg, nullptr, stream);
+    if (e == hipSuccess) e = launch_inim_final<float, u128>(img, g, scratch, mask, planes, nullptr, nullptr, 0.0, marg, nullptr,
+                                                         stream);
     return e == hipSuccess ? INIM_OK : hip_fail(e, "integral images");
 }
 

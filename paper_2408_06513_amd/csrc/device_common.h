@@ -239,16 +239,21 @@ __device__ __forceinline__ void map_sum(const Planes8& P, double x, double y, do
 
 // Scale factors of the deformation: 1 / (2 C_d) with C_d = C_r + d0 res^2 the
 // total of d = d_r + d0, and 1 / (2 res^2) for the constant raster.
+// omk = 1 - d0 res^2 / C_d, the weight of the defect once the constant part of
+// d is folded in (see deform_texel_defect).
 struct MapScale {
-    double d0, inv2Cd, inv2NN;
+    double d0, inv2Cd, inv2NN, omk, invN;
 };
 
 __device__ __forceinline__ MapScale map_scale(double Cr, int N, double d0) {
     const double NN = (double)N * (double)N;
+    const double Cd = Cr + d0 * NN;
     MapScale s;
     s.d0 = d0;
-    s.inv2Cd = 1.0 / (2.0 * (Cr + d0 * NN));
+    s.inv2Cd = 1.0 / (2.0 * Cd);
     s.inv2NN = 1.0 / (2.0 * NN);
+    s.omk = Cr / Cd;
+    s.invN = 1.0 / (double)N;
     return s;
 }
 
@@ -268,6 +273,19 @@ __device__ __forceinline__ float2 deform_texel(const Planes8& R, const MapScale&
     map_sum(O, x, y, s1x, s1y);
     const double tx = sdx * ms.inv2Cd - s1x * ms.inv2NN;
     const double ty = sdy * ms.inv2Cd - s1y * ms.inv2NN;
+    return make_float2((float)(x + tx), (float)(y + ty));
+}
+
+// The same deformation with the defect field t1 = t(p; 1) precomputed: the map
+// is linear in the planes, S(d) = S(d_r) + d0 S(1) and 2 C_d t(p; d0) / (2 C_d)
+// = t1, so T = p + S(d_r) / (2 C_d) - (1 - d0 res^2 / C_d) t1.
+__device__ __forceinline__ float2 deform_texel_defect(const Planes8& R, const MapScale& ms, int i, int j, float2 t1) {
+    const double x = ((double)i + 0.5) * ms.invN;
+    const double y = ((double)j + 0.5) * ms.invN;
+    double sx, sy;
+    map_sum(R, x, y, sx, sy);
+    const double tx = sx * ms.inv2Cd - ms.omk * (double)t1.x;
+    const double ty = sy * ms.inv2Cd - ms.omk * (double)t1.y;
     return make_float2((float)(x + tx), (float)(y + ty));
 }
 

@@ -65,7 +65,7 @@ inline Geom make_geom(int N, int acc_bytes = 4, int q_hint = 0, int h_hint = 0) 
         H = 64;
     } else {
         Q = acc_bytes > 4 ? 2 : 4;
-        H = 128;
+        H = N / 128 > 64 ? N / 128 : 64;  // 64-row bands, at most 128 of them
     }
     if (q_hint > 0) Q = q_hint > 4 ? 4 : q_hint;
     if (h_hint > 0) H = h_hint;

@@ -30,7 +30,6 @@
 namespace inim {
 
 constexpr int kWavesPerBlock = 4;
-constexpr int kPF = 4;  // rows prefetched ahead
 
 template <typename Tin, int Q>
 __device__ __forceinline__ void load_tile_row(const Tin* __restrict__ p, bool act, Tin (&v)[Q]) {
@@ -49,15 +48,18 @@ __device__ __forceinline__ void load_tile_row(const Tin* __restrict__ p, bool ac
 template <int Q, typename Acc>
 struct TileAgg {
     Acc cp[Q], L[Q], R[Q];
+    // per-row outputs parked in lane r % 64, slot r / 64 (H <= 128)
+    Acc pk_row[2], pk_le[2], pk_re[2];
 
     __device__ __forceinline__ void init() {
 #pragma unroll
         for (int e = 0; e < Q; ++e) cp[e] = L[e] = R[e] = Acc(0);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) pk_row[k] = pk_le[k] = pk_re[k] = Acc(0);
     }
 
     template <typename Tin>
-    __device__ __forceinline__ void step(const Tin (&v)[Q], int r, int lane, int lastLane, const Agg<Acc>& A,
-                                         size_t ebase) {
+    __device__ __forceinline__ void step(const Tin (&v)[Q], int r, int lane, int lastLane) {
 #pragma unroll
         for (int e = 0; e < Q; ++e) cp[e] += to_acc<Acc, Tin>(v[e]);
         Acc upL = shfl_up1(L[Q - 1]);
@@ -74,15 +76,25 @@ struct TileAgg {
 #pragma unroll
         for (int e = 0; e < Q; ++e) s += cp[e];
         s = wave_sum(s);
-        if (lane == 0) {
-            A.trow[ebase + r] = s;
-            A.tRedge[ebase + r] = R[0];
+        const Acc le = bcast(L[Q - 1], lastLane), re = bcast(R[0], 0);
+        if (lane == (r & 63)) {
+            if (r < 64) { pk_row[0] = s; pk_le[0] = le; pk_re[0] = re; }
+            else        { pk_row[1] = s; pk_le[1] = le; pk_re[1] = re; }
         }
-        if (lane == lastLane) A.tLedge[ebase + r] = L[Q - 1];
     }
 
-    // band-level outputs: column sums, their in-tile prefix, diagonal sums
-    __device__ __forceinline__ void finish(int lane, bool act, const Agg<Acc>& A, size_t o) {
+    // per-row edge sums and row sums of the tile, then the band-level outputs:
+    // column sums, their in-tile prefix, diagonal sums
+    __device__ __forceinline__ void finish(int lane, bool act, int H, const Agg<Acc>& A, size_t ebase, size_t o) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int r = lane + 64 * k;
+            if (r < H) {
+                A.trow[ebase + r] = pk_row[k];
+                A.tLedge[ebase + r] = pk_le[k];
+                A.tRedge[ebase + r] = pk_re[k];
+            }
+        }
         Acc pre[Q];
         Acc run = Acc(0);
 #pragma unroll
@@ -102,6 +114,10 @@ struct TileAgg {
     }
 };
 
+// Rows prefetched ahead: deeper for 16-byte rows per lane.
+template <int Q, typename Tin>
+constexpr int prefetch_rows() { return Q * sizeof(Tin) >= 16 ? 8 : 4; }
+
 template <int Q, typename Tin, typename Acc>
 __global__ __launch_bounds__(256) void k_inim_aggregate(const Tin* __restrict__ img, Geom g, Agg<Acc> A,
                                                         const int* status) {
@@ -119,25 +135,26 @@ __global__ __launch_bounds__(256) void k_inim_aggregate(const Tin* __restrict__ 
 
     TileAgg<Q, Acc> st;
     st.init();
-    Tin buf[kPF][Q];
+    constexpr int PF = prefetch_rows<Q, Tin>();
+    Tin buf[PF][Q];
 #pragma unroll
-    for (int p = 0; p < kPF; ++p)
+    for (int p = 0; p < PF; ++p)
         if (p < g.H) load_tile_row<Tin, Q>(src + (size_t)p * N, act, buf[p]);
 
-    for (int r0 = 0; r0 < g.H; r0 += kPF) {
+    for (int r0 = 0; r0 < g.H; r0 += PF) {
 #pragma unroll
-        for (int p = 0; p < kPF; ++p) {
+        for (int p = 0; p < PF; ++p) {
             const int r = r0 + p;
             if (r < g.H) {
                 Tin v[Q];
 #pragma unroll
                 for (int e = 0; e < Q; ++e) v[e] = buf[p][e];
-                if (r + kPF < g.H) load_tile_row<Tin, Q>(src + (size_t)(r + kPF) * N, act, buf[p]);
-                st.step(v, r, lane, g.lastLane, A, ebase);
+                if (r + PF < g.H) load_tile_row<Tin, Q>(src + (size_t)(r + PF) * N, act, buf[p]);
+                st.step(v, r, lane, g.lastLane);
             }
         }
     }
-    st.finish(lane, act, A, (size_t)b * N + col);
+    st.finish(lane, act, g.H, A, ebase, (size_t)b * N + col);
 }
 
 // Blur fused with pass 1 for 64 x 16 tiles (g.W == 64, g.H == 16, N >= 64):
@@ -161,18 +178,43 @@ __global__ __launch_bounds__(256) void k_blur_aggregate(const uint32_t* __restri
         if (zero_next != nullptr) zero_next[k] = 0u;
     });
     __syncthreads();
-    if (threadIdx.x >= 64) return;
-    const int lane = lane_id();
+    const int lane = lane_id(), wave = (int)(threadIdx.x >> 6);
     const int b = blockIdx.y, c = blockIdx.x;
     const size_t ebase = ((size_t)b * g.T + c) * g.H;
-    TileAgg<1, Acc> st;
-    st.init();
-#pragma unroll 4
-    for (int r = 0; r < kBY; ++r) {
-        const float v[1] = {tile[r][lane]};
-        st.step(v, r, lane, 63, A, ebase);
+    if (wave == 0) {
+        // column prefixes and the two diagonal sums, row by row; the edge values
+        // of row r are parked in lane r and stored once at the end
+        Acc cp = Acc(0), L = Acc(0), R = Acc(0), eL = Acc(0), eR = Acc(0);
+#pragma unroll
+        for (int r = 0; r < kBY; ++r) {
+            cp += (Acc)tile[r][lane];
+            Acc upL = shfl_up1(L), dnR = shfl_down1(R);
+            if (lane == 0) upL = Acc(0);
+            if (lane == 63) dnR = Acc(0);
+            L = cp + upL;
+            R = cp + dnR;
+            const Acc l63 = bcast(L, 63), r0 = bcast(R, 0);
+            if (lane == r) { eL = l63; eR = r0; }
+        }
+        if (lane < kBY) {
+            A.tLedge[ebase + lane] = eL;
+            A.tRedge[ebase + lane] = eR;
+        }
+        const Acc incl = wave_inclusive_scan(cp);
+        const size_t o = (size_t)b * N + ox + lane;
+        A.colsum[o] = cp;
+        A.tcsp[o] = incl;
+        A.tLend[o] = L;
+        A.tRend[o] = R;
+    } else if (wave == 1) {
+        // trow(r) = sum over the tile of the band-local column prefix at row r,
+        // i.e. the prefix over rows of the tile's row sums
+        Acc rs = Acc(0);
+        if (lane < kBY)
+            for (int x = 0; x < kBX; ++x) rs += (Acc)tile[lane][(x + lane) & (kBX - 1)];
+        const Acc tr = wave_inclusive_scan(rs);
+        if (lane < kBY) A.trow[ebase + lane] = tr;
     }
-    st.finish(lane, true, A, (size_t)b * N + ox + lane);
 }
 
 // ------------------------------------------------------------------ passes 2 and 3
@@ -398,7 +440,8 @@ enum { kModePlanes = 0, kModeDeform = 1 };
 template <int Q, typename Tin, typename Acc, int MODE>
 __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img, Geom g, Agg<Acc> A, Carry<Acc> K,
                                                     uint32_t mask, Tin* __restrict__ planes,
-                                                    float2* __restrict__ field, double d0, const int* status) {
+                                                    float2* __restrict__ field, const float2* __restrict__ t1,
+                                                    double d0, const int* status) {
     extern __shared__ unsigned char smem_raw[];
     if (failed(status)) return;
     const int lane = lane_id();
@@ -477,7 +520,7 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
     }
     Acc Lleft = (c > 0) ? Linb[cW - 1] : Acc(0);
     Acc Rright = (cW + W < N) ? Rinb[cW + W] : Acc(0);
-    MapScale ms;
+    MapScale ms{};
     if constexpr (MODE == kModeDeform) ms = map_scale(to_f64(Ctot), N, d0);
 
     // output slots of the requested planes
@@ -489,20 +532,21 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
     }
 
     const Tin* src = img + (size_t)b * H * N + col;
-    Tin buf[kPF][Q];
+    constexpr int PF = prefetch_rows<Q, Tin>();
+    Tin buf[PF][Q];
 #pragma unroll
-    for (int p = 0; p < kPF; ++p)
+    for (int p = 0; p < PF; ++p)
         if (p < H) load_tile_row<Tin, Q>(src + (size_t)p * N, act, buf[p]);
 
-    for (int r0 = 0; r0 < H; r0 += kPF) {
+    for (int r0 = 0; r0 < H; r0 += PF) {
 #pragma unroll
-        for (int p = 0; p < kPF; ++p) {
+        for (int p = 0; p < PF; ++p) {
             const int r = r0 + p;
             if (r < H) {
                 Tin v[Q];
 #pragma unroll
                 for (int e = 0; e < Q; ++e) v[e] = buf[p][e];
-                if (r + kPF < H) load_tile_row<Tin, Q>(src + (size_t)(r + kPF) * N, act, buf[p]);
+                if (r + PF < H) load_tile_row<Tin, Q>(src + (size_t)(r + PF) * N, act, buf[p]);
                 const int j = b * H + r;
 
 #pragma unroll
@@ -575,7 +619,9 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
                         if (mask & INIM_DELTA_T) store_row_nt<Tin, Q>(rowp + slot[7] * NN, odt);
                     }
                 } else {
-                    float2 o[Q];
+                    float2 o[Q], d1[Q];
+                    load_row<float, 2 * Q>(reinterpret_cast<const float*>(t1 + (size_t)j * N + col),
+                                           reinterpret_cast<float(&)[2 * Q]>(d1));
 #pragma unroll
                     for (int e = 0; e < Q; ++e) {
                         const int x = x0 + e;
@@ -584,13 +630,131 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
                         Planes8 P;
                         P.a = to_f64(al[e]); P.b = to_f64(cm.b); P.g = to_f64(cm.g); P.d = to_f64(cm.d);
                         P.at = to_f64(at[e]); P.bt = to_f64(cm.bt); P.gt = to_f64(cm.gt); P.dt = to_f64(cm.dt);
-                        o[e] = deform_texel(P, ms, cW + x, j, N);
+                        o[e] = deform_texel_defect(P, ms, cW + x, j, d1[e]);
                     }
                     store_field_nt<Q>(field + (size_t)j * N + col, o);
                 }
             }
         }
     }
+}
+
+// ------------------------------------------------------------------ pass 4, deformation, 64 x 16 tiles
+// The final pass of the regularisation for the common tiling (W = 64, Q = 1,
+// H = 16, N >= 64, so every lane is active): all 16 input rows and defect
+// values are loaded up front and the row loop is fully unrolled without
+// branches, so the per-texel map of row r overlaps the scans of row r+1.
+template <typename Tin, typename Acc>
+__global__ __launch_bounds__(256) void k_inim_deform16(const Tin* __restrict__ img, Geom g, Agg<Acc> A, Carry<Acc> K,
+                                                       float2* __restrict__ field, const float2* __restrict__ t1,
+                                                       double d0, const int* status) {
+    constexpr int H = 16, W = 64;
+    extern __shared__ unsigned char smem_raw[];
+    if (failed(status)) return;
+    const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
+    const int tile = blockIdx.x * kWavesPerBlock + wave;
+    if (tile >= g.B * g.T) return;
+    const int N = g.N, T = g.T;
+    const int b = tile / T, c = tile - (tile / T) * T;
+    const int cW = c * W;
+    const int col = cW + lane;
+    const Acc* ainb = K.ain + (size_t)b * N;
+    const Acc* Linb = K.Lin + (size_t)b * N;
+    const Acc* Rinb = K.Rin + (size_t)b * N;
+
+    // inputs and defect values of the tile's 16 rows
+    Tin v[H];
+    float2 d1[H];
+    const Tin* src = img + (size_t)b * H * N + col;
+    const float2* t1p = t1 + (size_t)b * H * N + col;
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+        v[r] = src[(size_t)r * N];
+        d1[r] = t1p[(size_t)r * N];
+    }
+
+    // per-row boundary values (lane r holds row r)
+    Acc lb = Acc(0), rb = Acc(0), ac = Acc(0), yv = Acc(0);
+    if (lane < H) {
+        const int r = lane;
+        const size_t eb = (size_t)b * T * H;
+        const Acc* acb = K.AC + (size_t)b * (T + 1) * H + r;
+        ac = acb[(size_t)c * H];
+        yv = acb[(size_t)T * H];
+        if (c > 0) {
+            const int m = cW - 2 - r;
+            lb = ainb[cW - 1] - (m >= 0 ? ainb[m] : Acc(0));
+            lb += A.tLedge[eb + (size_t)(c - 1) * H + r];
+            if (m >= 0) lb += Linb[m];
+        }
+        if (c < T - 1) {
+            const int m = cW + W + r;
+            rb = ainb[m] - ainb[cW + W - 1];
+            rb += A.tRedge[eb + (size_t)(c + 1) * H + r];
+            if (m + 1 < N) rb += Rinb[m + 1];
+        }
+    }
+
+    // U and V over the tile's anti-diagonals and diagonals
+    constexpr int S = W + H - 1;
+    const int u0 = cW + b * H;
+    const int v0 = cW - b * H - (H - 1);
+    Acc* Uw = reinterpret_cast<Acc*>(smem_raw) + (size_t)wave * 2 * S;
+    Acc* Vw = Uw + S;
+    for (int k = lane; k < S; k += 64) {
+        Uw[k] = marg_U(g, A, K, u0 + k);
+        Vw[k] = marg_V(g, A, K, v0 + k);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+
+    const Acc Ctot = K.ain[(size_t)g.B * N + (N - 1)];
+    const Acc X = K.ain[(size_t)g.B * N + col];
+    Acc cp = K.cpin[(size_t)b * N + col];
+    Acc L = Linb[col], R = Rinb[col];
+    Acc Lleft = (c > 0) ? Linb[cW - 1] : Acc(0);
+    Acc Rright = (cW + W < N) ? Rinb[cW + W] : Acc(0);
+    const MapScale ms = map_scale(to_f64(Ctot), N, d0);
+
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+        const int j = b * H + r;
+        cp += to_acc<Acc, Tin>(v[r]);
+        const Acc incl = wave_inclusive_scan(cp);
+        const Acc al = bcast(ac, r) + incl;
+        Acc upL = shfl_up1(L), dnR = shfl_down1(R);
+        if (lane == 0) upL = Lleft;
+        if (lane == 63) dnR = Rright;
+        L = cp + upL;
+        R = cp + dnR;
+        Lleft = bcast(lb, r);
+        Rright = bcast(rb, r);
+        const Acc at = (L + R) - cp;
+        const Acc U = Uw[lane + r], V = Vw[lane - r + H - 1];
+        const Compl<Acc> cm = complements<Acc>(al, at, X, bcast(yv, r), U, V, Ctot, col, j, N);
+        Planes8 P;
+        P.a = to_f64(al); P.b = to_f64(cm.b); P.g = to_f64(cm.g); P.d = to_f64(cm.d);
+        P.at = to_f64(at); P.bt = to_f64(cm.bt); P.gt = to_f64(cm.gt); P.dt = to_f64(cm.dt);
+        const float2 o[1] = {deform_texel_defect(P, ms, col, j, d1[r])};
+        store_field_nt<1>(field + (size_t)j * N + col, o);
+    }
+}
+
+// ------------------------------------------------------------------ defect field
+// t(p; 1) of the constant raster at every texel centre (Sec. 4.2: the defect
+// does not depend on the density, so it is computed once per call).
+__global__ __launch_bounds__(256) void k_defect_field(int N, float2* __restrict__ t1) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t NN = (size_t)N * N;
+    if (k >= NN) return;
+    const int j = (int)(k / N), i = (int)(k - (size_t)j * N);
+    const double invN = 1.0 / (double)N;
+    const double x = ((double)i + 0.5) * invN, y = ((double)j + 0.5) * invN;
+    double sx, sy;
+    map_sum(ones_planes(i, j, N), x, y, sx, sy);
+    const double s = 1.0 / (2.0 * (double)NN);
+    t1[k] = make_float2((float)(sx * s), (float)(sy * s));
 }
 
 // ------------------------------------------------------------------ deform from stored planes
@@ -676,20 +840,24 @@ hipError_t launch_inim_carries(const Tin* img, const Geom& g, void* scratch, con
 
 template <typename Tin, typename Acc, int Q>
 static hipError_t launch_final_q(const Tin* img, const Geom& g, void* scratch, uint32_t mask, Tin* planes,
-                                 float2* field, double d0, double* marg, const int* status, hipStream_t st) {
+                                 float2* field, const float2* t1, double d0, double* marg, const int* status,
+                                 hipStream_t st) {
     Agg<Acc> A;
     Carry<Acc> K;
     carve<Acc>(g, (char*)scratch, A, K);
     const int tiles = g.B * g.T;
     const dim3 blk(64 * kWavesPerBlock);
     const dim3 grd((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
-    if (field != nullptr) {
+    if (field != nullptr && Q == 1 && g.W == 64 && g.H == 16 && g.N >= 64) {
+        hipLaunchKernelGGL((k_inim_deform16<Tin, Acc>), grd, blk, final_smem<Acc>(g, true), st, img, g, A, K, field, t1,
+                           d0, status);
+    } else if (field != nullptr) {
         hipLaunchKernelGGL((k_inim_final<Q, Tin, Acc, kModeDeform>), grd, blk, final_smem<Acc>(g, true), st, img, g, A,
-                           K, 0u, (Tin*)nullptr, field, d0, status);
+                           K, 0u, (Tin*)nullptr, field, t1, d0, status);
     } else if (mask != 0) {
         const bool needUV = (mask & (INIM_BETA_T | INIM_GAMMA_T | INIM_DELTA_T)) != 0;
         hipLaunchKernelGGL((k_inim_final<Q, Tin, Acc, kModePlanes>), grd, blk, final_smem<Acc>(g, needUV), st, img, g,
-                           A, K, mask, planes, (float2*)nullptr, 0.0, status);
+                           A, K, mask, planes, (float2*)nullptr, (const float2*)nullptr, 0.0, status);
     }
     if (marg != nullptr) {
         const int M = 6 * g.N - 1;
@@ -700,11 +868,12 @@ static hipError_t launch_final_q(const Tin* img, const Geom& g, void* scratch, u
 
 template <typename Tin, typename Acc>
 hipError_t launch_inim_final(const Tin* img, const Geom& g, void* scratch, uint32_t mask, Tin* planes, float2* field,
-                             double d0, double* marg, const int* status, hipStream_t st) {
+                             const float2* t1, double d0, double* marg, const int* status, hipStream_t st) {
+    if (field != nullptr && t1 == nullptr) return hipErrorInvalidValue;
     switch (g.Q) {
-        case 1: return launch_final_q<Tin, Acc, 1>(img, g, scratch, mask, planes, field, d0, marg, status, st);
-        case 2: return launch_final_q<Tin, Acc, 2>(img, g, scratch, mask, planes, field, d0, marg, status, st);
-        case 4: return launch_final_q<Tin, Acc, 4>(img, g, scratch, mask, planes, field, d0, marg, status, st);
+        case 1: return launch_final_q<Tin, Acc, 1>(img, g, scratch, mask, planes, field, t1, d0, marg, status, st);
+        case 2: return launch_final_q<Tin, Acc, 2>(img, g, scratch, mask, planes, field, t1, d0, marg, status, st);
+        case 4: return launch_final_q<Tin, Acc, 4>(img, g, scratch, mask, planes, field, t1, d0, marg, status, st);
     }
     return hipErrorInvalidValue;
 }
@@ -713,12 +882,18 @@ hipError_t launch_inim_final(const Tin* img, const Geom& g, void* scratch, uint3
     template hipError_t launch_inim_carries<TIN, ACC>(const TIN*, const Geom&, void*, const int*, hipStream_t);      \
     template hipError_t launch_inim_aggregate<TIN, ACC>(const TIN*, const Geom&, void*, const int*, hipStream_t);    \
     template hipError_t launch_inim_scans<ACC>(const Geom&, void*, const int*, hipStream_t);                         \
-    template hipError_t launch_inim_final<TIN, ACC>(const TIN*, const Geom&, void*, uint32_t, TIN*, float2*, double, \
-                                                    double*, const int*, hipStream_t);
+    template hipError_t launch_inim_final<TIN, ACC>(const TIN*, const Geom&, void*, uint32_t, TIN*, float2*,        \
+                                                    const float2*, double, double*, const int*, hipStream_t);
 INIM_INSTANTIATE(uint32_t, uint32_t)
 INIM_INSTANTIATE(float, u128)
 INIM_INSTANTIATE(float, double)
 #undef INIM_INSTANTIATE
+
+hipError_t launch_defect_field(int N, float2* t1, hipStream_t st) {
+    const size_t NN = (size_t)N * N;
+    hipLaunchKernelGGL(k_defect_field, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, st, N, t1);
+    return hipGetLastError();
+}
 
 hipError_t launch_deform_planes(const void* alpha, const void* alpha_t, int dt, const double* marg, int N, double d0,
                                 float2* field, hipStream_t st) {

@@ -160,9 +160,12 @@ __global__ __launch_bounds__(256) void k_splat_rank(const float2* __restrict__ x
     }
 }
 
-// Exclusive prefix of a uint32 array in three passes: per-block sums, a scan
-// of the block sums by one block, and the scan within each block.
-constexpr int kScanThreads = 1024, kScanItems = 16, kScanBlock = kScanThreads * kScanItems;
+// Exclusive prefix of a uint32 array (length a multiple of 4) in three passes:
+// per-block sums, a scan of the block sums by one block, and the scan within
+// each block.  A block of 256 threads covers 1024 consecutive words, four per
+// thread as one 16-byte vector.
+constexpr int kScanThreads = 256, kScanBlock = 4 * kScanThreads;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds_wave, uint32_t& total) {
     const int lane = lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -180,25 +183,20 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* l
     return lds_wave[wave] + incl - v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ a, size_t m,
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ a,
                                                               uint32_t* __restrict__ partial, const int* status) {
     __shared__ uint32_t lw[33];
     if (failed(status)) return;
-    const size_t base = (size_t)blockIdx.x * kScanBlock + (size_t)threadIdx.x * kScanItems;
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < m) s += a[base + k];
+    const u32x4 v = reinterpret_cast<const u32x4*>(a)[(size_t)blockIdx.x * kScanThreads + threadIdx.x];
     uint32_t total;
-    (void)block_exclusive_scan(s, lw, total);
+    (void)block_exclusive_scan(v.x + v.y + v.z + v.w, lw, total);
     if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t* __restrict__ partial, int nb,
-                                                                const int* status) {
+__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* __restrict__ partial, int nb, const int* status) {
     __shared__ uint32_t lw[33];
     if (failed(status)) return;
-    const int per = (nb + kScanThreads - 1) / kScanThreads;
+    const int per = (nb + (int)blockDim.x - 1) / (int)blockDim.x;
     const int b0 = threadIdx.x * per;
     uint32_t s = 0;
     for (int k = 0; k < per; ++k)
@@ -213,26 +211,33 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t* __rest
         }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ a, size_t m,
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ a,
                                                             const uint32_t* __restrict__ partial,
                                                             uint32_t* __restrict__ out, const int* status) {
     __shared__ uint32_t lw[33];
     if (failed(status)) return;
-    const size_t base = (size_t)blockIdx.x * kScanBlock + (size_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems], s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = base + k < m ? a[base + k] : 0u;
-        s += v[k];
-    }
+    const size_t k = (size_t)blockIdx.x * kScanThreads + threadIdx.x;
+    const u32x4 v = reinterpret_cast<const u32x4*>(a)[k];
     uint32_t total;
-    uint32_t run = partial[blockIdx.x] + block_exclusive_scan(s, lw, total);
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < m) {
-            out[base + k] = run;
-            run += v[k];
-        }
+    const uint32_t run = partial[blockIdx.x] + block_exclusive_scan(v.x + v.y + v.z + v.w, lw, total);
+    u32x4 o;
+    o.x = run;
+    o.y = run + v.x;
+    o.z = o.y + v.y;
+    o.w = o.z + v.z;
+    reinterpret_cast<u32x4*>(out)[k] = o;
+}
+
+// Exclusive prefix of at most 1024 words by one block.
+__global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* __restrict__ a, int m,
+                                                     uint32_t* __restrict__ out, const int* status) {
+    __shared__ uint32_t lw[33];
+    if (failed(status)) return;
+    const int t = threadIdx.x;
+    const uint32_t v = t < m ? a[t] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(v, lw, total);
+    if (t < m) out[t] = ex;
 }
 
 // Moves every sample to slot offset[texel] + rank: texel (row-major) order.
@@ -304,13 +309,17 @@ size_t scan_partials(size_t m) { return (m + kScanBlock - 1) / kScanBlock; }
 hipError_t launch_sort_by_texel(const float2* xy, int64_t n, int N, uint32_t* counts, uint32_t* rank,
                                 uint32_t* offsets, uint32_t* partial, float2* sxy, uint32_t* perm, int* status,
                                 hipStream_t st) {
-    const size_t m = (size_t)N * N;
+    const size_t m = (size_t)N * N;  // a multiple of 4 (N >= 2, a power of two)
     const int nb = (int)scan_partials(m);
     hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)(m / 4 + 1), 256, 2048)), dim3(256), 0, st, counts, m, status, 1);
     hipLaunchKernelGGL(k_splat_rank, dim3(grid_for(n)), dim3(256), 0, st, xy, n, N, counts, rank, status);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, counts, m, partial, status);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, partial, nb, status);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, st, counts, m, partial, offsets, status);
+    if (m % kScanBlock == 0) {
+        hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, counts, partial, status);
+        hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, partial, nb, status);
+        hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, st, counts, partial, offsets, status);
+    } else {  // fewer than 1024 texels (N <= 16): one partial block
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, counts, (int)m, offsets, status);
+    }
     hipLaunchKernelGGL(k_scatter_sorted, dim3(grid_for(n)), dim3(256), 0, st, xy, n, N, rank, offsets, sxy, perm,
                        status);
     return hipGetLastError();

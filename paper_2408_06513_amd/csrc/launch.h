@@ -28,9 +28,12 @@ template <typename Tin, typename Acc>
 hipError_t launch_inim_aggregate(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st);
 template <typename Acc>
 hipError_t launch_inim_scans(const Geom& g, void* scratch, const int* status, hipStream_t st);
+// field != nullptr needs t1, the defect field of launch_defect_field.
 template <typename Tin, typename Acc>
 hipError_t launch_inim_final(const Tin* img, const Geom& g, void* scratch, uint32_t mask, Tin* planes, float2* field,
-                             double d0, double* marg, const int* status, hipStream_t st);
+                             const float2* t1, double d0, double* marg, const int* status, hipStream_t st);
+// t1[j*N+i] = t(p; 1), the map of the constant raster at texel (i, j), as floats.
+hipError_t launch_defect_field(int N, float2* t1, hipStream_t st);
 
 hipError_t launch_deform_planes(const void* alpha, const void* alpha_t, int dt, const double* marg, int N, double d0,
                                 float2* field, hipStream_t st);
