@@ -209,9 +209,25 @@ def test_map_is_convex_combination_and_scale_invariant():
     assert np.array_equal(oracle.deform(d, 0.5), oracle.deform(d * 4.0, 2.0))
 
 
-def test_map_of_spike_moves_toward_it():
-    """A single heavy pixel attracts its neighbourhood: texels left of it are
-    displaced to the right and texels right of it to the left (Sec. 3.2)."""
+def test_background_density_damps_displacement():
+    """eq. (map) is a ratio of functionals linear in d, so with d = d_r + d0
+    (eq. (d0)) the displacement of eq. (map_res) is that of d_r alone scaled
+    by C_r / (C_r + N^2 d0): doubling the background shrinks it by a known
+    factor, and a huge background makes the map the identity."""
+    N = 16
+    dr = dg.rng(3).lognormal(0.0, 1.0, size=(N, N))
+    Cr = dr.sum()
+    c = (np.arange(N) + 0.5) / N
+    P = np.stack(np.broadcast_arrays(c[None, :], c[:, None]), axis=-1)
+    d1 = oracle.deform(dr, 0.5) - P
+    d2 = oracle.deform(dr, 1.0) - P
+    np.testing.assert_allclose(d2, d1 * (Cr + N * N * 0.5) / (Cr + N * N * 1.0), rtol=1e-10, atol=1e-15)
+    assert np.abs(oracle.deform(dr, 1e12) - P).max() < 1e-9
+
+
+def test_map_of_spike_pushes_neighbourhood_away():
+    """A single heavy pixel expands its surroundings: texels left of it are
+    displaced to the left and texels right of it to the right (Sec. 3.2)."""
     N = 32
     d = np.zeros((N, N))
     d[16, 16] = 1000.0
