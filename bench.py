@@ -124,7 +124,9 @@ def bench_inim(dev, res: int = 8192, reps: int = 20) -> dict:
     from paper_2408_06513_amd import capi, datagen
 
     out = {}
-    flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+    # evicting the 256 MB last-level cache between calls by reading 512 MB
+    # (a read leaves no dirty lines whose write-back would land in the timing)
+    flush = torch.ones(128 << 20, dtype=torch.float32, device=dev)
     for name, img_np in (("u32", datagen.poisson_raster(0, res)), ("f32", datagen.lognormal_raster(0, res))):
         log(f"inim {name} {res}^2")
         img = torch.from_numpy(img_np).to(dev)
@@ -136,7 +138,7 @@ def bench_inim(dev, res: int = 8192, reps: int = 20) -> dict:
             capi.inim(img, 0xFF, planes=planes, marg=marg, ws=ws)
         times = []
         for _ in range(reps):
-            flush.zero_()
+            flush.sum()
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record()
@@ -178,6 +180,8 @@ def main():
     ap.add_argument("--no-inim", action="store_true", help="skip the 8192^2 integral-image measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--only-inim", action="store_true",
+                    help="print only the 8192^2 integral-image measurement (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -190,6 +194,9 @@ def main():
     from paper_2408_06513_amd import capi
     capi.lib()
 
+    if args.only_inim:
+        print(json.dumps({"inim_8192_all_planes": bench_inim(dev)}), flush=True)
+        return
     xy0_np, value, ms_per_step, stage_us, roofline, graph_value = bench_regularize(args, dev)
     rec = {
         "metric": METRIC,

@@ -39,11 +39,12 @@ struct Agg {
 // Carries at the row above band b (b = 0..B; row B is the state after the last row):
 //   cpin[b][i] column prefix, ain[b][i] alpha, Lin[b][i] / Rin[b][i] the
 //   up-left / up-right diagonal sums of column prefixes;
-// and per band row: AC[b][c][r] = alpha(cW-1, bH+r) for c = 0..T (c = T gives
-// the row marginal Y(bH+r) = alpha(N-1, bH+r)).
+// per band row: AC[b][c][r] = alpha(cW-1, bH+r) for c = 0..T (c = T gives
+// the row marginal Y(bH+r) = alpha(N-1, bH+r)); and the diagonal marginals
+// U[u] = sum over i'+j' <= u, V[v+N-1] = sum over i'-j' >= v (2N-1 each).
 template <typename Acc>
 struct Carry {
-    Acc *cpin, *ain, *Lin, *Rin, *AC;
+    Acc *cpin, *ain, *Lin, *Rin, *AC, *U, *V;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -65,7 +66,7 @@ inline Geom make_geom(int N, int acc_bytes = 4, int q_hint = 0, int h_hint = 0) 
         H = 64;
     } else {
         Q = acc_bytes > 4 ? 2 : 4;
-        H = N / 128 > 64 ? N / 128 : 64;  // 64-row bands, at most 128 of them
+        H = N / 256 > 32 ? N / 256 : 32;  // 32-row bands, at most 256 of them
     }
     if (q_hint > 0) Q = q_hint > 4 ? 4 : q_hint;
     if (h_hint > 0) H = h_hint;
@@ -78,7 +79,7 @@ inline Geom make_geom(int N, int acc_bytes = 4, int q_hint = 0, int h_hint = 0) 
     if (H > W) H = W;
     if (H > 128) H = 128;
     if (H > N) H = N;
-    while (N / H > 128) H <<= 1;  // at most 128 bands (carry scans)
+    while (N / H > 256) H <<= 1;  // at most 256 bands (carry scans)
     g.Q = Q;
     g.W = W;
     g.H = H;
@@ -89,7 +90,7 @@ inline Geom make_geom(int N, int acc_bytes = 4, int q_hint = 0, int h_hint = 0) 
 }
 
 inline bool geom_ok(const Geom& g) {
-    return g.W >= g.H && g.B <= 128 && g.W % g.Q == 0 && g.W / g.Q <= 64 && g.N % g.W == 0 &&
+    return g.W >= g.H && g.B <= 256 && g.W % g.Q == 0 && g.W / g.Q <= 64 && g.N % g.W == 0 &&
            g.N % g.H == 0 && g.H <= 128 && (g.Q == 1 || g.Q == 2 || g.Q == 4);
 }
 
@@ -102,6 +103,7 @@ inline size_t inim_scratch_bytes(const Geom& g, size_t acc) {
     s += 3 * align256((size_t)g.B * g.T * g.H * acc);         // tLedge tRedge trow
     s += 4 * align256((size_t)(g.B + 1) * N * acc);           // cpin ain Lin Rin
     s += align256((size_t)g.B * (g.T + 1) * g.H * acc);       // AC
+    s += 2 * align256((size_t)(2 * N) * acc);                 // U V
     return s;
 }
 
@@ -112,6 +114,7 @@ inline void carve(const Geom& g, char* base, Agg<Acc>& A, Carry<Acc>& K) {
     const size_t edge = align256((size_t)g.B * g.T * g.H * sizeof(Acc));
     const size_t car = align256((size_t)(g.B + 1) * N * sizeof(Acc));
     const size_t acb = align256((size_t)g.B * (g.T + 1) * g.H * sizeof(Acc));
+    const size_t uvb = align256((size_t)(2 * N) * sizeof(Acc));
     char* p = base;
     A.colsum = (Acc*)p; p += col;
     A.tcsp = (Acc*)p; p += col;
@@ -125,6 +128,8 @@ inline void carve(const Geom& g, char* base, Agg<Acc>& A, Carry<Acc>& K) {
     K.Lin = (Acc*)p; p += car;
     K.Rin = (Acc*)p; p += car;
     K.AC = (Acc*)p; p += acb;
+    K.U = (Acc*)p; p += uvb;
+    K.V = (Acc*)p; p += uvb;
 }
 
 }  // namespace inim

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void k_blur_aggregate(const uint32_t* __restri
 // at once, sums them in registers, publishes its total in LDS, and adds the
 // totals of the waves above it.  One round of loads, one barrier.
 constexpr int kScanWaves = 16;
-constexpr int kScanMaxP = 8;  // B <= kScanWaves * kScanMaxP = 128
+constexpr int kScanMaxP = 16;  // B <= kScanWaves * kScanMaxP = 256
 
 __host__ __device__ inline int scan_waves(int B) { return B < kScanWaves ? B : kScanWaves; }
 __host__ __device__ inline int scan_per_wave(int B) { return (B + scan_waves(B) - 1) / scan_waves(B); }
@@ -239,15 +239,24 @@ __global__ __launch_bounds__(1024) void k_inim_scan_col(Geom g, Agg<Acc> A, Carr
     extern __shared__ unsigned char smem_raw[];
     if (failed(status)) return;
     Acc* tot = reinterpret_cast<Acc*>(smem_raw);  // [waves][2][64]
+    __shared__ Acc left[kScanWaves * kScanMaxP];     // per band: totals of the tiles left of c
     const int lane = lane_id();
     const int wave = (int)(threadIdx.x >> 6);
     const int nw = scan_waves(g.B), P = scan_per_wave(g.B);
     const int i = blockIdx.x * 64 + lane;
     const bool valid = i < g.N;
     const int ii = valid ? i : 0;
-    const int c = ii / g.W;
+    const int c = (blockIdx.x * 64) / g.W;  // the block's 64 columns lie in one tile
     const size_t N = (size_t)g.N;
     const int b0 = wave * P;
+    for (int b = threadIdx.x; b < g.B; b += blockDim.x) {
+        Acc t = Acc(0);
+        const Acc* tr = A.trow + (size_t)b * g.T * g.H + (g.H - 1);
+#pragma unroll 8
+        for (int cc = 0; cc < c; ++cc) t += tr[(size_t)cc * g.H];
+        left[b] = t;
+    }
+    __syncthreads();
 
     Acc cs[kScanMaxP], da[kScanMaxP];
 #pragma unroll
@@ -255,15 +264,9 @@ __global__ __launch_bounds__(1024) void k_inim_scan_col(Geom g, Agg<Acc> A, Carr
         cs[k] = Acc(0);
         da[k] = Acc(0);
         const int b = b0 + k;
-        if (k < P && b < g.B) {
-            Acc t = Acc(0);
-            for (int c0 = 0; c0 < c; c0 += 64)
-                if (c0 + lane < c) t += A.trow[((size_t)b * g.T + c0 + lane) * g.H + (g.H - 1)];
-            const Acc left = wave_sum(t);
-            if (valid) {
-                cs[k] = A.colsum[(size_t)b * N + ii];
-                da[k] = A.tcsp[(size_t)b * N + ii] + left;
-            }
+        if (k < P && b < g.B && valid) {
+            cs[k] = A.colsum[(size_t)b * N + ii];
+            da[k] = A.tcsp[(size_t)b * N + ii] + left[b];
         }
     }
     Acc rc = Acc(0), ra = Acc(0);
@@ -321,6 +324,7 @@ __global__ __launch_bounds__(1024) void k_inim_scan_diag(Geom g, Agg<Acc> A, Car
         Acc* ac = K.AC + (size_t)b * (T + 1) * H + r;
         Acc run = Acc(0);
         ac[0] = Acc(0);
+#pragma unroll 8
         for (int c = 1; c <= T; ++c) {
             run += tr[(size_t)(c - 1) * H];
             ac[(size_t)c * H] = ainb[c * W - 1] + run;
@@ -420,18 +424,29 @@ __device__ __forceinline__ Acc marg_Y(const Geom& g, const Carry<Acc>& K, int j)
     return K.AC[((size_t)b * (g.T + 1) + g.T) * g.H + r];
 }
 
+// The diagonal marginals U and V into the carry arrays (used by the final
+// pass), and, when `marg` is not null, all marginals as doubles.
 template <typename Acc>
-__global__ __launch_bounds__(256) void k_inim_marg(Geom g, Agg<Acc> A, Carry<Acc> K, double* marg) {
+__global__ __launch_bounds__(256) void k_inim_marg(Geom g, Agg<Acc> A, Carry<Acc> K, double* marg, const int* status) {
+    if (failed(status)) return;
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     const int N = g.N, M = 2 * N - 1;
     if (o >= 2 * N + 2 * M + 1) return;
     Acc v;
-    if (o < N) v = K.ain[(size_t)g.B * N + o];
-    else if (o < 2 * N) v = marg_Y(g, K, o - N);
-    else if (o < 2 * N + M) v = marg_U(g, A, K, o - 2 * N);
-    else if (o < 2 * N + 2 * M) v = marg_V(g, A, K, (o - 2 * N - M) - (N - 1));
-    else v = K.ain[(size_t)g.B * N + (N - 1)];
-    marg[o] = to_f64(v);
+    if (o < N) {
+        v = K.ain[(size_t)g.B * N + o];
+    } else if (o < 2 * N) {
+        v = marg_Y(g, K, o - N);
+    } else if (o < 2 * N + M) {
+        v = marg_U(g, A, K, o - 2 * N);
+        K.U[o - 2 * N] = v;
+    } else if (o < 2 * N + 2 * M) {
+        v = marg_V(g, A, K, (o - 2 * N - M) - (N - 1));
+        K.V[o - 2 * N - M] = v;
+    } else {
+        v = K.ain[(size_t)g.B * N + (N - 1)];
+    }
+    if (marg != nullptr) marg[o] = to_f64(v);
 }
 
 // ------------------------------------------------------------------ pass 4
@@ -491,7 +506,8 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
         LBv[k] = lb; RBv[k] = rb; ACv[k] = ac; YVv[k] = yv;
     }
 
-    // U and V over the tile's anti-diagonals u0..u0+S-1 and diagonals v0..v0+S-1.
+    // U and V over the tile's anti-diagonals u0..u0+S-1 and diagonals
+    // v0..v0+S-1, staged in LDS from the marginal arrays.
     const int S = W + H - 1;
     const int u0 = cW + b * H;
     const int v0 = cW - b * H - (H - 1);
@@ -499,8 +515,8 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
     Acc* Vw = Uw + S;
     if (needUV) {
         for (int k = lane; k < S; k += 64) {
-            Uw[k] = marg_U(g, A, K, u0 + k);
-            Vw[k] = marg_V(g, A, K, v0 + k);
+            Uw[k] = K.U[u0 + k];
+            Vw[k] = K.V[v0 + k + N - 1];
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -696,15 +712,15 @@ __global__ __launch_bounds__(256) void k_inim_deform16(const Tin* __restrict__ i
         }
     }
 
-    // U and V over the tile's anti-diagonals and diagonals
+    // U and V over the tile's anti-diagonals and diagonals, staged in LDS
     constexpr int S = W + H - 1;
     const int u0 = cW + b * H;
     const int v0 = cW - b * H - (H - 1);
     Acc* Uw = reinterpret_cast<Acc*>(smem_raw) + (size_t)wave * 2 * S;
     Acc* Vw = Uw + S;
     for (int k = lane; k < S; k += 64) {
-        Uw[k] = marg_U(g, A, K, u0 + k);
-        Vw[k] = marg_V(g, A, K, v0 + k);
+        Uw[k] = K.U[u0 + k];
+        Vw[k] = K.V[v0 + k + N - 1];
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -778,11 +794,6 @@ __global__ __launch_bounds__(256) void k_deform_planes(const Tin* __restrict__ a
 
 // ------------------------------------------------------------------ launchers
 template <typename Acc>
-static size_t final_smem(const Geom& g, bool needUV) {
-    return needUV ? (size_t)kWavesPerBlock * 2 * (g.W + g.H - 1) * sizeof(Acc) : 0;
-}
-
-template <typename Acc>
 hipError_t launch_inim_scans(const Geom& g, void* scratch, const int* status, hipStream_t st) {
     Agg<Acc> A;
     Carry<Acc> K;
@@ -848,20 +859,18 @@ static hipError_t launch_final_q(const Tin* img, const Geom& g, void* scratch, u
     const int tiles = g.B * g.T;
     const dim3 blk(64 * kWavesPerBlock);
     const dim3 grd((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+    const int M = 6 * g.N - 1;
+    hipLaunchKernelGGL((k_inim_marg<Acc>), dim3((M + 255) / 256), dim3(256), 0, st, g, A, K, marg, status);
+    const size_t smem = (size_t)kWavesPerBlock * 2 * (g.W + g.H - 1) * sizeof(Acc);
     if (field != nullptr && Q == 1 && g.W == 64 && g.H == 16 && g.N >= 64) {
-        hipLaunchKernelGGL((k_inim_deform16<Tin, Acc>), grd, blk, final_smem<Acc>(g, true), st, img, g, A, K, field, t1,
-                           d0, status);
+        hipLaunchKernelGGL((k_inim_deform16<Tin, Acc>), grd, blk, smem, st, img, g, A, K, field, t1, d0, status);
     } else if (field != nullptr) {
-        hipLaunchKernelGGL((k_inim_final<Q, Tin, Acc, kModeDeform>), grd, blk, final_smem<Acc>(g, true), st, img, g, A,
-                           K, 0u, (Tin*)nullptr, field, t1, d0, status);
+        hipLaunchKernelGGL((k_inim_final<Q, Tin, Acc, kModeDeform>), grd, blk, smem, st, img, g, A, K, 0u,
+                           (Tin*)nullptr, field, t1, d0, status);
     } else if (mask != 0) {
         const bool needUV = (mask & (INIM_BETA_T | INIM_GAMMA_T | INIM_DELTA_T)) != 0;
-        hipLaunchKernelGGL((k_inim_final<Q, Tin, Acc, kModePlanes>), grd, blk, final_smem<Acc>(g, needUV), st, img, g,
-                           A, K, mask, planes, (float2*)nullptr, (const float2*)nullptr, 0.0, status);
-    }
-    if (marg != nullptr) {
-        const int M = 6 * g.N - 1;
-        hipLaunchKernelGGL((k_inim_marg<Acc>), dim3((M + 255) / 256), dim3(256), 0, st, g, A, K, marg);
+        hipLaunchKernelGGL((k_inim_final<Q, Tin, Acc, kModePlanes>), grd, blk, needUV ? smem : 0, st, img, g, A, K,
+                           mask, planes, (float2*)nullptr, (const float2*)nullptr, 0.0, status);
     }
     return hipGetLastError();
 }
