@@ -91,27 +91,57 @@ __device__ __forceinline__ u128 shfl_xor(u128 v, int d) {
                 __shfl_xor((unsigned long long)(uint64_t)(v >> 64), d, kWave));
 }
 
-template <typename T>
-__device__ __forceinline__ T shfl_up1(T v) { return shfl_up(v, 1); }
-template <typename T>
-__device__ __forceinline__ T shfl_down1(T v) { return shfl_down(v, 1); }
-
-// Inclusive Kogge-Stone scan over the 64 lanes.
-template <typename T>
-__device__ __forceinline__ T wave_inclusive_scan(T v) {
-    const int lane = lane_id();
+// Lane moves through the DPP crossbar (GFX9 encodings), applied to each
+// 32-bit word of a value.  A lane whose source lies outside the pattern, or
+// whose 16-lane row is not in ROWS, receives 0 (the identity of every sum
+// below).  All 64 lanes must be active.
+enum : int {
+    kDppRowShr1 = 0x111,
+    kDppRowShr2 = 0x112,
+    kDppRowShr4 = 0x114,
+    kDppRowShr8 = 0x118,
+    kDppWaveShl1 = 0x130,   // lane l reads lane l+1
+    kDppWaveShr1 = 0x138,   // lane l reads lane l-1
+    kDppRowBcast15 = 0x142, // lane 15 of each row to the next row
+    kDppRowBcast31 = 0x143  // lane 31 to rows 2 and 3
+};
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, true);
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) { return dpp32<CTRL, ROWS>(v); }
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = dpp32<CTRL, ROWS>((uint32_t)b), hi = dpp32<CTRL, ROWS>((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ u128 dpp(u128 v) {
+    u128 r = 0;
 #pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        T y = shfl_up(v, off);
-        if (lane >= off) v += y;
-    }
-    return v;
+    for (int k = 0; k < 4; ++k) r |= (u128)dpp32<CTRL, ROWS>((uint32_t)(v >> (32 * k))) << (32 * k);
+    return r;
 }
 
+// Value of lane l-1 (0 in lane 0) and of lane l+1 (0 in lane 63).
 template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += shfl_xor(v, off);
+__device__ __forceinline__ T shfl_up1(T v) { return dpp<kDppWaveShr1>(v); }
+template <typename T>
+__device__ __forceinline__ T shfl_down1(T v) { return dpp<kDppWaveShl1>(v); }
+
+// Inclusive scan over the 64 lanes: Hillis-Steele steps 1, 2, 4, 8 inside
+// each 16-lane row, then the totals of rows 0 and 2 into rows 1 and 3, then
+// the total of rows 0-1 into rows 2 and 3.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+    v += dpp<kDppRowShr1>(v);
+    v += dpp<kDppRowShr2>(v);
+    v += dpp<kDppRowShr4>(v);
+    v += dpp<kDppRowShr8>(v);
+    v += dpp<kDppRowBcast15, 0xA>(v);
+    v += dpp<kDppRowBcast31, 0xC>(v);
     return v;
 }
 

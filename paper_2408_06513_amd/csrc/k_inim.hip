@@ -75,7 +75,7 @@ struct TileAgg {
         Acc s = Acc(0);
 #pragma unroll
         for (int e = 0; e < Q; ++e) s += cp[e];
-        s = wave_sum(s);
+        s = bcast(wave_inclusive_scan(s), 63);
         const Acc le = bcast(L[Q - 1], lastLane), re = bcast(R[0], 0);
         if (lane == (r & 63)) {
             if (r < 64) { pk_row[0] = s; pk_le[0] = le; pk_re[0] = re; }
