@@ -7,6 +7,10 @@ Headline workload (one step = one whole regularisation call):
 Also reported:
   - per-stage times from HIP events recorded by the library on its stream,
     and the roofline of the dominant stage (algorithmic bytes / time);
+  - the same call through a captured HIP graph, and with the 1024 x 1024
+    texel lattice moved along as probe points (composite map output);
+  - a 45-plot scatterplot matrix (200,000 samples x 10 dims, rasters of
+    256/512/1024, 6 iterations) in one batched call against 45 single calls;
   - the integral images alone on 8192 x 8192 rasters (uint32 Poisson(4) and
     float32 lognormal, all eight planes): Gpixel/s and GB/s;
   - the FP64 CPU oracle timed on the same workload (cpu_baseline).
@@ -26,6 +30,35 @@ sys.path.insert(0, ROOT)
 METRIC = "InIm Gpixel/s (% HBM peak); regularize iters/s at 1M pts; surrogate vs plain speedup"
 HBM_PEAK_GBS = 8000.0
 PAPER_ITERS_PER_S = 8 / 12.63e-3  # Table 1: 8 iterations, 1M points, 1024^2, r = 8, RTX 2060
+
+
+# HBM traffic per launch of the dominant stage's kernel from two rocprofv3
+# --pmc runs of `bench.py --profile-short` (FETCH_SIZE, then WRITE_SIZE; see
+# profiles/pmc_traffic_regularize_1M_1024.md), each scaled by what the same
+# counter reads for a plain 256 MiB device copy in that run.  Valid only for
+# the kernel sources they were taken with (SHA-256 over csrc/*.hip, *.h).
+TRAFFIC = {
+    "src_sha256": "",
+    "smooth_aggregate": None,  # bytes per launch of k_blur_aggregate
+}
+
+
+def kernel_sources_sha256() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2408_06513_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage: str):
+    if TRAFFIC.get("src_sha256") != kernel_sources_sha256():
+        return None
+    return TRAFFIC.get(stage)
 
 
 def log(msg: str):
@@ -95,6 +128,27 @@ def bench_regularize(args, dev):
     graph_value = iters * args.steps / (t1 - t0)
     graph.close()
 
+    # the same steps also moving the res x res texel lattice as probe points
+    # (the composite map of all iterations on the lattice)
+    lat0 = torch.from_numpy(datagen.lattice_points(res)).to(dev)
+    lat = torch.empty_like(lat0)
+
+    def pstep():
+        xy.copy_(xy0)
+        lat.copy_(lat0)
+        capi.regularize_probes(xy, lat, res, iters, radius=radius, ws=ws, check=False)
+
+    for _ in range(max(1, args.warmup)):
+        pstep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pstep()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert capi.sync_status(ws) == capi.OK
+    probe_value = iters * args.steps / (t1 - t0)
+
     # per-stage HIP events (same stream), separate pass so the headline is unperturbed
     log("stage timing")
     acc = {k: 0.0 for k in capi.STAGES}
@@ -112,9 +166,9 @@ def bench_regularize(args, dev):
     t_dom = stage_us[dom] * 1e-6
     achieved = sb[dom] / t_dom / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom), "kernel": dom,
                 "bytes_per_launch": sb[dom], "launch_us": round(stage_us[dom], 3)}
-    return xy0_np, value, ms_per_step, stage_us, roofline, graph_value
+    return xy0_np, value, ms_per_step, stage_us, roofline, graph_value, probe_value
 
 
 def bench_inim(dev, res: int = 8192, reps: int = 20) -> dict:
@@ -154,6 +208,86 @@ def bench_inim(dev, res: int = 8192, reps: int = 20) -> dict:
     return out
 
 
+def profile_short(args, dev):
+    """A short run for rocprofv3 --pmc: each kernel of interest a few times."""
+    import torch
+
+    from paper_2408_06513_amd import capi, datagen
+    src = torch.ones(64 << 20, dtype=torch.float32, device=dev)  # 256 MiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)  # the calibration copy: 256 MiB read, 256 MiB written
+    torch.cuda.synchronize()
+    del src, dst
+    xy0 = torch.from_numpy(datagen.plain_large(0, n=args.n)).to(dev)
+    ws = capi.workspace(capi.workspace_size(args.res, args.n, 8), dev)
+    capi.regularize(xy0.clone(), args.res, args.iters, radius=8, ws=ws)
+    torch.cuda.synchronize()
+    res = 8192
+    for dt, img_np in ((capi.U32, datagen.poisson_raster(0, res)), (capi.F32, datagen.lognormal_raster(0, res))):
+        img = torch.from_numpy(img_np).to(dev)
+        wsi = capi.workspace(capi.inim_workspace_size(res, dt), dev)
+        planes = torch.empty((8, res, res), dtype=img.dtype, device=dev)
+        capi.inim(img, 0xFF, planes=planes, ws=wsi)
+        torch.cuda.synchronize()
+        del img, wsi, planes
+    print(json.dumps({"profile_short": "done", "n": args.n, "res": args.res, "iters": args.iters}), flush=True)
+
+
+def bench_splom(dev, reps: int = 5) -> dict:
+    """Scatterplot matrix: 200,000 samples x 10 dims, all 45 pairwise plots
+    at raster sizes drawn from 256/512/1024, 6 iterations each; one batched
+    call (plain launches, autotuned shape, captured graph) against 45
+    inim_regularize calls.  Times from events around the calls only."""
+    import numpy as np
+    import torch
+
+    from paper_2408_06513_amd import capi, datagen
+    iters = 6
+    log("splom: 45 plots")
+    plots = datagen.splom_plots(0)
+    src = [torch.from_numpy(xy).to(dev) for xy, _ in plots]
+    res = [r for _, r in plots]
+    xs = [torch.empty_like(s) for s in src]
+    ws = capi.workspace(capi.batch_workspace_size(xs, res), dev)
+    wss = [capi.workspace(capi.workspace_size(r, s.shape[0]), dev) for s, r in zip(src, res)]
+
+    def timed(fn):
+        out = []
+        for rep in range(reps + 1):
+            for x, s in zip(xs, src):
+                x.copy_(s)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            if rep:
+                out.append(a.elapsed_time(b))
+        return float(np.median(out))
+
+    def seq():
+        for x, r, w in zip(xs, res, wss):
+            capi.regularize(x, r, iters, ws=w, check=False)
+
+    t_seq = timed(seq)
+    t_def = timed(lambda: capi.regularize_batch(xs, res, iters, ws=ws, check=False))
+    cfg, _ = capi.batch_autotune(xs, res, iters, ws=ws)
+    t_tuned = timed(lambda: capi.regularize_batch(xs, res, iters, cfg=cfg, ws=ws, check=False))
+    graph = capi.Graph()
+    t_graph = timed(lambda: capi.regularize_batch(xs, res, iters, cfg=cfg, ws=ws, graph=graph, check=False))
+    graph.close()
+    assert capi.sync_status(ws) == capi.OK
+    best = min(t_def, t_tuned, t_graph)
+    return {"plots": len(plots), "samples_per_plot": int(src[0].shape[0]), "iters": iters,
+            "sizes": {str(s): res.count(s) for s in sorted(set(res))},
+            "sequential_ms": round(t_seq, 3), "batched_ms": round(t_def, 3), "batched_tuned_ms": round(t_tuned, 3),
+            "batched_tuned_graph_ms": round(t_graph, 3), "tuned_config": repr(cfg),
+            "speedup_vs_sequential": round(t_seq / best, 2)}
+
+
 def cpu_baseline(xy0_np, res: int, iters: int, budget_s: float) -> dict:
     import oracle
     log("cpu baseline (oracle)")
@@ -179,9 +313,14 @@ def main():
     ap.add_argument("--iters", type=int, default=8)
     ap.add_argument("--no-inim", action="store_true", help="skip the 8192^2 integral-image measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-splom", action="store_true", help="skip the 45-plot scatterplot-matrix measurement")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--only-inim", action="store_true",
                     help="print only the 8192^2 integral-image measurement (for profiling)")
+    ap.add_argument("--profile-short", action="store_true",
+                    help="for counter collection: one 256 MiB device copy (the calibration of the byte "
+                         "counters), one regularisation of the headline workload and one 8192^2 "
+                         "integral-image call of each type; prints one line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -197,7 +336,10 @@ def main():
     if args.only_inim:
         print(json.dumps({"inim_8192_all_planes": bench_inim(dev)}), flush=True)
         return
-    xy0_np, value, ms_per_step, stage_us, roofline, graph_value = bench_regularize(args, dev)
+    if args.profile_short:
+        profile_short(args, dev)
+        return
+    xy0_np, value, ms_per_step, stage_us, roofline, graph_value, probe_value = bench_regularize(args, dev)
     rec = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -218,9 +360,12 @@ def main():
         "roofline": roofline,
         "stages_us_per_iter": {k: round(v, 3) for k, v in stage_us.items()},
         "graph_replay_iters_per_s": round(graph_value, 2),
+        "with_lattice_probes_iters_per_s": round(probe_value, 2),
     }
     if not args.no_inim:
         rec["inim_8192_all_planes"] = bench_inim(dev)
+    if not args.no_splom:
+        rec["splom_45_plots"] = bench_splom(dev)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(xy0_np, args.res, args.iters, args.cpu_seconds)
     print(json.dumps(rec), flush=True)

@@ -183,6 +183,24 @@ int inim_regularize(float* xy, int64_t n, int32_t res, int32_t iters, const inim
                     void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * inim_regularize with probe points (Sec. 4.3; the deformed grid of Sec. 5
+ * without its rendering): the m points of `probe` are moved by the same
+ * per-texel deformation as the samples in every iteration, but are never
+ * splatted, so they do not change the density or the samples' results.
+ * Started at the texel centres, the probes end up holding the composite map
+ * T_iters o ... o T_1 of all iterations on the texel lattice.
+ *   probe  device, float [m][2] in [0,1]^2, updated in place; may be NULL
+ *          when m == 0.
+ * xy, n, res, iters, p, ws as for inim_regularize (same workspace size).
+ * n == 0 or iters == 0 is a no-op that leaves the probes unchanged.  A NaN or
+ * out-of-range probe is reported like an invalid sample (EDOMAIN from
+ * inim_sync_status; samples and probes unchanged).  EINVAL if m < 0 or probe
+ * is NULL with m > 0.
+ */
+int inim_regularize_probes(float* xy, int64_t n, float* probe, int64_t m, int32_t res, int32_t iters,
+                           const inim_params* p, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
  * inim_regularize instrumented for measurement: records HIP events on
  * `stream` around the stages, synchronises after each iteration, and adds the
  * elapsed milliseconds into stage_ms[0..5]:
@@ -215,6 +233,51 @@ int inim_graph_create(void** graph);
 int inim_graph_destroy(void* graph);
 int inim_regularize_graph(float* xy, int64_t n, int32_t res, int32_t iters, const inim_params* p,
                           void* ws, size_t ws_bytes, void* graph, hipStream_t stream);
+
+/*
+ * Several plots in one call (Sec. 4.3 for each plot of a scatterplot matrix,
+ * Sec. 6): `count` plots, plot k with its own samples xy[k] (device, float
+ * [n[k]][2], updated in place) on its own res[k] x res[k] raster, all with
+ * the same iteration count and parameters (d0 < 0 selects n[k] / res[k]^2 per
+ * plot).  Every stage of the iteration is one launch over the tiles and
+ * samples of all plots, so small plots fill the GPU together.  Each plot gets
+ * exactly the result of inim_regularize for it alone (bit for bit).
+ *   xy, n, res  host arrays of `count` entries; 0 <= count <= 64;
+ *               64 <= res[k] <= 2048 (powers of two); plots with n[k] == 0
+ *               are left alone.
+ *   p           radius >= 1 (the smoothed-density path).
+ *   cfg         launch shape, NULL for the default (see inim_batch_config);
+ *               every shape gives the same results.
+ *   ws          device workspace of inim_batch_workspace_size bytes.
+ *   graph       NULL: plain launches; or a handle of inim_graph_create: the
+ *               launch sequence is captured once per distinct argument set
+ *               and replayed as one HIP graph.
+ * A NaN or out-of-range sample in any plot makes the whole call a no-op
+ * reported as EDOMAIN by inim_sync_status.  EINVAL for a bad count, size,
+ * pointer or configuration.
+ */
+typedef struct {
+    int32_t waves_per_block; /* tiles per block of the deformation stage: 1, 2, 4 or 8; 0 = 4 */
+    int32_t order;           /* 0: plots in input order; 1: larger rasters first */
+} inim_batch_config;
+
+int inim_batch_workspace_size(float* const* xy, const int64_t* n, const int32_t* res, int32_t count,
+                              const inim_params* p, size_t* bytes);
+int inim_regularize_batch(float* const* xy, const int64_t* n, const int32_t* res, int32_t count, int32_t iters,
+                          const inim_params* p, const inim_batch_config* cfg, void* ws, size_t ws_bytes, void* graph,
+                          hipStream_t stream);
+
+/*
+ * Picks the fastest launch shape of inim_regularize_batch for these plots by
+ * timing each candidate (waves_per_block 1, 2, 4, 8 x both orders) on the
+ * device with the caller's data: every candidate runs the whole iteration
+ * but leaves its results in the workspace, so xy is not modified.
+ * Synchronises `stream`.  best (host) receives the winner, best_ms (host, may
+ * be NULL) its time in milliseconds.  iters >= 1.
+ */
+int inim_batch_autotune(float* const* xy, const int64_t* n, const int32_t* res, int32_t count, int32_t iters,
+                        const inim_params* p, void* ws, size_t ws_bytes, hipStream_t stream,
+                        inim_batch_config* best, double* best_ms);
 
 /*
  * Waits for `stream`, returns the status word of the last call that used ws

@@ -54,6 +54,7 @@ def lib():
         L.oracle_deform.argtypes = [dp, i32, f64, dp]
         L.oracle_advect.argtypes = [dp, i32, dp, i64]
         L.oracle_regularize.argtypes = [dp, i64, i32, i32, i32, f64, f64]
+        L.oracle_regularize_probes.argtypes = [dp, i64, dp, i64, i32, i32, i32, f64, f64]
         _lib = L
     return _lib
 
@@ -146,6 +147,16 @@ def regularize(xy, res: int, iters: int, radius: int = 8, sigma: float = 0.0,
     xy = _f64(xy).reshape(-1, 2).copy()
     _check(lib().oracle_regularize(_p(xy), xy.shape[0], res, iters, radius, sigma, d0))
     return xy
+
+
+def regularize_probes(xy, probe, res: int, iters: int, radius: int = 8, sigma: float = 0.0,
+                      d0: float = -1.0) -> tuple[np.ndarray, np.ndarray]:
+    """The iteration with passive probe points moved by the same deformations
+    (the composite map at the probes); returns (samples, probes)."""
+    xy = _f64(xy).reshape(-1, 2).copy()
+    pr = _f64(probe).reshape(-1, 2).copy()
+    _check(lib().oracle_regularize_probes(_p(xy), xy.shape[0], _p(pr), pr.shape[0], res, iters, radius, sigma, d0))
+    return xy, pr
 
 
 def regularize_status(xy, res: int, iters: int, radius: int = 8, sigma: float = 0.0,

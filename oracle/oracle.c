@@ -399,11 +399,16 @@ int oracle_advect(const double* field, int N, double* xy, int64_t n) {
 /* ------------------------------------------------------------------------ */
 /* Sec. 4.3: the iteration.                                                   */
 /* ------------------------------------------------------------------------ */
-/* d0 < 0 selects the paper's choice n / N^2; sigma <= 0 selects r/2. */
-int oracle_regularize(double* xy, int64_t n, int N, int iters, int r, double sigma, double d0) {
-    if (!valid_res(N) || n < 0 || iters < 0 || r < 0) return ORACLE_EINVAL;
+/* d0 < 0 selects the paper's choice n / N^2; sigma <= 0 selects r/2.
+ * The m probe points (may be 0) are moved by the same deformation as the
+ * samples in every iteration but take no part in the density: they sample
+ * the composite map of all iterations (the deformed grid of Sec. 5). */
+static int regularize(double* xy, int64_t n, double* probe, int64_t m, int N, int iters, int r, double sigma,
+                      double d0) {
+    if (!valid_res(N) || n < 0 || m < 0 || iters < 0 || r < 0) return ORACLE_EINVAL;
     if (oracle_check_points(xy, n)) return ORACLE_EDOMAIN;
-    if (n == 0 || iters == 0) return ORACLE_OK;
+    if (n == 0 || iters == 0) return ORACLE_OK; /* no density: nothing moves */
+    if (oracle_check_points(probe, m)) return ORACLE_EDOMAIN;
     size_t NN = (size_t)N * (size_t)N;
     if (d0 < 0.0) d0 = (double)n / (double)NN;
     double* cnt = (double*)malloc(sizeof(double) * NN);
@@ -418,8 +423,19 @@ int oracle_regularize(double* xy, int64_t n, int N, int iters, int r, double sig
             if (st == ORACLE_OK) st = oracle_blur(cnt, N, r, sigma, dr); /* step 1 */
             if (st == ORACLE_OK) st = deform_with_defect(dr, N, d0, defect, field); /* steps 2-3 */
             if (st == ORACLE_OK) st = oracle_advect(field, N, xy, n);   /* step 3 */
+            if (st == ORACLE_OK && m > 0) st = oracle_advect(field, N, probe, m);
         }
     }
     free(cnt); free(dr); free(field); free(defect);
     return st;
+}
+
+int oracle_regularize(double* xy, int64_t n, int N, int iters, int r, double sigma, double d0) {
+    return regularize(xy, n, NULL, 0, N, iters, r, sigma, d0);
+}
+
+int oracle_regularize_probes(double* xy, int64_t n, double* probe, int64_t m, int N, int iters, int r,
+                             double sigma, double d0) {
+    if (m > 0 && probe == NULL) return ORACLE_EINVAL;
+    return regularize(xy, n, probe, m, N, iters, r, sigma, d0);
 }

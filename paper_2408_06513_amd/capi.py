@@ -29,7 +29,8 @@ EXPORTS = (
     "inim_default_params", "inim_strerror", "inim_last_error", "inim_workspace_size",
     "inim_inim_workspace_size", "inim_rasterize", "inim_inim_u32", "inim_inim_f32",
     "inim_deform", "inim_advect", "inim_regularize", "inim_regularize_timed", "inim_sync_status",
-    "inim_graph_create", "inim_graph_destroy", "inim_regularize_graph",
+    "inim_graph_create", "inim_graph_destroy", "inim_regularize_graph", "inim_regularize_probes",
+    "inim_batch_workspace_size", "inim_regularize_batch", "inim_batch_autotune",
 )
 
 
@@ -67,6 +68,14 @@ class Params(ctypes.Structure):
     _fields_ = [("radius", ctypes.c_int32), ("sigma", ctypes.c_float), ("d0", ctypes.c_double)]
 
 
+class BatchConfig(ctypes.Structure):
+    """Launch shape of a batched call (inim_batch_config)."""
+    _fields_ = [("waves_per_block", ctypes.c_int32), ("order", ctypes.c_int32)]
+
+    def __repr__(self):
+        return f"BatchConfig(waves_per_block={self.waves_per_block}, order={self.order})"
+
+
 _lib = None
 
 
@@ -101,6 +110,11 @@ def lib() -> ctypes.CDLL:
     L.inim_graph_create.argtypes = [ctypes.POINTER(vp)]
     L.inim_graph_destroy.argtypes = [vp]
     L.inim_regularize_graph.argtypes = [vp, i64, i32, i32, pp, vp, sz, vp, vp]
+    L.inim_regularize_probes.argtypes = [vp, i64, vp, i64, i32, i32, pp, vp, sz, vp]
+    bp = ctypes.POINTER(BatchConfig)
+    L.inim_batch_workspace_size.argtypes = [vp, vp, vp, i32, pp, ctypes.POINTER(sz)]
+    L.inim_regularize_batch.argtypes = [vp, vp, vp, i32, i32, pp, bp, vp, sz, vp, vp]
+    L.inim_batch_autotune.argtypes = [vp, vp, vp, i32, i32, pp, vp, sz, vp, bp, ctypes.POINTER(f64)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("inim_default_params", "inim_strerror", "inim_last_error"):
@@ -243,6 +257,25 @@ def regularize(xy: torch.Tensor, res: int, iters: int, radius: int = 8, sigma=No
     return xy
 
 
+def regularize_probes(xy: torch.Tensor, probe: torch.Tensor, res: int, iters: int, radius: int = 8, sigma=None,
+                      d0=None, ws=None, check: bool = True) -> tuple[torch.Tensor, torch.Tensor]:
+    """regularize, also moving the probe points (float32 [m, 2], same device)
+    by every iteration's deformation without splatting them: started at the
+    texel centres they return the composite map on the texel lattice."""
+    n = _xy(xy)
+    m = _xy(probe)
+    if probe.device != xy.device:
+        raise ValueError("probe and xy must be on the same device")
+    p = params(radius, sigma, d0)
+    if ws is None:
+        ws = workspace(workspace_size(res, n, radius, sigma, d0), xy.device)
+    _check(lib().inim_regularize_probes(_ptr(xy), n, _ptr(probe), m, res, iters, ctypes.byref(p), _ptr(ws),
+                                        ws.numel(), _stream(xy)))
+    if check:
+        _check(sync_status(ws))
+    return xy, probe
+
+
 def regularize_timed(xy: torch.Tensor, res: int, iters: int, radius: int = 8, sigma=None, d0=None,
                      ws=None) -> dict:
     """regularize with per-stage HIP-event timings (milliseconds, summed over iterations)."""
@@ -286,6 +319,54 @@ def regularize_graph(xy: torch.Tensor, res: int, iters: int, graph: Graph, ws: t
     if check:
         _check(sync_status(ws))
     return xy
+
+
+def _batch_arrays(xys, res):
+    if len(xys) != len(res):
+        raise ValueError("one raster size per plot")
+    ns = [_xy(t) for t in xys]
+    if len({t.device for t in xys}) > 1:
+        raise ValueError("all plots must be on one device")
+    k = len(xys)
+    return ((ctypes.c_void_p * k)(*[t.data_ptr() for t in xys]), (ctypes.c_int64 * k)(*ns),
+            (ctypes.c_int32 * k)(*[int(r) for r in res]), k)
+
+
+def batch_workspace_size(xys, res, radius: int = 8, sigma=None, d0=None) -> int:
+    a, n, r, k = _batch_arrays(xys, res)
+    p = params(radius, sigma, d0)
+    out = ctypes.c_size_t()
+    _check(lib().inim_batch_workspace_size(a, n, r, k, ctypes.byref(p), ctypes.byref(out)))
+    return out.value
+
+
+def regularize_batch(xys, res, iters: int, radius: int = 8, sigma=None, d0=None, cfg: BatchConfig | None = None,
+                     ws=None, graph: "Graph | None" = None, check: bool = True):
+    """Regularises every plot (xys[k]: float32 [n_k, 2] on one device, raster
+    res[k]) in shared launches, in place; same results as one regularize per plot."""
+    a, n, r, k = _batch_arrays(xys, res)
+    p = params(radius, sigma, d0)
+    if ws is None:
+        ws = workspace(batch_workspace_size(xys, res, radius, sigma, d0), xys[0].device)
+    _check(lib().inim_regularize_batch(a, n, r, k, iters, ctypes.byref(p), ctypes.byref(cfg) if cfg else None,
+                                       _ptr(ws), ws.numel(), graph.handle if graph else None, _stream(ws)))
+    if check:
+        _check(sync_status(ws))
+    return xys
+
+
+def batch_autotune(xys, res, iters: int, radius: int = 8, sigma=None, d0=None, ws=None) -> tuple[BatchConfig, float]:
+    """Times every launch shape of regularize_batch on these plots (the plots
+    are not modified); returns the fastest and its time in milliseconds."""
+    a, n, r, k = _batch_arrays(xys, res)
+    p = params(radius, sigma, d0)
+    if ws is None:
+        ws = workspace(batch_workspace_size(xys, res, radius, sigma, d0), xys[0].device)
+    best = BatchConfig()
+    ms = ctypes.c_double()
+    _check(lib().inim_batch_autotune(a, n, r, k, iters, ctypes.byref(p), _ptr(ws), ws.numel(), _stream(ws),
+                                     ctypes.byref(best), ctypes.byref(ms)))
+    return best, ms.value
 
 
 def sync_status(ws: torch.Tensor) -> int:

@@ -2,15 +2,18 @@
 // argument validation, workspace layout and the launch sequence of each call.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "inim.h"
 #include "inim_plan.h"
 #include "launch.h"
+#include "reg_layout.h"
 
 using namespace inim;
 
@@ -78,36 +81,6 @@ BlurTaps make_taps(int r, double sigma) {
     return t;
 }
 
-constexpr size_t kStatusBytes = 256;
-
-// Workspace of rasterize / advect / regularize.
-struct RegLayout {
-    size_t status, counts[2], density, field, defect, scratch, sxy, perm, rank, partial, total;
-    Geom g;
-    bool f32;  // integral images of the float density in double (radius > 0), or of the counts
-};
-
-RegLayout reg_layout(int32_t res, int64_t n, int radius) {
-    RegLayout L;
-    const size_t NN = (size_t)res * (size_t)res;
-    const size_t nn = n > 0 ? (size_t)n : 0;
-    L.f32 = radius > 0;
-    L.g = make_geom(res, L.f32 ? 8 : 4);
-    size_t o = 0;
-    L.status = o; o += kStatusBytes;
-    L.counts[0] = o; o += align256(NN * 4);
-    L.counts[1] = o; o += align256(NN * 4);
-    L.density = o; o += align256(NN * 4);
-    L.field = o; o += align256(NN * 8);
-    L.defect = o; o += align256(NN * 8);
-    L.scratch = o; o += inim_scratch_bytes(L.g, L.f32 ? 8 : 4);
-    L.sxy = o; o += align256(nn * 8);
-    L.perm = o; o += align256(nn * 4);
-    L.rank = o; o += align256(nn * 4);
-    L.partial = o; o += align256(scan_partials(NN) * 4);
-    L.total = o;
-    return L;
-}
 
 int check_ws(const void* ws, size_t ws_bytes, size_t need) {
     if (ws == nullptr) return fail(INIM_EWORKSPACE, "workspace is NULL");
@@ -137,8 +110,9 @@ struct StageEvents {
 // Iteration k reads the count raster counts[k % 2]; its advection splats the
 // moved samples into counts[(k+1) % 2], which the smoothing of iteration k has
 // zeroed.
-int enqueue_regularize(float* xy, int64_t n, int32_t res, int32_t iters, double d0, const BlurTaps& taps,
-                       const RegLayout& L, char* ws, hipStream_t st, StageEvents* ev, double* stage_ms) {
+int enqueue_regularize(float* xy, int64_t n, float* probe, int64_t m, int32_t res, int32_t iters, double d0,
+                       const BlurTaps& taps, const RegLayout& L, char* ws, hipStream_t st, StageEvents* ev,
+                       double* stage_ms) {
     int* status = reinterpret_cast<int*>(ws + L.status);
     uint32_t* counts[2] = {reinterpret_cast<uint32_t*>(ws + L.counts[0]), reinterpret_cast<uint32_t*>(ws + L.counts[1])};
     float* density = reinterpret_cast<float*>(ws + L.density);
@@ -154,6 +128,8 @@ int enqueue_regularize(float* xy, int64_t n, int32_t res, int32_t iters, double 
                              reinterpret_cast<uint32_t*>(ws + L.rank), counts[1],
                              reinterpret_cast<uint32_t*>(ws + L.partial), pts, perm, status, st);
     if (e != hipSuccess) return hip_fail(e, "sort by texel");
+    if (m > 0 && (e = launch_validate(reinterpret_cast<const float2*>(probe), m, status, st)) != hipSuccess)
+        return hip_fail(e, "validate probes");
     float2* defect = reinterpret_cast<float2*>(ws + L.defect);
     if ((e = launch_defect_field(res, defect, st)) != hipSuccess) return hip_fail(e, "defect field");
     if (ev) {
@@ -192,6 +168,9 @@ int enqueue_regularize(float* xy, int64_t n, int32_t res, int32_t iters, double 
         if (e != hipSuccess) return hip_fail(e, "integral images + deformation");
         if (ev) (void)hipEventRecord(ev->it[3], st);
         if ((e = launch_advect(field, res, pts, n, nxt, status, st)) != hipSuccess) return hip_fail(e, "advect");
+        if (m > 0 && (e = launch_advect(field, res, reinterpret_cast<float2*>(probe), m, nullptr, status, st)) !=
+                         hipSuccess)
+            return hip_fail(e, "advect probes");
         if (ev) {
             (void)hipEventRecord(ev->it[4], st);
             if (hipEventSynchronize(ev->it[4]) != hipSuccess) return fail(INIM_EHIP, "hipEventSynchronize failed");
@@ -215,11 +194,13 @@ int enqueue_regularize(float* xy, int64_t n, int32_t res, int32_t iters, double 
     return INIM_OK;
 }
 
-int regularize_impl(float* xy, int64_t n, int32_t res, int32_t iters, const inim_params* p, void* ws,
-                    size_t ws_bytes, hipStream_t stream, double* stage_ms) {
+int regularize_impl(float* xy, int64_t n, float* probe, int64_t m, int32_t res, int32_t iters, const inim_params* p,
+                    void* ws, size_t ws_bytes, hipStream_t stream, double* stage_ms) {
     int s;
     if ((s = check_res(res)) != INIM_OK) return s;
     if ((s = check_xy(xy, n)) != INIM_OK) return s;
+    if (m < 0) return fail(INIM_EINVAL, "m=%lld is negative", (long long)m);
+    if (m > 0 && probe == nullptr) return fail(INIM_EINVAL, "probe is NULL with m=%lld", (long long)m);
     if (iters < 0) return fail(INIM_EINVAL, "iters=%d is negative", (int)iters);
     Params P;
     if ((s = resolve_params(p, P)) != INIM_OK) return s;
@@ -232,7 +213,8 @@ int regularize_impl(float* xy, int64_t n, int32_t res, int32_t iters, const inim
     }
     const double d0 = P.d0 < 0.0 ? (double)n / ((double)res * (double)res) : P.d0;
     const BlurTaps taps = make_taps(P.radius, P.sigma);
-    if (stage_ms == nullptr) return enqueue_regularize(xy, n, res, iters, d0, taps, L, (char*)ws, stream, nullptr, nullptr);
+    if (stage_ms == nullptr)
+        return enqueue_regularize(xy, n, probe, m, res, iters, d0, taps, L, (char*)ws, stream, nullptr, nullptr);
 
     StageEvents ev;
     hipEvent_t t0, t1;
@@ -240,7 +222,7 @@ int regularize_impl(float* xy, int64_t n, int32_t res, int32_t iters, const inim
     for (auto* h : all)
         if (hipEventCreate(h) != hipSuccess) return fail(INIM_EHIP, "hipEventCreate failed");
     (void)hipEventRecord(t0, stream);
-    s = enqueue_regularize(xy, n, res, iters, d0, taps, L, (char*)ws, stream, &ev, stage_ms);
+    s = enqueue_regularize(xy, n, probe, m, res, iters, d0, taps, L, (char*)ws, stream, &ev, stage_ms);
     (void)hipEventRecord(t1, stream);
     if (s == INIM_OK && hipEventSynchronize(t1) == hipSuccess) {
         float ms = 0.0f;
@@ -249,6 +231,154 @@ int regularize_impl(float* xy, int64_t n, int32_t res, int32_t iters, const inim
     }
     for (auto* h : all) (void)hipEventDestroy(*h);
     return s;
+}
+
+}  // namespace
+
+namespace {
+
+// ------------------------------------------------------------------ batched plots
+// The plots of one batched call that have samples (plots with n == 0 are
+// left untouched, as inim_regularize leaves them), in input order.
+struct BatchPlan {
+    BatchArgs a;
+    int index[kMaxBatch];  // input position of each active plot
+    unsigned blocks[kBStages];
+    size_t total;
+    BlurTaps taps;
+};
+
+int batch_plan(float* const* xy, const int64_t* n, const int32_t* res, int32_t count, const inim_params* p,
+               const inim_batch_config* cfg, BatchPlan& B) {
+    int s;
+    if (count < 0 || count > kMaxBatch) return fail(INIM_EINVAL, "count=%d outside [0, %d]", (int)count, kMaxBatch);
+    if (count > 0 && (xy == nullptr || n == nullptr || res == nullptr))
+        return fail(INIM_EINVAL, "xy, n or res is NULL");
+    Params P;
+    if ((s = resolve_params(p, P)) != INIM_OK) return s;
+    if (P.radius < 1) return fail(INIM_EINVAL, "batched plots need radius >= 1");
+    const int wpb = (cfg && cfg->waves_per_block) ? cfg->waves_per_block : 4;
+    if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8)
+        return fail(INIM_EINVAL, "waves_per_block=%d is not 1, 2, 4 or 8", (int)wpb);
+    const int order = cfg ? cfg->order : 0;
+    if (order != 0 && order != 1) return fail(INIM_EINVAL, "order=%d is not 0 or 1", (int)order);
+    std::memset(&B.a, 0, sizeof B.a);
+    int m = 0;
+    for (int k = 0; k < count; ++k) {
+        if ((s = check_res(res[k])) != INIM_OK) return s;
+        if (res[k] < 64 || res[k] > 2048) return fail(INIM_EINVAL, "plot %d: res=%d outside [64, 2048]", k, (int)res[k]);
+        if ((s = check_xy(xy[k], n[k])) != INIM_OK) return s;
+        if (n[k] == 0) continue;
+        B.a.in[m].xy = xy[k];
+        B.a.in[m].n = n[k];
+        B.a.in[m].N = res[k];
+        B.index[m] = k;
+        ++m;
+    }
+    B.a.count = m;
+    B.a.wpb = wpb;
+    B.a.radius = P.radius;
+    B.a.d0 = P.d0;
+    for (int q = 0; q < m; ++q) B.a.order[q] = q;
+    if (order == 1)  // larger rasters first (then more samples), ties in input order
+        std::stable_sort(B.a.order, B.a.order + m, [&](int u, int v) {
+            const BatchInput &U = B.a.in[u], &V = B.a.in[v];
+            return U.N != V.N ? U.N > V.N : U.n > V.n;
+        });
+    for (int st = 0; st < kBStages; ++st) {
+        unsigned run = 0;
+        for (int q = 0; q < m; ++q) {
+            bool own = true;
+            for (int r = 0; r < q; ++r)
+                if (B.a.in[r].N == B.a.in[q].N) { own = false; break; }
+            run += batch_stage_blocks(st, B.a.in[q].N, B.a.in[q].n, wpb, own);
+        }
+        B.blocks[st] = run;
+    }
+    B.total = batch_plot_offset(m, B.a.in, P.radius);
+    B.taps = make_taps(P.radius, P.sigma);
+    return INIM_OK;
+}
+
+// The batched call on `st`; with `dry` the results stay in the workspace
+// (the samples' positions in the caller's arrays are not written).
+int enqueue_batch(BatchPlan& B, int32_t iters, char* ws, hipStream_t st, bool dry) {
+    B.a.ws = ws;
+    int* status = reinterpret_cast<int*>(ws);
+    BatchTable* T = reinterpret_cast<BatchTable*>(ws + batch_table_offset());
+    hipError_t e = launch_batch_init(B.a, T, st);
+    for (int s : {kBFill, kBSplatRank, kBScanReduce, kBScanPartials, kBScanDown, kBScatter})
+        if (e == hipSuccess) e = launch_batch_raster(s, T, B.blocks[s], 0, iters, status, st);
+    if (e == hipSuccess) e = launch_batch_inim(kBDefect, T, B.blocks[kBDefect], B.a.wpb, B.taps, 0, iters, status, st);
+    for (int it = 0; it < iters && e == hipSuccess; ++it) {
+        for (int s : {kBBlurAgg, kBScanCol, kBScanDiag, kBMarg, kBDeform})
+            if (e == hipSuccess) e = launch_batch_inim(s, T, B.blocks[s], B.a.wpb, B.taps, it, iters, status, st);
+        if (e == hipSuccess) e = launch_batch_raster(kBAdvect, T, B.blocks[kBAdvect], it, iters, status, st);
+    }
+    if (e == hipSuccess && !dry) e = launch_batch_raster(kBUnpermute, T, B.blocks[kBUnpermute], 0, iters, status, st);
+    return e == hipSuccess ? INIM_OK : hip_fail(e, "batched regularisation");
+}
+
+}  // namespace
+
+struct inim_graph_cache {
+    bool valid = false;
+    std::vector<char> key;  // every argument of the captured call, as bytes
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    void drop() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        valid = false;
+    }
+};
+
+namespace {
+
+// Argument bytes of a call, the key of a captured graph.
+struct KeyWriter {
+    std::vector<char> bytes;
+    template <typename T>
+    KeyWriter& put(const T& v) {
+        const char* p = reinterpret_cast<const char*>(&v);
+        bytes.insert(bytes.end(), p, p + sizeof(T));
+        return *this;
+    }
+};
+
+// Launches the graph of G on `stream`, first capturing `enqueue` (on G's
+// private stream) when `key` differs from the captured call's.
+template <typename Enqueue>
+int graph_launch(inim_graph_cache* G, const std::vector<char>& key, hipStream_t stream, Enqueue enqueue) {
+    if (!(G->valid && G->key == key)) {
+        G->drop();
+        if (G->capture == nullptr && hipStreamCreateWithFlags(&G->capture, hipStreamNonBlocking) != hipSuccess)
+            return fail(INIM_EHIP, "hipStreamCreate failed");
+        hipError_t e = hipStreamBeginCapture(G->capture, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        const int s = enqueue(G->capture);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(G->capture, &g);
+        if (s != INIM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        G->graph = g;
+        e = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            G->drop();
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        G->valid = true;
+        G->key = key;
+    }
+    hipError_t e = hipGraphLaunch(G->exec, stream);
+    return e == hipSuccess ? INIM_OK : hip_fail(e, "hipGraphLaunch");
 }
 
 }  // namespace
@@ -390,35 +520,19 @@ int inim_advect(const float* field, int32_t res, float* xy, int64_t n, void* ws,
 
 int inim_regularize(float* xy, int64_t n, int32_t res, int32_t iters, const inim_params* p, void* ws,
                     size_t ws_bytes, hipStream_t stream) {
-    return regularize_impl(xy, n, res, iters, p, ws, ws_bytes, stream, nullptr);
+    return regularize_impl(xy, n, nullptr, 0, res, iters, p, ws, ws_bytes, stream, nullptr);
+}
+
+int inim_regularize_probes(float* xy, int64_t n, float* probe, int64_t m, int32_t res, int32_t iters,
+                           const inim_params* p, void* ws, size_t ws_bytes, hipStream_t stream) {
+    return regularize_impl(xy, n, probe, m, res, iters, p, ws, ws_bytes, stream, nullptr);
 }
 
 int inim_regularize_timed(float* xy, int64_t n, int32_t res, int32_t iters, const inim_params* p, void* ws,
                           size_t ws_bytes, hipStream_t stream, double* stage_ms) {
     if (stage_ms == nullptr) return fail(INIM_EINVAL, "stage_ms is NULL");
-    return regularize_impl(xy, n, res, iters, p, ws, ws_bytes, stream, stage_ms);
+    return regularize_impl(xy, n, nullptr, 0, res, iters, p, ws, ws_bytes, stream, stage_ms);
 }
-
-struct inim_graph_cache {
-    bool valid = false;
-    float* xy = nullptr;
-    int64_t n = 0;
-    int32_t res = 0, iters = 0;
-    Params P{};
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
-    hipStream_t capture = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-
-    void drop() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        exec = nullptr;
-        graph = nullptr;
-        valid = false;
-    }
-};
 
 int inim_graph_create(void** graph) {
     if (graph == nullptr) return fail(INIM_EINVAL, "graph is NULL");
@@ -447,37 +561,88 @@ int inim_regularize_graph(float* xy, int64_t n, int32_t res, int32_t iters, cons
     if ((s = resolve_params(p, P)) != INIM_OK) return s;
     const RegLayout L = reg_layout(res, n, P.radius);
     if ((s = check_ws(ws, ws_bytes, L.total)) != INIM_OK) return s;
-    if (n == 0 || iters == 0) return regularize_impl(xy, n, res, iters, p, ws, ws_bytes, stream, nullptr);
-    const bool same = G->valid && G->xy == xy && G->n == n && G->res == res && G->iters == iters &&
-                      G->P.radius == P.radius && G->P.sigma == P.sigma && G->P.d0 == P.d0 && G->ws == ws &&
-                      G->ws_bytes == ws_bytes;
-    if (!same) {
-        G->drop();
-        if (G->capture == nullptr && hipStreamCreateWithFlags(&G->capture, hipStreamNonBlocking) != hipSuccess)
-            return fail(INIM_EHIP, "hipStreamCreate failed");
-        const double d0 = P.d0 < 0.0 ? (double)n / ((double)res * (double)res) : P.d0;
-        const BlurTaps taps = make_taps(P.radius, P.sigma);
-        hipError_t e = hipStreamBeginCapture(G->capture, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        s = enqueue_regularize(xy, n, res, iters, d0, taps, L, (char*)ws, G->capture, nullptr, nullptr);
-        hipGraph_t g = nullptr;
-        e = hipStreamEndCapture(G->capture, &g);
-        if (s != INIM_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return s;
-        }
-        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-        G->graph = g;
-        e = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            G->drop();
-            return hip_fail(e, "hipGraphInstantiate");
-        }
-        G->valid = true;
-        G->xy = xy; G->n = n; G->res = res; G->iters = iters; G->P = P; G->ws = ws; G->ws_bytes = ws_bytes;
+    if (n == 0 || iters == 0) return regularize_impl(xy, n, nullptr, 0, res, iters, p, ws, ws_bytes, stream, nullptr);
+    KeyWriter k;
+    k.put(1).put(xy).put(n).put(res).put(iters).put(P.radius).put(P.sigma).put(P.d0).put(ws).put(ws_bytes);
+    const double d0 = P.d0 < 0.0 ? (double)n / ((double)res * (double)res) : P.d0;
+    const BlurTaps taps = make_taps(P.radius, P.sigma);
+    return graph_launch(G, k.bytes, stream, [&](hipStream_t cs) {
+        return enqueue_regularize(xy, n, nullptr, 0, res, iters, d0, taps, L, (char*)ws, cs, nullptr, nullptr);
+    });
+}
+
+int inim_batch_workspace_size(float* const* xy, const int64_t* n, const int32_t* res, int32_t count,
+                              const inim_params* p, size_t* bytes) {
+    if (bytes == nullptr) return fail(INIM_EINVAL, "bytes is NULL");
+    BatchPlan B;
+    const int s = batch_plan(xy, n, res, count, p, nullptr, B);
+    if (s != INIM_OK) return s;
+    *bytes = B.total;
+    return INIM_OK;
+}
+
+int inim_regularize_batch(float* const* xy, const int64_t* n, const int32_t* res, int32_t count, int32_t iters,
+                          const inim_params* p, const inim_batch_config* cfg, void* ws, size_t ws_bytes, void* graph,
+                          hipStream_t stream) {
+    BatchPlan B;
+    int s = batch_plan(xy, n, res, count, p, cfg, B);
+    if (s != INIM_OK) return s;
+    if (iters < 0) return fail(INIM_EINVAL, "iters=%d is negative", (int)iters);
+    if ((s = check_ws(ws, ws_bytes, B.total)) != INIM_OK) return s;
+    if (B.a.count == 0 || iters == 0) {
+        hipError_t e = launch_fill(nullptr, 0, reinterpret_cast<int*>(ws), true, stream);
+        return e == hipSuccess ? INIM_OK : hip_fail(e, "fill");
     }
-    hipError_t e = hipGraphLaunch(G->exec, stream);
-    return e == hipSuccess ? INIM_OK : hip_fail(e, "hipGraphLaunch");
+    if (graph == nullptr) return enqueue_batch(B, iters, (char*)ws, stream, false);
+    KeyWriter k;
+    k.put(2).put(iters).put(ws).put(ws_bytes).put(B.a).put(B.taps);
+    return graph_launch(static_cast<inim_graph_cache*>(graph), k.bytes, stream,
+                        [&](hipStream_t cs) { return enqueue_batch(B, iters, (char*)ws, cs, false); });
+}
+
+int inim_batch_autotune(float* const* xy, const int64_t* n, const int32_t* res, int32_t count, int32_t iters,
+                        const inim_params* p, void* ws, size_t ws_bytes, hipStream_t stream,
+                        inim_batch_config* best, double* best_ms) {
+    if (best == nullptr) return fail(INIM_EINVAL, "best is NULL");
+    BatchPlan B;
+    int s = batch_plan(xy, n, res, count, p, nullptr, B);
+    if (s != INIM_OK) return s;
+    if (iters < 1) return fail(INIM_EINVAL, "iters=%d: tuning needs at least one iteration", (int)iters);
+    if ((s = check_ws(ws, ws_bytes, B.total)) != INIM_OK) return s;
+    best->waves_per_block = 4;
+    best->order = 0;
+    if (best_ms) *best_ms = 0.0;
+    if (B.a.count == 0) return INIM_OK;
+    hipEvent_t t0, t1;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
+        return fail(INIM_EHIP, "hipEventCreate failed");
+    double bestv = 1e300;
+    for (int order = 0; order < 2 && s == INIM_OK; ++order) {
+        for (int wpb : {1, 2, 4, 8}) {
+            const inim_batch_config c{wpb, order};
+            BatchPlan C;
+            if ((s = batch_plan(xy, n, res, count, p, &c, C)) != INIM_OK) break;
+            float ms_min = 1e30f;
+            for (int rep = 0; rep < 3 && s == INIM_OK; ++rep) {  // the first run warms up
+                (void)hipEventRecord(t0, stream);
+                s = enqueue_batch(C, iters, (char*)ws, stream, true);
+                (void)hipEventRecord(t1, stream);
+                if (s == INIM_OK && hipEventSynchronize(t1) != hipSuccess) s = fail(INIM_EHIP, "hipEventSynchronize");
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, t0, t1);
+                if (rep > 0 && ms < ms_min) ms_min = ms;
+            }
+            if (s != INIM_OK) break;
+            if (ms_min < bestv) {
+                bestv = ms_min;
+                *best = c;
+            }
+        }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (s == INIM_OK && best_ms) *best_ms = bestv;
+    return s;
 }
 
 int inim_sync_status(void* ws, hipStream_t stream) {

@@ -48,6 +48,55 @@ __device__ __forceinline__ double fx_to_double(u128 v) {
     return neg ? -d : d;
 }
 
+// The fixed-point value as a float, correctly rounded (to nearest, ties to
+// even) in one step: the 24 bits below the leading one, then the round bit
+// and a sticky bit of everything further down.  |value| >= 2^-64 always
+// gives a normal float.
+__device__ __noinline__ float fx_to_float_exact(u128 v) {
+    const bool neg = (int64_t)(uint64_t)(v >> 64) < 0;
+    if (neg) v = (u128)0 - v;
+    const uint64_t hi = (uint64_t)(v >> 64), lo = (uint64_t)v;
+    if ((hi | lo) == 0) return 0.0f;
+    uint64_t top;  // the magnitude shifted so that its leading one is bit 63
+    bool sticky;   // a one below the 64 bits of `top`
+    int e;         // the leading one's weight is 2^e
+    if (hi != 0) {
+        const int lz = __clzll((long long)hi);
+        top = lz ? (hi << lz) | (lo >> (64 - lz)) : hi;
+        sticky = (lz ? (lo << lz) : lo) != 0;
+        e = 63 - lz;
+    } else {
+        const int lz = __clzll((long long)lo);
+        top = lo << lz;
+        sticky = false;
+        e = -1 - lz;
+    }
+    uint32_t mant = (uint32_t)(top >> 40);  // 24 bits, leading one included
+    const uint64_t rest = top & ((1ull << 40) - 1), half = 1ull << 39;
+    if (rest > half || (rest == half && (sticky || (mant & 1u)))) {
+        if (++mant == (1u << 24)) {
+            mant >>= 1;
+            ++e;
+        }
+    }
+    const uint32_t bits = ((uint32_t)neg << 31) | ((uint32_t)(e + 127) << 23) | (mant & 0x7FFFFFu);
+    return __uint_as_float(bits);
+}
+
+// The same result, mostly without the bit scan: for a non-negative value the
+// sum of its two halves converted to double is within 1.5 units in the last
+// place of double of the exact value, so its float rounding is the correct
+// one unless it lies that close to a midpoint between two floats (whose
+// double has 0x10000000 in the 29 bits below the float's mantissa); negative
+// values and those near a midpoint take the exact conversion.
+__device__ __forceinline__ float fx_to_float(u128 v) {
+    const uint64_t hi = (uint64_t)(v >> 64), lo = (uint64_t)v;
+    const double d = (double)hi + (double)lo * 0x1p-64;
+    const uint32_t low = (uint32_t)(uint64_t)__double_as_longlong(d) & 0x1FFFFFFFu;
+    if ((int64_t)hi < 0 || low - 0x0FFFFFFEu <= 4u) return fx_to_float_exact(v);
+    return (float)d;
+}
+
 // ---------------------------------------------------------------- accumulators
 // uint32 rasters accumulate modulo 2^32 (exact below 2^32); float rasters in
 // the 128-bit fixed point above where exact planes are required, or in double
@@ -64,7 +113,7 @@ __device__ __forceinline__ double to_f64(double a) { return a; }
 
 template <typename Tout, typename Acc> __device__ __forceinline__ Tout narrow(Acc a);
 template <> __device__ __forceinline__ uint32_t narrow<uint32_t, uint32_t>(uint32_t a) { return a; }
-template <> __device__ __forceinline__ float narrow<float, u128>(u128 a) { return (float)fx_to_double(a); }
+template <> __device__ __forceinline__ float narrow<float, u128>(u128 a) { return fx_to_float(a); }
 template <> __device__ __forceinline__ float narrow<float, double>(double a) { return (float)a; }
 
 // ---------------------------------------------------------------- wave64 ops
@@ -323,7 +372,8 @@ __device__ __forceinline__ float2 deform_texel_defect(const Planes8& R, const Ma
 // (partitions of Sec. 3.1), in the accumulation type.  Regions that are empty
 // by construction (beta on the last row, delta on the last column, gamma on
 // either, beta_t on the first column, gamma_t on the last row, delta_t on the
-// last column) are set to exactly zero.
+// last column) come out exactly zero from the integer accumulators (both
+// terms are exact sums of the same texels); in double they are set to zero.
 template <typename Acc>
 struct Compl {
     Acc b, g, d, bt, gt, dt;
@@ -333,12 +383,18 @@ template <typename Acc>
 __device__ __forceinline__ Compl<Acc> complements(Acc al, Acc at, Acc X, Acc Y, Acc U, Acc V, Acc C,
                                                   int i, int j, int N) {
     Compl<Acc> o;
-    o.b = (j == N - 1) ? Acc(0) : Acc(X - al);
-    o.d = (i == N - 1) ? Acc(0) : Acc(Y - al);
-    o.g = (i == N - 1 || j == N - 1) ? Acc(0) : Acc(C - X - Y + al);
-    o.bt = (i == 0) ? Acc(0) : Acc(U - at);
-    o.dt = (i == N - 1) ? Acc(0) : Acc(V - at);
-    o.gt = (j == N - 1) ? Acc(0) : Acc(C - U - V + at);
+    o.b = X - al;
+    o.d = Y - al;
+    o.g = (C - X) - Y + al;
+    o.bt = U - at;
+    o.dt = V - at;
+    o.gt = (C - U) - V + at;
+    if constexpr (__is_same(Acc, double)) {
+        if (j == N - 1) { o.b = 0.0; o.gt = 0.0; }
+        if (i == N - 1) { o.d = 0.0; o.dt = 0.0; }
+        if (i == N - 1 || j == N - 1) o.g = 0.0;
+        if (i == 0) o.bt = 0.0;
+    }
     return o;
 }
 

@@ -2,6 +2,7 @@
 // uses; shared by the kernels and the host-side C ABI.
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -47,11 +48,11 @@ struct Carry {
     Acc *cpin, *ain, *Lin, *Rin, *AC, *U, *V;
 };
 
-inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // acc_bytes: 4 for uint32 rasters, 8 or 16 for float rasters (wider
 // accumulators need more registers per column, so float tiles are narrower).
-inline Geom make_geom(int N, int acc_bytes = 4, int q_hint = 0, int h_hint = 0) {
+__host__ __device__ inline Geom make_geom(int N, int acc_bytes = 4, int q_hint = 0, int h_hint = 0) {
     Geom g;
     g.N = N;
     int Q, H;
@@ -89,14 +90,14 @@ inline Geom make_geom(int N, int acc_bytes = 4, int q_hint = 0, int h_hint = 0) 
     return g;
 }
 
-inline bool geom_ok(const Geom& g) {
+__host__ __device__ inline bool geom_ok(const Geom& g) {
     return g.W >= g.H && g.B <= 256 && g.W % g.Q == 0 && g.W / g.Q <= 64 && g.N % g.W == 0 &&
            g.N % g.H == 0 && g.H <= 128 && (g.Q == 1 || g.Q == 2 || g.Q == 4);
 }
 
 // Bytes of the aggregate and carry arrays for accumulator size `acc`
 // (4 for uint32 rasters; 8 (double) or 16 (128-bit fixed point) for float rasters).
-inline size_t inim_scratch_bytes(const Geom& g, size_t acc) {
+__host__ __device__ inline size_t inim_scratch_bytes(const Geom& g, size_t acc) {
     const size_t N = (size_t)g.N;
     size_t s = 0;
     s += 4 * align256((size_t)g.B * N * acc);                 // colsum tcsp tLend tRend
@@ -108,7 +109,7 @@ inline size_t inim_scratch_bytes(const Geom& g, size_t acc) {
 }
 
 template <typename Acc>
-inline void carve(const Geom& g, char* base, Agg<Acc>& A, Carry<Acc>& K) {
+__host__ __device__ inline void carve(const Geom& g, char* base, Agg<Acc>& A, Carry<Acc>& K) {
     const size_t N = (size_t)g.N;
     const size_t col = align256((size_t)g.B * N * sizeof(Acc));
     const size_t edge = align256((size_t)g.B * g.T * g.H * sizeof(Acc));

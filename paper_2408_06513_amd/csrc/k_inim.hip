@@ -22,6 +22,7 @@
 //                 deformation of Sec. 4.2 directly.
 #include <hip/hip_runtime.h>
 
+#include "batch_plan.h"
 #include "blur_tile.h"
 #include "device_common.h"
 #include "inim_plan.h"
@@ -162,15 +163,16 @@ __global__ __launch_bounds__(256) void k_inim_aggregate(const Tin* __restrict__ 
 // keeps the tile in LDS, optionally zeroes the same texels of the next
 // iteration's count raster, then its first wave runs the aggregate over the
 // tile rows from LDS.
+// Kernel bodies take their block coordinates explicitly: the single-raster
+// kernels pass blockIdx, the batched kernels of a scatterplot matrix pass the
+// block's place among the blocks of its plot.
 template <typename Acc>
-__global__ __launch_bounds__(256) void k_blur_aggregate(const uint32_t* __restrict__ counts, float* __restrict__ density,
-                                                        uint32_t* __restrict__ zero_next, BlurTaps taps, Geom g,
-                                                        Agg<Acc> A, const int* status) {
-    extern __shared__ float lds[];
-    __shared__ float tile[kBY][kBX];
-    if (failed(status)) return;
+__device__ __forceinline__ void blur_aggregate_body(const uint32_t* __restrict__ counts, float* __restrict__ density,
+                                                    uint32_t* __restrict__ zero_next, const BlurTaps& taps,
+                                                    const Geom& g, const Agg<Acc>& A, float* lds,
+                                                    float (&tile)[kBY][kBX], int bx, int by) {
     const int N = g.N;
-    const int ox = blockIdx.x * kBX, oy = blockIdx.y * kBY;
+    const int ox = bx * kBX, oy = by * kBY;
     blur_tile(counts, N, taps, ox, oy, lds, [&](int row, int cc, float v) {
         const size_t k = (size_t)(oy + row) * N + ox + cc;
         density[k] = v;
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(256) void k_blur_aggregate(const uint32_t* __restri
     });
     __syncthreads();
     const int lane = lane_id(), wave = (int)(threadIdx.x >> 6);
-    const int b = blockIdx.y, c = blockIdx.x;
+    const int b = by, c = bx;
     const size_t ebase = ((size_t)b * g.T + c) * g.H;
     if (wave == 0) {
         // column prefixes and the two diagonal sums, row by row; the edge values
@@ -217,6 +219,16 @@ __global__ __launch_bounds__(256) void k_blur_aggregate(const uint32_t* __restri
     }
 }
 
+template <typename Acc>
+__global__ __launch_bounds__(256) void k_blur_aggregate(const uint32_t* __restrict__ counts, float* __restrict__ density,
+                                                        uint32_t* __restrict__ zero_next, BlurTaps taps, Geom g,
+                                                        Agg<Acc> A, const int* status) {
+    extern __shared__ float lds[];
+    __shared__ float tile[kBY][kBX];
+    if (failed(status)) return;
+    blur_aggregate_body<Acc>(counts, density, zero_next, taps, g, A, lds, tile, blockIdx.x, blockIdx.y);
+}
+
 // ------------------------------------------------------------------ passes 2 and 3
 // The carries are prefix sums over bands.  Each workgroup takes 64 chains
 // (one per lane) and spreads the B bands over its waves, kScanWaves at most,
@@ -234,19 +246,18 @@ __host__ __device__ inline int scan_per_wave(int B) { return (B + scan_waves(B) 
 // the band's column sums: the in-tile prefix tcsp plus the totals of the tiles
 // to the left (a wave-wide sum; tiles are at least 64 columns wide, so all
 // lanes of a wave lie in one tile, or N < 64 and there is one tile).
+// Blocks of 64 * waves threads, waves >= scan_waves(g.B); extra waves only
+// take part in the barriers.
 template <typename Acc>
-__global__ __launch_bounds__(1024) void k_inim_scan_col(Geom g, Agg<Acc> A, Carry<Acc> K, const int* status) {
-    extern __shared__ unsigned char smem_raw[];
-    if (failed(status)) return;
-    Acc* tot = reinterpret_cast<Acc*>(smem_raw);  // [waves][2][64]
-    __shared__ Acc left[kScanWaves * kScanMaxP];     // per band: totals of the tiles left of c
+__device__ __forceinline__ void scan_col_body(const Geom& g, const Agg<Acc>& A, const Carry<Acc>& K, Acc* tot,
+                                              Acc* left, int bx) {
     const int lane = lane_id();
     const int wave = (int)(threadIdx.x >> 6);
     const int nw = scan_waves(g.B), P = scan_per_wave(g.B);
-    const int i = blockIdx.x * 64 + lane;
+    const int i = bx * 64 + lane;
     const bool valid = i < g.N;
     const int ii = valid ? i : 0;
-    const int c = (blockIdx.x * 64) / g.W;  // the block's 64 columns lie in one tile
+    const int c = (bx * 64) / g.W;  // the block's 64 columns lie in one tile
     const size_t N = (size_t)g.N;
     const int b0 = wave * P;
     for (int b = threadIdx.x; b < g.B; b += blockDim.x) {
@@ -297,6 +308,14 @@ __global__ __launch_bounds__(1024) void k_inim_scan_col(Geom g, Agg<Acc> A, Carr
     }
 }
 
+template <typename Acc>
+__global__ __launch_bounds__(1024) void k_inim_scan_col(Geom g, Agg<Acc> A, Carry<Acc> K, const int* status) {
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ Acc left[kScanWaves * kScanMaxP];  // per band: totals of the tiles left of c
+    if (failed(status)) return;
+    scan_col_body<Acc>(g, A, K, reinterpret_cast<Acc*>(smem_raw), left, blockIdx.x);
+}
+
 // Pass 3.  blockIdx.y = 0 follows the up-left chains s = t - N (columns
 // i = s + (b+1)H), blockIdx.y = 1 the up-right chains s = t (columns
 // i = s - (b+1)H), t = 0..2N:
@@ -311,12 +330,11 @@ __global__ __launch_bounds__(1024) void k_inim_scan_col(Geom g, Agg<Acc> A, Carr
 // tiles of its band AC[b][c][r] = alpha(cW-1, j) = ain[b][cW-1] + sum over
 // c' < c of trow[b][c'][r], for c = 0..T.
 template <typename Acc>
-__global__ __launch_bounds__(1024) void k_inim_scan_diag(Geom g, Agg<Acc> A, Carry<Acc> K, const int* status) {
-    extern __shared__ unsigned char smem_raw[];
-    if (failed(status)) return;
+__device__ __forceinline__ void scan_diag_body(const Geom& g, const Agg<Acc>& A, const Carry<Acc>& K, Acc* tot,
+                                               int bx, int by) {
     const int N = g.N, H = g.H, W = g.W, T = g.T;
-    if (blockIdx.y == 2) {
-        const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (by == 2) {
+        const int j = bx * blockDim.x + threadIdx.x;
         if (j >= N) return;
         const int b = j / H, r = j - b * H;
         const Acc* ainb = K.ain + (size_t)b * N;
@@ -331,12 +349,11 @@ __global__ __launch_bounds__(1024) void k_inim_scan_diag(Geom g, Agg<Acc> A, Car
         }
         return;
     }
-    Acc* tot = reinterpret_cast<Acc*>(smem_raw);  // [waves][64]
     const int lane = lane_id();
     const int wave = (int)(threadIdx.x >> 6);
     const int P = scan_per_wave(g.B);
-    const int t = blockIdx.x * 64 + lane;
-    const bool left_chain = blockIdx.y == 0;
+    const int t = bx * 64 + lane;
+    const bool left_chain = by == 0;
     const bool tval = t <= 2 * N;
     const int s = left_chain ? t - N : t;
     const int b0 = wave * P;
@@ -383,6 +400,13 @@ __global__ __launch_bounds__(1024) void k_inim_scan_diag(Geom g, Agg<Acc> A, Car
     }
 }
 
+template <typename Acc>
+__global__ __launch_bounds__(1024) void k_inim_scan_diag(Geom g, Agg<Acc> A, Carry<Acc> K, const int* status) {
+    extern __shared__ unsigned char smem_raw[];
+    if (failed(status)) return;
+    scan_diag_body<Acc>(g, A, K, reinterpret_cast<Acc*>(smem_raw), blockIdx.x, blockIdx.y);
+}
+
 // ------------------------------------------------------------------ marginals
 // U(u) = sum over i'+j' <= u:  for u < N it is R(0, u); beyond, R(u-N+1, N-1)
 // misses exactly the columns left of u-N+1, i.e. X(u-N).
@@ -427,9 +451,8 @@ __device__ __forceinline__ Acc marg_Y(const Geom& g, const Carry<Acc>& K, int j)
 // The diagonal marginals U and V into the carry arrays (used by the final
 // pass), and, when `marg` is not null, all marginals as doubles.
 template <typename Acc>
-__global__ __launch_bounds__(256) void k_inim_marg(Geom g, Agg<Acc> A, Carry<Acc> K, double* marg, const int* status) {
-    if (failed(status)) return;
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void marg_body(const Geom& g, const Agg<Acc>& A, const Carry<Acc>& K, double* marg, int bx) {
+    const int o = bx * blockDim.x + threadIdx.x;
     const int N = g.N, M = 2 * N - 1;
     if (o >= 2 * N + 2 * M + 1) return;
     Acc v;
@@ -449,12 +472,21 @@ __global__ __launch_bounds__(256) void k_inim_marg(Geom g, Agg<Acc> A, Carry<Acc
     if (marg != nullptr) marg[o] = to_f64(v);
 }
 
+template <typename Acc>
+__global__ __launch_bounds__(256) void k_inim_marg(Geom g, Agg<Acc> A, Carry<Acc> K, double* marg, const int* status) {
+    if (failed(status)) return;
+    marg_body<Acc>(g, A, K, marg, blockIdx.x);
+}
+
 // ------------------------------------------------------------------ pass 4
 enum { kModePlanes = 0, kModeDeform = 1 };
 
-template <int Q, typename Tin, typename Acc, int MODE>
+// FIXMASK != 0 fixes the plane mask at compile time; FULL promises that all
+// 64 lanes are active (W == 64 Q) and that H is a multiple of the prefetch
+// depth, so the row loop has no per-row or per-plane branches.
+template <int Q, typename Tin, typename Acc, int MODE, uint32_t FIXMASK = 0, bool FULL = false>
 __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img, Geom g, Agg<Acc> A, Carry<Acc> K,
-                                                    uint32_t mask, Tin* __restrict__ planes,
+                                                    uint32_t mask_arg, Tin* __restrict__ planes,
                                                     float2* __restrict__ field, const float2* __restrict__ t1,
                                                     double d0, const int* status) {
     extern __shared__ unsigned char smem_raw[];
@@ -466,7 +498,8 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
     const int N = g.N, H = g.H, W = g.W, T = g.T;
     const int b = tile / T, c = tile - (tile / T) * T;
     const int x0 = lane * Q;
-    const bool act = lane <= g.lastLane;
+    const bool act = FULL || lane <= g.lastLane;
+    const uint32_t mask = FIXMASK ? FIXMASK : mask_arg;
     const int cW = c * W;
     const int col = cW + x0;
     const size_t NN = (size_t)N * (size_t)N;
@@ -558,11 +591,14 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
 #pragma unroll
         for (int p = 0; p < PF; ++p) {
             const int r = r0 + p;
-            if (r < H) {
+            if (FULL || r < H) {
                 Tin v[Q];
 #pragma unroll
                 for (int e = 0; e < Q; ++e) v[e] = buf[p][e];
-                if (r + PF < H) load_tile_row<Tin, Q>(src + (size_t)(r + PF) * N, act, buf[p]);
+                if (r + PF < H) {
+                    if constexpr (FULL) load_row<Tin, Q>(src + (size_t)(r + PF) * N, buf[p]);
+                    else load_tile_row<Tin, Q>(src + (size_t)(r + PF) * N, act, buf[p]);
+                }
                 const int j = b * H + r;
 
 #pragma unroll
@@ -660,16 +696,15 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
 // H = 16, N >= 64, so every lane is active): all 16 input rows and defect
 // values are loaded up front and the row loop is fully unrolled without
 // branches, so the per-texel map of row r overlaps the scans of row r+1.
+// One wave per tile: `tile` is the wave's tile, `wave` its slot in the block's
+// LDS (2 (W + H - 1) accumulators per wave).
 template <typename Tin, typename Acc>
-__global__ __launch_bounds__(256) void k_inim_deform16(const Tin* __restrict__ img, Geom g, Agg<Acc> A, Carry<Acc> K,
-                                                       float2* __restrict__ field, const float2* __restrict__ t1,
-                                                       double d0, const int* status) {
+__device__ __forceinline__ void deform16_body(const Tin* __restrict__ img, const Geom& g, const Agg<Acc>& A,
+                                              const Carry<Acc>& K, float2* __restrict__ field,
+                                              const float2* __restrict__ t1, double d0, unsigned char* smem_raw,
+                                              int tile, int wave) {
     constexpr int H = 16, W = 64;
-    extern __shared__ unsigned char smem_raw[];
-    if (failed(status)) return;
     const int lane = lane_id();
-    const int wave = (int)(threadIdx.x >> 6);
-    const int tile = blockIdx.x * kWavesPerBlock + wave;
     if (tile >= g.B * g.T) return;
     const int N = g.N, T = g.T;
     const int b = tile / T, c = tile - (tile / T) * T;
@@ -757,11 +792,21 @@ __global__ __launch_bounds__(256) void k_inim_deform16(const Tin* __restrict__ i
     }
 }
 
+template <typename Tin, typename Acc>
+__global__ __launch_bounds__(256) void k_inim_deform16(const Tin* __restrict__ img, Geom g, Agg<Acc> A, Carry<Acc> K,
+                                                       float2* __restrict__ field, const float2* __restrict__ t1,
+                                                       double d0, const int* status) {
+    extern __shared__ unsigned char smem_raw[];
+    if (failed(status)) return;
+    const int wave = (int)(threadIdx.x >> 6);
+    deform16_body<Tin, Acc>(img, g, A, K, field, t1, d0, smem_raw, blockIdx.x * kWavesPerBlock + wave, wave);
+}
+
 // ------------------------------------------------------------------ defect field
 // t(p; 1) of the constant raster at every texel centre (Sec. 4.2: the defect
 // does not depend on the density, so it is computed once per call).
-__global__ __launch_bounds__(256) void k_defect_field(int N, float2* __restrict__ t1) {
-    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void defect_body(int N, float2* __restrict__ t1, int64_t bid) {
+    const size_t k = (size_t)bid * blockDim.x + threadIdx.x;
     const size_t NN = (size_t)N * N;
     if (k >= NN) return;
     const int j = (int)(k / N), i = (int)(k - (size_t)j * N);
@@ -772,6 +817,8 @@ __global__ __launch_bounds__(256) void k_defect_field(int N, float2* __restrict_
     const double s = 1.0 / (2.0 * (double)NN);
     t1[k] = make_float2((float)(sx * s), (float)(sy * s));
 }
+
+__global__ __launch_bounds__(256) void k_defect_field(int N, float2* __restrict__ t1) { defect_body(N, t1, blockIdx.x); }
 
 // ------------------------------------------------------------------ deform from stored planes
 template <typename Tin>
@@ -869,8 +916,16 @@ static hipError_t launch_final_q(const Tin* img, const Geom& g, void* scratch, u
                            (Tin*)nullptr, field, t1, d0, status);
     } else if (mask != 0) {
         const bool needUV = (mask & (INIM_BETA_T | INIM_GAMMA_T | INIM_DELTA_T)) != 0;
-        hipLaunchKernelGGL((k_inim_final<Q, Tin, Acc, kModePlanes>), grd, blk, needUV ? smem : 0, st, img, g, A, K,
-                           mask, planes, (float2*)nullptr, (const float2*)nullptr, 0.0, status);
+        const bool full = g.W == 64 * Q && g.H % prefetch_rows<Q, Tin>() == 0;
+        if (full && mask == INIM_ALL)
+            hipLaunchKernelGGL((k_inim_final<Q, Tin, Acc, kModePlanes, INIM_ALL, true>), grd, blk, smem, st, img, g, A,
+                               K, mask, planes, (float2*)nullptr, (const float2*)nullptr, 0.0, status);
+        else if (full && mask == INIM_MIN)
+            hipLaunchKernelGGL((k_inim_final<Q, Tin, Acc, kModePlanes, INIM_MIN, true>), grd, blk, 0, st, img, g, A, K,
+                               mask, planes, (float2*)nullptr, (const float2*)nullptr, 0.0, status);
+        else
+            hipLaunchKernelGGL((k_inim_final<Q, Tin, Acc, kModePlanes>), grd, blk, needUV ? smem : 0, st, img, g, A,
+                               K, mask, planes, (float2*)nullptr, (const float2*)nullptr, 0.0, status);
     }
     return hipGetLastError();
 }
@@ -885,6 +940,137 @@ hipError_t launch_inim_final(const Tin* img, const Geom& g, void* scratch, uint3
         case 4: return launch_final_q<Tin, Acc, 4>(img, g, scratch, mask, planes, field, t1, d0, marg, status, st);
     }
     return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ batched (scatterplot matrix)
+// The plot table, built by one block: thread k fills plot k; thread 0 then
+// lays out the blocks of every stage in launch order.
+__global__ __launch_bounds__(64) void kb_init(BatchArgs a, BatchTable* __restrict__ T) {
+    const int k = threadIdx.x;
+    if (k < a.count) {
+        const BatchInput& in = a.in[k];
+        const RegLayout L = reg_layout(in.N, in.n, a.radius);
+        char* base = a.ws + batch_plot_offset(k, a.in, a.radius);
+        int owner = k;  // the first plot of this raster size holds its defect field
+        for (int q = 0; q < k; ++q)
+            if (a.in[q].N == in.N) { owner = q; break; }
+        BatchPlot P;
+        P.xy = reinterpret_cast<float2*>(in.xy);
+        P.n = in.n;
+        P.N = in.N;
+        P.d0 = a.d0 < 0.0 ? (double)in.n / ((double)in.N * (double)in.N) : a.d0;
+        P.g = L.g;
+        P.counts[0] = reinterpret_cast<uint32_t*>(base + L.counts[0]);
+        P.counts[1] = reinterpret_cast<uint32_t*>(base + L.counts[1]);
+        P.density = reinterpret_cast<float*>(base + L.density);
+        P.field = reinterpret_cast<float2*>(base + L.field);
+        P.defect = reinterpret_cast<float2*>(a.ws + batch_plot_offset(owner, a.in, a.radius) + L.defect);
+        P.defect_owner = owner == k;
+        P.sxy = reinterpret_cast<float2*>(base + L.sxy);
+        P.perm = reinterpret_cast<uint32_t*>(base + L.perm);
+        P.rank = reinterpret_cast<uint32_t*>(base + L.rank);
+        P.partial = reinterpret_cast<uint32_t*>(base + L.partial);
+        carve<double>(L.g, base + L.scratch, P.A, P.K);
+        T->plot[k] = P;
+    }
+    if (k == 0) {
+        T->count = a.count;
+        T->wpb = a.wpb;
+        for (int q = 0; q < a.count; ++q) T->order[q] = a.order[q];
+        for (int s = 0; s < kBStages; ++s) {
+            uint32_t run = 0;
+            for (int q = 0; q < a.count; ++q) {
+                T->first[s][q] = run;
+                const int p = a.order[q];
+                bool own = true;
+                for (int r = 0; r < p; ++r)
+                    if (a.in[r].N == a.in[p].N) { own = false; break; }
+                run += batch_stage_blocks(s, a.in[p].N, a.in[p].n, a.wpb, own);
+            }
+            T->first[s][a.count] = run;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void kb_defect(const BatchTable* __restrict__ T) {
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBDefect, blockIdx.x, bid, nblk);
+    defect_body(P.N, P.defect, bid);
+}
+
+__global__ __launch_bounds__(256) void kb_blur_agg(const BatchTable* __restrict__ T, BlurTaps taps, int it, int iters,
+                                                   const int* status) {
+    extern __shared__ float lds[];
+    __shared__ float tile[kBY][kBX];
+    if (failed(status)) return;
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBBlurAgg, blockIdx.x, bid, nblk);
+    const int tx = P.N / kBX;
+    uint32_t* nxt = (it + 1 < iters) ? P.counts[(it + 1) & 1] : nullptr;
+    blur_aggregate_body<double>(P.counts[it & 1], P.density, nxt, taps, P.g, P.A, lds, tile, (int)(bid % tx),
+                                (int)(bid / tx));
+}
+
+__global__ __launch_bounds__(1024) void kb_scan_col(const BatchTable* __restrict__ T, const int* status) {
+    __shared__ double tot[kScanWaves * 2 * 64];
+    __shared__ double left[kScanWaves * kScanMaxP];
+    if (failed(status)) return;
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBScanCol, blockIdx.x, bid, nblk);
+    scan_col_body<double>(P.g, P.A, P.K, tot, left, (int)bid);
+}
+
+__global__ __launch_bounds__(1024) void kb_scan_diag(const BatchTable* __restrict__ T, const int* status) {
+    __shared__ double tot[kScanWaves * 64];
+    if (failed(status)) return;
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBScanDiag, blockIdx.x, bid, nblk);
+    const int tx = (2 * P.N + 1 + 63) / 64;
+    scan_diag_body<double>(P.g, P.A, P.K, tot, (int)(bid % tx), (int)(bid / tx));
+}
+
+__global__ __launch_bounds__(256) void kb_marg(const BatchTable* __restrict__ T, const int* status) {
+    if (failed(status)) return;
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBMarg, blockIdx.x, bid, nblk);
+    marg_body<double>(P.g, P.A, P.K, nullptr, (int)bid);
+}
+
+__global__ __launch_bounds__(512) void kb_deform(const BatchTable* __restrict__ T, const int* status) {
+    extern __shared__ unsigned char smem_raw[];
+    if (failed(status)) return;
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBDeform, blockIdx.x, bid, nblk);
+    const int wave = (int)(threadIdx.x >> 6);
+    deform16_body<float, double>(P.density, P.g, P.A, P.K, P.field, P.defect, P.d0, smem_raw,
+                                 (int)bid * T->wpb + wave, wave);
+}
+
+hipError_t launch_batch_init(const BatchArgs& a, BatchTable* T, hipStream_t st) {
+    hipLaunchKernelGGL(kb_init, dim3(1), dim3(64), 0, st, a, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_inim(int stage, const BatchTable* T, unsigned blocks, int wpb, const BlurTaps& taps, int it,
+                             int iters, const int* status, hipStream_t st) {
+    if (blocks == 0) return hipSuccess;
+    switch (stage) {
+        case kBDefect: hipLaunchKernelGGL(kb_defect, dim3(blocks), dim3(256), 0, st, T); break;
+        case kBBlurAgg:
+            hipLaunchKernelGGL(kb_blur_agg, dim3(blocks), dim3(256), sizeof(float) * blur_smem_floats(taps.r), st, T,
+                               taps, it, iters, status);
+            break;
+        case kBScanCol: hipLaunchKernelGGL(kb_scan_col, dim3(blocks), dim3(1024), 0, st, T, status); break;
+        case kBScanDiag: hipLaunchKernelGGL(kb_scan_diag, dim3(blocks), dim3(1024), 0, st, T, status); break;
+        case kBMarg: hipLaunchKernelGGL(kb_marg, dim3(blocks), dim3(256), 0, st, T, status); break;
+        case kBDeform:
+            if (wpb < 1 || wpb > 8) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(kb_deform, dim3(blocks), dim3(64 * wpb), (size_t)wpb * 2 * (64 + 16 - 1) * sizeof(double),
+                               st, T, status);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 #define INIM_INSTANTIATE(TIN, ACC)                                                                                    \

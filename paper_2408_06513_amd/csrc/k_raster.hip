@@ -5,7 +5,9 @@
 
 #include "blur_tile.h"
 #include "device_common.h"
+#include "batch_plan.h"
 #include "launch.h"
+#include "reg_layout.h"
 
 namespace inim {
 
@@ -19,15 +21,23 @@ __device__ __forceinline__ void flag_domain(int* status) {
 }
 
 // ------------------------------------------------------------------ fill
-__global__ __launch_bounds__(256) void k_fill(uint32_t* __restrict__ counts, size_t count, int* status, int clear) {
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Kernel bodies take their block index and block count explicitly: the
+// single-raster kernels pass blockIdx.x and gridDim.x, the batched kernels
+// of a scatterplot matrix pass the block's place among the plot's blocks.
+__device__ __forceinline__ void fill_body(uint32_t* __restrict__ counts, size_t count, int* status, int clear,
+                                          int64_t bid, int64_t nblk) {
+    const size_t t = (size_t)bid * blockDim.x + threadIdx.x;
     if (clear && t == 0) *status = 0;
     typedef uint32_t u4 __attribute__((ext_vector_type(4)));
     const size_t n4 = count / 4;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t stride = (size_t)nblk * blockDim.x;
     const u4 z = {0u, 0u, 0u, 0u};
     for (size_t k = t; k < n4; k += stride) reinterpret_cast<u4*>(counts)[k] = z;
     for (size_t k = n4 * 4 + t; k < count; k += stride) counts[k] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_fill(uint32_t* __restrict__ counts, size_t count, int* status, int clear) {
+    fill_body(counts, count, status, clear, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------ splat
@@ -113,11 +123,10 @@ __device__ __forceinline__ void wave_count(uint32_t* __restrict__ counts, uint32
 // count raster of the next iteration (Sec. 4.3, step 1 of the next round).
 // Every wave runs the same number of loop trips so that wave_count sees all
 // 64 lanes.
-__global__ __launch_bounds__(256) void k_advect(const float2* __restrict__ field, int N, float2* __restrict__ xy,
-                                                int64_t n, uint32_t* __restrict__ counts_next, const int* status) {
-    if (failed(status)) return;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t first = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
+__device__ __forceinline__ void advect_body(const float2* __restrict__ field, int N, float2* __restrict__ xy, int64_t n,
+                                            uint32_t* __restrict__ counts_next, int64_t bid, int64_t nblk) {
+    const int64_t stride = (int64_t)nblk * blockDim.x;
+    const int64_t first = (int64_t)bid * blockDim.x + (threadIdx.x & ~63u);
     for (int64_t base = first; base < n; base += stride) {
         const int64_t p = base + lane_id();
         uint32_t key = 0xFFFFFFFFu;
@@ -141,15 +150,20 @@ __global__ __launch_bounds__(256) void k_advect(const float2* __restrict__ field
     }
 }
 
+__global__ __launch_bounds__(256) void k_advect(const float2* __restrict__ field, int N, float2* __restrict__ xy,
+                                                int64_t n, uint32_t* __restrict__ counts_next, const int* status) {
+    if (failed(status)) return;
+    advect_body(field, N, xy, n, counts_next, blockIdx.x, gridDim.x);
+}
+
 // ------------------------------------------------------------------ texel order
 // Splat that also returns each sample's rank among the samples of its texel
 // (the value of the count before its own increment); flags invalid samples.
-__global__ __launch_bounds__(256) void k_splat_rank(const float2* __restrict__ xy, int64_t n, int N,
-                                                    uint32_t* __restrict__ counts, uint32_t* __restrict__ rank,
-                                                    int* status) {
-    if (failed(status)) return;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+__device__ __forceinline__ void splat_rank_body(const float2* __restrict__ xy, int64_t n, int N,
+                                                uint32_t* __restrict__ counts, uint32_t* __restrict__ rank, int* status,
+                                                int64_t bid, int64_t nblk) {
+    const int64_t stride = (int64_t)nblk * blockDim.x;
+    for (int64_t p = (int64_t)bid * blockDim.x + threadIdx.x; p < n; p += stride) {
         const float2 q = xy[p];
         if (!in_unit_square(q)) {
             flag_domain(status);
@@ -160,11 +174,17 @@ __global__ __launch_bounds__(256) void k_splat_rank(const float2* __restrict__ x
     }
 }
 
+__global__ __launch_bounds__(256) void k_splat_rank(const float2* __restrict__ xy, int64_t n, int N,
+                                                    uint32_t* __restrict__ counts, uint32_t* __restrict__ rank,
+                                                    int* status) {
+    if (failed(status)) return;
+    splat_rank_body(xy, n, N, counts, rank, status, blockIdx.x, gridDim.x);
+}
+
 // Exclusive prefix of a uint32 array (length a multiple of 4) in three passes:
 // per-block sums, a scan of the block sums by one block, and the scan within
 // each block.  A block of 256 threads covers 1024 consecutive words, four per
 // thread as one 16-byte vector.
-constexpr int kScanThreads = 256, kScanBlock = 4 * kScanThreads;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds_wave, uint32_t& total) {
@@ -183,19 +203,22 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* l
     return lds_wave[wave] + incl - v;
 }
 
+__device__ __forceinline__ void scan_reduce_body(const uint32_t* __restrict__ a, uint32_t* __restrict__ partial,
+                                                 uint32_t* lw, int64_t bid) {
+    const u32x4 v = reinterpret_cast<const u32x4*>(a)[(size_t)bid * kScanThreads + threadIdx.x];
+    uint32_t total;
+    (void)block_exclusive_scan(v.x + v.y + v.z + v.w, lw, total);
+    if (threadIdx.x == 0) partial[bid] = total;
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ a,
                                                               uint32_t* __restrict__ partial, const int* status) {
     __shared__ uint32_t lw[33];
     if (failed(status)) return;
-    const u32x4 v = reinterpret_cast<const u32x4*>(a)[(size_t)blockIdx.x * kScanThreads + threadIdx.x];
-    uint32_t total;
-    (void)block_exclusive_scan(v.x + v.y + v.z + v.w, lw, total);
-    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+    scan_reduce_body(a, partial, lw, blockIdx.x);
 }
 
-__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* __restrict__ partial, int nb, const int* status) {
-    __shared__ uint32_t lw[33];
-    if (failed(status)) return;
+__device__ __forceinline__ void scan_partials_body(uint32_t* __restrict__ partial, int nb, uint32_t* lw) {
     const int per = (nb + (int)blockDim.x - 1) / (int)blockDim.x;
     const int b0 = threadIdx.x * per;
     uint32_t s = 0;
@@ -211,21 +234,32 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* __restrict__ p
         }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ a,
-                                                            const uint32_t* __restrict__ partial,
-                                                            uint32_t* __restrict__ out, const int* status) {
+__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* __restrict__ partial, int nb, const int* status) {
     __shared__ uint32_t lw[33];
     if (failed(status)) return;
-    const size_t k = (size_t)blockIdx.x * kScanThreads + threadIdx.x;
+    scan_partials_body(partial, nb, lw);
+}
+
+__device__ __forceinline__ void scan_down_body(const uint32_t* __restrict__ a, const uint32_t* __restrict__ partial,
+                                               uint32_t* __restrict__ out, uint32_t* lw, int64_t bid) {
+    const size_t k = (size_t)bid * kScanThreads + threadIdx.x;
     const u32x4 v = reinterpret_cast<const u32x4*>(a)[k];
     uint32_t total;
-    const uint32_t run = partial[blockIdx.x] + block_exclusive_scan(v.x + v.y + v.z + v.w, lw, total);
+    const uint32_t run = partial[bid] + block_exclusive_scan(v.x + v.y + v.z + v.w, lw, total);
     u32x4 o;
     o.x = run;
     o.y = run + v.x;
     o.z = o.y + v.y;
     o.w = o.z + v.z;
     reinterpret_cast<u32x4*>(out)[k] = o;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ a,
+                                                            const uint32_t* __restrict__ partial,
+                                                            uint32_t* __restrict__ out, const int* status) {
+    __shared__ uint32_t lw[33];
+    if (failed(status)) return;
+    scan_down_body(a, partial, out, lw, blockIdx.x);
 }
 
 // Exclusive prefix of at most 1024 words by one block.
@@ -241,13 +275,12 @@ __global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* __restrict_
 }
 
 // Moves every sample to slot offset[texel] + rank: texel (row-major) order.
-__global__ __launch_bounds__(256) void k_scatter_sorted(const float2* __restrict__ xy, int64_t n, int N,
-                                                        const uint32_t* __restrict__ rank,
-                                                        const uint32_t* __restrict__ offset, float2* __restrict__ sxy,
-                                                        uint32_t* __restrict__ perm, const int* status) {
-    if (failed(status)) return;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+__device__ __forceinline__ void scatter_sorted_body(const float2* __restrict__ xy, int64_t n, int N,
+                                                    const uint32_t* __restrict__ rank,
+                                                    const uint32_t* __restrict__ offset, float2* __restrict__ sxy,
+                                                    uint32_t* __restrict__ perm, int64_t bid, int64_t nblk) {
+    const int64_t stride = (int64_t)nblk * blockDim.x;
+    for (int64_t p = (int64_t)bid * blockDim.x + threadIdx.x; p < n; p += stride) {
         const float2 q = xy[p];
         const int i = texel_of(q.x, N), j = texel_of(q.y, N);
         const uint32_t slot = offset[(size_t)j * N + i] + rank[p];
@@ -256,11 +289,24 @@ __global__ __launch_bounds__(256) void k_scatter_sorted(const float2* __restrict
     }
 }
 
+__global__ __launch_bounds__(256) void k_scatter_sorted(const float2* __restrict__ xy, int64_t n, int N,
+                                                        const uint32_t* __restrict__ rank,
+                                                        const uint32_t* __restrict__ offset, float2* __restrict__ sxy,
+                                                        uint32_t* __restrict__ perm, const int* status) {
+    if (failed(status)) return;
+    scatter_sorted_body(xy, n, N, rank, offset, sxy, perm, blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ void unpermute_body(const float2* __restrict__ sxy, const uint32_t* __restrict__ perm,
+                                               int64_t n, float2* __restrict__ xy, int64_t bid, int64_t nblk) {
+    const int64_t stride = (int64_t)nblk * blockDim.x;
+    for (int64_t q = (int64_t)bid * blockDim.x + threadIdx.x; q < n; q += stride) xy[perm[q]] = sxy[q];
+}
+
 __global__ __launch_bounds__(256) void k_unpermute(const float2* __restrict__ sxy, const uint32_t* __restrict__ perm,
                                                    int64_t n, float2* __restrict__ xy, const int* status) {
     if (failed(status)) return;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) xy[perm[q]] = sxy[q];
+    unpermute_body(sxy, perm, n, xy, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -304,8 +350,6 @@ hipError_t launch_advect(const float2* field, int N, float2* xy, int64_t n, uint
 
 namespace inim {
 
-size_t scan_partials(size_t m) { return (m + kScanBlock - 1) / kScanBlock; }
-
 hipError_t launch_sort_by_texel(const float2* xy, int64_t n, int N, uint32_t* counts, uint32_t* rank,
                                 uint32_t* offsets, uint32_t* partial, float2* sxy, uint32_t* perm, int* status,
                                 hipStream_t st) {
@@ -322,6 +366,89 @@ hipError_t launch_sort_by_texel(const float2* xy, int64_t n, int N, uint32_t* co
     }
     hipLaunchKernelGGL(k_scatter_sorted, dim3(grid_for(n)), dim3(256), 0, st, xy, n, N, rank, offsets, sxy, perm,
                        status);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ batched (scatterplot matrix)
+// One launch per stage for all plots of a BatchTable; each block runs the
+// single-plot body for its plot with its block index among that plot's.
+__global__ __launch_bounds__(256) void kb_fill(const BatchTable* __restrict__ T, int* status) {
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBFill, blockIdx.x, bid, nblk);
+    fill_body(P.counts[0], (size_t)P.N * P.N, status, blockIdx.x == 0 ? 1 : 0, bid, nblk);
+}
+
+__global__ __launch_bounds__(256) void kb_splat_rank(const BatchTable* __restrict__ T, int* status) {
+    if (failed(status)) return;
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBSplatRank, blockIdx.x, bid, nblk);
+    splat_rank_body(reinterpret_cast<const float2*>(P.xy), P.n, P.N, P.counts[0], P.rank, status, bid, nblk);
+}
+
+__global__ __launch_bounds__(kScanThreads) void kb_scan_reduce(const BatchTable* __restrict__ T, const int* status) {
+    __shared__ uint32_t lw[33];
+    if (failed(status)) return;
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBScanReduce, blockIdx.x, bid, nblk);
+    scan_reduce_body(P.counts[0], P.partial, lw, bid);
+}
+
+__global__ __launch_bounds__(1024) void kb_scan_partials(const BatchTable* __restrict__ T, const int* status) {
+    __shared__ uint32_t lw[33];
+    if (failed(status)) return;
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBScanPartials, blockIdx.x, bid, nblk);
+    scan_partials_body(P.partial, (int)scan_partials((size_t)P.N * P.N), lw);
+}
+
+__global__ __launch_bounds__(kScanThreads) void kb_scan_down(const BatchTable* __restrict__ T, const int* status) {
+    __shared__ uint32_t lw[33];
+    if (failed(status)) return;
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBScanDown, blockIdx.x, bid, nblk);
+    scan_down_body(P.counts[0], P.partial, P.counts[1], lw, bid);
+}
+
+__global__ __launch_bounds__(256) void kb_scatter(const BatchTable* __restrict__ T, const int* status) {
+    if (failed(status)) return;
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBScatter, blockIdx.x, bid, nblk);
+    scatter_sorted_body(reinterpret_cast<const float2*>(P.xy), P.n, P.N, P.rank, P.counts[1], P.sxy, P.perm, bid,
+                        nblk);
+}
+
+__global__ __launch_bounds__(256) void kb_advect(const BatchTable* __restrict__ T, int it, int iters,
+                                                 const int* status) {
+    if (failed(status)) return;
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBAdvect, blockIdx.x, bid, nblk);
+    uint32_t* nxt = (it + 1 < iters) ? P.counts[(it + 1) & 1] : nullptr;
+    advect_body(P.field, P.N, P.sxy, P.n, nxt, bid, nblk);
+}
+
+__global__ __launch_bounds__(256) void kb_unpermute(const BatchTable* __restrict__ T, const int* status) {
+    if (failed(status)) return;
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBUnpermute, blockIdx.x, bid, nblk);
+    unpermute_body(P.sxy, P.perm, P.n, reinterpret_cast<float2*>(P.xy), bid, nblk);
+}
+
+hipError_t launch_batch_raster(int stage, const BatchTable* T, unsigned blocks, int it, int iters, int* status,
+                               hipStream_t st) {
+    if (blocks == 0) return hipSuccess;
+    switch (stage) {
+        case kBFill: hipLaunchKernelGGL(kb_fill, dim3(blocks), dim3(256), 0, st, T, status); break;
+        case kBSplatRank: hipLaunchKernelGGL(kb_splat_rank, dim3(blocks), dim3(256), 0, st, T, status); break;
+        case kBScanReduce:
+            hipLaunchKernelGGL(kb_scan_reduce, dim3(blocks), dim3(kScanThreads), 0, st, T, status);
+            break;
+        case kBScanPartials: hipLaunchKernelGGL(kb_scan_partials, dim3(blocks), dim3(1024), 0, st, T, status); break;
+        case kBScanDown: hipLaunchKernelGGL(kb_scan_down, dim3(blocks), dim3(kScanThreads), 0, st, T, status); break;
+        case kBScatter: hipLaunchKernelGGL(kb_scatter, dim3(blocks), dim3(256), 0, st, T, status); break;
+        case kBAdvect: hipLaunchKernelGGL(kb_advect, dim3(blocks), dim3(256), 0, st, T, it, iters, status); break;
+        case kBUnpermute: hipLaunchKernelGGL(kb_unpermute, dim3(blocks), dim3(256), 0, st, T, status); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "batch_plan.h"
 #include "inim_plan.h"
 
 namespace inim {
@@ -49,7 +50,6 @@ hipError_t launch_validate(const float2* xy, int64_t n, int* status, hipStream_t
 // into `offsets` (using `partial`, scan_partials(N*N) words), and writes the
 // samples in texel order to sxy with perm[slot] = original index.  `counts`
 // keeps the texel counts of the input.
-size_t scan_partials(size_t m);
 hipError_t launch_sort_by_texel(const float2* xy, int64_t n, int N, uint32_t* counts, uint32_t* rank,
                                 uint32_t* offsets, uint32_t* partial, float2* sxy, uint32_t* perm, int* status,
                                 hipStream_t st);
@@ -65,5 +65,13 @@ hipError_t launch_advect(const float2* field, int N, float2* xy, int64_t n, uint
 bool blur_aggregate_fits(const Geom& g);
 hipError_t launch_blur_aggregate(const uint32_t* counts, float* density, uint32_t* zero_next, int N,
                                  const BlurTaps& taps, const Geom& g, void* scratch, const int* status, hipStream_t st);
+
+// Batched regularisation of several plots (batch_plan.h): the table-building
+// launch, then one launch per stage with `blocks` = first[stage][count].
+hipError_t launch_batch_init(const BatchArgs& a, BatchTable* T, hipStream_t st);
+hipError_t launch_batch_raster(int stage, const BatchTable* T, unsigned blocks, int it, int iters, int* status,
+                               hipStream_t st);
+hipError_t launch_batch_inim(int stage, const BatchTable* T, unsigned blocks, int wpb, const BlurTaps& taps, int it,
+                             int iters, const int* status, hipStream_t st);
 
 }  // namespace inim

@@ -1,0 +1,45 @@
+// reg_layout.h -- the regularisation workspace: its regions and their
+// offsets, computed identically on the host (sizes, carving) and on the
+// device (the plot table of a batched call).
+#pragma once
+
+#include "inim_plan.h"
+
+namespace inim {
+
+constexpr size_t kStatusBytes = 256;
+constexpr int kScanThreads = 256, kScanBlock = 4 * kScanThreads;
+
+// Blocks of the per-block partial sums of an exclusive scan over m words.
+__host__ __device__ inline size_t scan_partials(size_t m) { return (m + kScanBlock - 1) / kScanBlock; }
+
+// Byte offsets of the regions of one plot's regularisation workspace.
+struct RegLayout {
+    size_t status, counts[2], density, field, defect, scratch, sxy, perm, rank, partial, total;
+    Geom g;
+    bool f32;  // integral images of the float density in double (radius > 0), or of the counts
+};
+
+__host__ __device__ inline RegLayout reg_layout(int32_t res, int64_t n, int radius) {
+    RegLayout L;
+    const size_t NN = (size_t)res * (size_t)res;
+    const size_t nn = n > 0 ? (size_t)n : 0;
+    L.f32 = radius > 0;
+    L.g = make_geom(res, L.f32 ? 8 : 4);
+    size_t o = 0;
+    L.status = o; o += kStatusBytes;
+    L.counts[0] = o; o += align256(NN * 4);
+    L.counts[1] = o; o += align256(NN * 4);
+    L.density = o; o += align256(NN * 4);
+    L.field = o; o += align256(NN * 8);
+    L.defect = o; o += align256(NN * 8);
+    L.scratch = o; o += inim_scratch_bytes(L.g, L.f32 ? 8 : 4);
+    L.sxy = o; o += align256(nn * 8);
+    L.perm = o; o += align256(nn * 4);
+    L.rank = o; o += align256(nn * 4);
+    L.partial = o; o += align256(scan_partials(NN) * 4);
+    L.total = o;
+    return L;
+}
+
+}  // namespace inim

@@ -25,6 +25,7 @@ __all__ = [
     "lognormal_raster",
     "lattice_points",
     "splom_table",
+    "splom_plots",
 ]
 
 
@@ -160,3 +161,16 @@ def splom_table(seed: int = 0, n: int = 200_000, dims: int = 10) -> np.ndarray:
     lo, hi = t.min(axis=0), t.max(axis=0)
     t = (t - lo) / (hi - lo)
     return np.ascontiguousarray(np.clip(t, 0.0, 1.0).astype(np.float32))
+
+
+def splom_plots(seed: int = 0, n: int = 200_000, dims: int = 10, sizes=(256, 512, 1024)):
+    """All dims*(dims-1)/2 pairwise plots of splom_table: a list of
+    (xy float32 [n, 2] = columns (a, b), raster size drawn from `sizes`)."""
+    t = splom_table(seed, n, dims)
+    g = rng(91_000 + seed)
+    out = []
+    for a in range(dims):
+        for b in range(a + 1, dims):
+            res = int(g.choice(np.asarray(sizes)))
+            out.append((np.ascontiguousarray(t[:, [a, b]]), res))
+    return out

@@ -72,5 +72,21 @@ def test_argument_errors_return_before_launch():
     assert L.inim_inim_u32(ctypes.c_void_p(0x1000), 64, 0x1FF, nul, nul, nul, 0, nul) == capi.EINVAL
     assert L.inim_deform(nul, nul, 1, nul, 64, 1.0, nul, nul) == capi.EINVAL
     assert L.inim_advect(nul, 64, nul, 5, nul, 0, nul) == capi.EINVAL
+    fake = ctypes.c_void_p(0x1000)
+    assert L.inim_regularize_probes(fake, 10, nul, 5, 64, 2, ctypes.byref(p), nul, 0, nul) == capi.EINVAL
+    assert L.inim_regularize_probes(fake, 10, fake, -1, 64, 2, ctypes.byref(p), nul, 0, nul) == capi.EINVAL
+    assert L.inim_regularize_probes(fake, 10, fake, 5, 64, 2, ctypes.byref(p), nul, 0, nul) == capi.EWORKSPACE
+    ptrs = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    ns = (ctypes.c_int64 * 2)(10, 10)
+    sz = ctypes.c_size_t()
+    assert L.inim_batch_workspace_size(ptrs, ns, (ctypes.c_int32 * 2)(64, 32), 2, ctypes.byref(p),
+                                       ctypes.byref(sz)) == capi.EINVAL                    # res < 64
+    assert L.inim_batch_workspace_size(ptrs, ns, (ctypes.c_int32 * 2)(64, 64), 65, ctypes.byref(p),
+                                       ctypes.byref(sz)) == capi.EINVAL                    # count > 64
+    assert L.inim_batch_workspace_size(ptrs, ns, (ctypes.c_int32 * 2)(64, 128), 2, ctypes.byref(p),
+                                       ctypes.byref(sz)) == capi.OK and sz.value > 0
+    cfg = capi.BatchConfig(3, 0)
+    assert L.inim_regularize_batch(ptrs, ns, (ctypes.c_int32 * 2)(64, 128), 2, 2, ctypes.byref(p), ctypes.byref(cfg),
+                                   nul, 0, nul, nul) == capi.EINVAL                        # waves_per_block
     assert L.inim_sync_status(nul, nul) == capi.EWORKSPACE
     assert "NULL" in capi.lib().inim_last_error().decode()

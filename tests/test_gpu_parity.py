@@ -90,6 +90,21 @@ def test_inim_f32_relative(capi, dev, res, mask):
         np.testing.assert_allclose(m[k], rm[k], rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("res", [256, 4096])
+def test_inim_f32_correctly_rounded(capi, dev, res):
+    """Float rasters of quarter-integers: every region sum is exact in FP64
+    (below 2^53), so each float plane element must be that sum rounded to
+    float once (nearest, ties to even), bit for bit; sums beyond 2^24
+    exercise the rounding."""
+    img = (dg.poisson_raster(7, res, lam=40.0).astype(np.float64) / 4.0).astype(np.float32)
+    note(f"inim_f32 rounding res={res}")
+    planes, _ = capi.inim(to_dev(img, dev), 0xFF)
+    torch.cuda.synchronize()
+    ref, _ = oracle.planes(img.astype(np.float64), 0xFF)
+    assert ref.max() < 2.0**53 and (res < 4096 or ref.max() > 2.0**24)
+    assert np.array_equal(planes.cpu().numpy(), ref.astype(np.float32))
+
+
 @pytest.mark.parametrize("which", ["ones", "spike", "row", "checker"])
 def test_inim_special_rasters(capi, dev, which):
     res = 64

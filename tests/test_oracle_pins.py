@@ -370,6 +370,42 @@ def iterate_with_grid(xy, N, iters, r=8):
     return out
 
 
+def test_probes_are_passive_and_follow_the_map():
+    """Probe points take no part in the density (the samples end exactly as
+    without them), a probe placed on a sample moves exactly like it, and the
+    probes on the texel lattice give the step-by-step composite of the
+    per-iteration deformations (Sec. 4.3)."""
+    xy = dg.plain_small(0)[:3000]
+    N = 64
+    probe = np.concatenate([xy[:50], dg.lattice_points(N)])
+    a = oracle.regularize(xy, N, 3)
+    s, p = oracle.regularize_probes(xy, probe, N, 3)
+    assert np.array_equal(s, a)
+    assert np.array_equal(p[:50], a[:50])
+    steps = iterate_with_grid(xy, N, 3)
+    assert np.array_equal(p[50:].reshape(N, N, 2), steps[-1][1])
+
+
+def test_composite_map_is_identity_for_uniform_samples():
+    """Samples on the texel lattice are a fixed point, so the composite map is
+    the identity at any probe (the field is affine and reproduced exactly)."""
+    N = 32
+    xy = dg.lattice_points(N)
+    probe = dg.rng(5).uniform(0, 1, size=(500, 2))
+    s, p = oracle.regularize_probes(xy, probe, N, 3)
+    np.testing.assert_allclose(p, probe, rtol=0, atol=1e-12)
+
+
+def test_probe_errors_and_noop():
+    xy = dg.plain_small(0)[:100]
+    bad = np.array([[0.5, 1.5]])
+    with pytest.raises(oracle.OracleError):
+        oracle.regularize_probes(xy, bad, 16, 2)
+    # no samples: nothing moves, whatever the probes hold
+    s, p = oracle.regularize_probes(np.zeros((0, 2)), bad, 16, 2)
+    assert np.array_equal(p, bad)
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_no_folds_and_decreasing_measures_small(seed):
     """Sec. 5 and Sec. 6: the deformation keeps the lattice fold-free and
