@@ -1,0 +1,774 @@
+// k_nn.hip -- the kernels of the learned surrogate on gfx950: 3x3 (and 1x1)
+// convolutions as implicit GEMMs on the BF16 matrix cores with FP32
+// accumulation (forward, gradient of the input, gradient of the weights), and
+// the element-wise layers around them (average pooling, nearest upsampling,
+// channel concatenation, ReLU masks, mean-squared error, Adam).
+//
+// Layouts: activations are NHWC (pixel-major, channels contiguous), BF16 as
+// uint16 bit patterns or FP32; weights are [Cout][taps][Cin] with taps =
+// ks*ks in row-major (ky, kx) order; their transpose for the input gradient is
+// [Cin][taps][Cout].
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "inim.h"
+#include "inim_nn.h"
+#include "nn_plan.h"
+
+namespace inim {
+namespace nn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// Round to nearest even; NaN stays NaN.
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+// ------------------------------------------------------------------ implicit GEMM
+// C[m][n] = sum_k A[m][k] B[k][n] over one 128 x 128 block tile, K in steps of
+// 32 staged through LDS as [row][k] for A and [col][k] for B, so that every
+// lane reads its 8 consecutive k of one row (A) or one column (B) as one
+// 16-byte LDS read.  Four waves, each 64 x 64 = 2 x 2 tiles of the 32 x 32 x 16
+// BF16 MFMA.  MFMA lane layout (gfx950, 32x32x16): lane l holds A[l%32][8(l/32)+j]
+// and B[8(l/32)+j][l%32] for j < 8; result register i of lane l is
+// C[8(i/4) + 4(l/32) + i%4][l%32].
+constexpr int kBM = 128, kBN = 128, kBK = 32, kPad = 8;
+
+struct GemmLds {
+    uint16_t a[kBM][kBK + kPad];
+    uint16_t b[kBN][kBK + kPad];
+};
+
+// Element source of one operand: 8 consecutive k of row (A) or column (B) `r`.
+// Conv geometry: pixel p = (img, y, x) of an H x W image, taps t = (ky, kx).
+struct ConvGeom {
+    int H, W, P;  // P = images * H * W
+    int ks, taps, half;
+    __device__ __forceinline__ bool shift(int p, int t, int sign, int& q) const {
+        const int x = p % W, yy = p / W, y = yy % H;
+        const int dy = (t / ks - half) * sign, dx = (t % ks - half) * sign;
+        const int ny = y + dy, nx = x + dx;
+        if (ny < 0 || ny >= H || nx < 0 || nx >= W) return false;
+        q = p + dy * W + dx;
+        return true;
+    }
+};
+
+__device__ __forceinline__ u16x8 zero8() { return u16x8{0, 0, 0, 0, 0, 0, 0, 0}; }
+
+// Forward: A[p][(t, ci)] = x[p + off_t][ci]; B[(t, ci)][co] = w[co][t][ci].
+// Input gradient: A[q][(t, co)] = dy[q - off_t][co]; B[(t, co)][ci] = wT[ci][t][co].
+// Both read 8 channels of one pixel (C % 8 == 0) as one 16-byte load.
+struct RowShiftLoader {  // A of forward / input gradient
+    const uint16_t* src;
+    int C;      // channels of src
+    int sign;   // +1 forward, -1 input gradient
+    int M, K;   // K = taps * C
+    ConvGeom g;
+    __device__ __forceinline__ u16x8 load8(int m, int k) const {
+        if (m >= M || k >= K) return zero8();
+        const int t = k / C, c = k - t * C;
+        int q;
+        if (!g.shift(m, t, sign, q)) return zero8();
+        return *reinterpret_cast<const u16x8*>(src + (size_t)q * C + c);
+    }
+};
+struct WeightLoader {  // B of forward / input gradient: rows of [N][K] contiguous in k
+    const uint16_t* w;
+    int N, K;
+    __device__ __forceinline__ u16x8 load8(int n, int k) const {
+        if (n >= N || k >= K) return zero8();
+        return *reinterpret_cast<const u16x8*>(w + (size_t)n * K + k);
+    }
+};
+
+template <class LA, class LB>
+__device__ __forceinline__ void stage_vec(GemmLds& s, const LA& la, const LB& lb, int bm, int bn, int k0) {
+    // 128 x 32 of A and of B: 512 chunks of 8 each, two per thread
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = threadIdx.x + 256 * h;
+        const int r = c >> 2, kc = (c & 3) * 8;
+        *reinterpret_cast<u16x8*>(&s.a[r][kc]) = la.load8(bm + r, k0 + kc);
+        *reinterpret_cast<u16x8*>(&s.b[r][kc]) = lb.load8(bn + r, k0 + kc);
+    }
+}
+
+// Weight gradient: dW[co][(t, ci)] = sum_p dy[p][co] x[p + off_t][ci], i.e.
+// A[co][p] = dy[p][co] and B[p][(t, ci)] = x[p + off_t][ci]: element-wise
+// loads with consecutive threads on consecutive channels (coalesced),
+// transposed into the [row][k] LDS layout.
+struct WgradSrc {
+    const uint16_t* dy;  // [P][Cout]
+    const uint16_t* x;   // [P][Cin]
+    int Cout, Cin, N;    // N = taps * Cin
+    ConvGeom g;
+};
+
+__device__ __forceinline__ void stage_wgrad(GemmLds& s, const WgradSrc& w, int bm, int bn, int k0) {
+    // A: 128 co x 32 p, co fastest
+#pragma unroll 4
+    for (int h = 0; h < (kBM * kBK) / 256; ++h) {
+        const int e = threadIdx.x + 256 * h;
+        const int r = e % kBM, k = e / kBM;
+        const int co = bm + r, p = k0 + k;
+        s.a[r][k] = (co < w.Cout && p < w.g.P) ? w.dy[(size_t)p * w.Cout + co] : (uint16_t)0;
+    }
+    // B: 32 p x 128 (t, ci), (t, ci) fastest
+#pragma unroll 4
+    for (int h = 0; h < (kBN * kBK) / 256; ++h) {
+        const int e = threadIdx.x + 256 * h;
+        const int r = e % kBN, k = e / kBN;
+        const int n = bn + r, p = k0 + k;
+        uint16_t v = 0;
+        if (n < w.N && p < w.g.P) {
+            const int t = n / w.Cin, ci = n - t * w.Cin;
+            int q;
+            if (w.g.shift(p, t, 1, q)) v = w.x[(size_t)q * w.Cin + ci];
+        }
+        s.b[r][k] = v;
+    }
+}
+
+// The MFMA part of one K step of 32 for this wave's 64 x 64.
+__device__ __forceinline__ void mma_step(const GemmLds& s, f32x16 (&acc)[2][2], int wm, int wn, int lane) {
+#pragma unroll
+    for (int kk = 0; kk < kBK; kk += 16) {
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const u16x8 va = *reinterpret_cast<const u16x8*>(&s.a[wm * 64 + i * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+            const u16x8 vb = *reinterpret_cast<const u16x8*>(&s.b[wn * 64 + i * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+            a[i] = __builtin_bit_cast(bf16x8, va);
+            b[i] = __builtin_bit_cast(bf16x8, vb);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+// Epilogue over this wave's results: f(m, n, value).
+template <class F>
+__device__ __forceinline__ void for_each_result(const f32x16 (&acc)[2][2], int bm, int bn, int wm, int wn, int lane,
+                                                F f) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int m = bm + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int n = bn + wn * 64 + j * 32 + (lane & 31);
+                f(m, n, acc[i][j][r]);
+            }
+}
+
+// Forward convolution: y[p][co] = act(b[co] + sum x w), stored as BF16
+// (y16) and/or FP32 (y32); relu != 0 applies max(., 0).
+__global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
+    __shared__ GemmLds s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
+    const int bm = blockIdx.x * kBM, bn = blockIdx.y * kBN;
+    const ConvGeom g{a.H, a.W, a.P, a.ks, a.ks * a.ks, a.ks / 2};
+    const int K = g.taps * a.Cin;
+    const RowShiftLoader la{a.x, a.Cin, 1, a.P, K, g};
+    const WeightLoader lb{a.w, a.Cout, K};
+    f32x16 acc[2][2] = {};
+    for (int k0 = 0; k0 < K; k0 += kBK) {
+        stage_vec(s, la, lb, bm, bn, k0);
+        __syncthreads();
+        mma_step(s, acc, wm, wn, lane);
+        __syncthreads();
+    }
+    for_each_result(acc, bm, bn, wm, wn, lane, [&](int m, int n, float v) {
+        if (m >= a.P || n >= a.Cout) return;
+        v += a.bias ? a.bias[n] : 0.0f;
+        if (a.relu) v = v > 0.0f ? v : 0.0f;
+        const size_t o = (size_t)m * a.Cout + n;
+        if (a.y16) a.y16[o] = f2bf(v);
+        if (a.y32) a.y32[o] = v;
+    });
+}
+
+// Input gradient: dx[q][ci] = sum_{t, co} dy[q - off_t][co] wT[ci][t][co], FP32.
+__global__ __launch_bounds__(256) void k_conv_dgrad(ConvArgs a) {
+    __shared__ GemmLds s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
+    const int bm = blockIdx.x * kBM, bn = blockIdx.y * kBN;
+    const ConvGeom g{a.H, a.W, a.P, a.ks, a.ks * a.ks, a.ks / 2};
+    const int K = g.taps * a.Cout;
+    const RowShiftLoader la{a.dy, a.Cout, -1, a.P, K, g};
+    const WeightLoader lb{a.wT, a.Cin, K};
+    f32x16 acc[2][2] = {};
+    for (int k0 = 0; k0 < K; k0 += kBK) {
+        stage_vec(s, la, lb, bm, bn, k0);
+        __syncthreads();
+        mma_step(s, acc, wm, wn, lane);
+        __syncthreads();
+    }
+    for_each_result(acc, bm, bn, wm, wn, lane, [&](int m, int n, float v) {
+        if (m >= a.P || n >= a.Cin) return;
+        a.dx[(size_t)m * a.Cin + n] = v;
+    });
+}
+
+// Weight gradient, FP32 [Cout][taps][Cin]; K (pixels) split over gridDim.z
+// slices of `kslice` pixels, each slice writing its own partial [slice][...].
+__global__ __launch_bounds__(256) void k_conv_wgrad(ConvArgs a, int kslice) {
+    __shared__ GemmLds s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
+    const int bm = blockIdx.x * kBM, bn = blockIdx.y * kBN;
+    const ConvGeom g{a.H, a.W, a.P, a.ks, a.ks * a.ks, a.ks / 2};
+    const int N = g.taps * a.Cin;
+    const WgradSrc src{a.dy, a.x, a.Cout, a.Cin, N, g};
+    const int kbeg = blockIdx.z * kslice, kend = min(a.P, kbeg + kslice);
+    f32x16 acc[2][2] = {};
+    for (int k0 = kbeg; k0 < kend; k0 += kBK) {
+        stage_wgrad(s, src, bm, bn, k0);
+        __syncthreads();
+        mma_step(s, acc, wm, wn, lane);
+        __syncthreads();
+    }
+    float* out = a.dw + (size_t)blockIdx.z * a.Cout * N;
+    for_each_result(acc, bm, bn, wm, wn, lane, [&](int m, int n, float v) {
+        if (m >= a.Cout || n >= N) return;
+        out[(size_t)m * N + n] = v;
+    });
+}
+
+// Sum of `parts` partial arrays of length len (fixed order), optional bias
+// gradient rows: out[i] = sum_s part[s][i].
+__global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int parts, size_t len,
+                                                   float* __restrict__ out) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (size_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int q = 0; q < parts; ++q) s += part[(size_t)q * len + i];
+        out[i] = s;
+    }
+}
+
+// Bias gradient partials: part[b][co] = sum over pixels of block b of dy[p][co].
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dy, int P, int C, int per,
+                                                   float* __restrict__ part) {
+    const int co = threadIdx.x;
+    const int p0 = blockIdx.x * per, p1 = min(P, p0 + per);
+    for (int c = co; c < C; c += blockDim.x) {
+        float s = 0.0f;
+        for (int p = p0; p < p1; ++p) s += bf2f(dy[(size_t)p * C + c]);
+        part[(size_t)blockIdx.x * C + c] = s;
+    }
+}
+
+// wT[ci][t][co] = w[co][t][ci]
+__global__ __launch_bounds__(256) void k_wtrans(const uint16_t* __restrict__ w, int Cout, int taps, int Cin,
+                                                uint16_t* __restrict__ wT) {
+    const size_t n = (size_t)Cout * taps * Cin;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int ci = (int)(i % Cin);
+        const size_t r = i / Cin;
+        const int t = (int)(r % taps), co = (int)(r / taps);
+        wT[((size_t)ci * taps + t) * Cout + co] = w[i];
+    }
+}
+
+// ------------------------------------------------------------------ element-wise layers
+__global__ __launch_bounds__(256) void k_f32_to_bf16(const float* __restrict__ a, size_t n, uint16_t* __restrict__ b) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b[i] = f2bf(a[i]);
+}
+
+// 2x2 average pooling, NHWC: y[img][y][x][c] of an (H/2) x (W/2) image.
+__global__ __launch_bounds__(256) void k_pool2(const uint16_t* __restrict__ x, int imgs, int H, int W, int C,
+                                               uint16_t* __restrict__ y) {
+    const int h = H / 2, w = W / 2;
+    const size_t n = (size_t)imgs * h * w * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        size_t r = i / C;
+        const int xx = (int)(r % w);
+        r /= w;
+        const int yy = (int)(r % h);
+        const size_t img = r / h;
+        const size_t b = ((img * H + 2 * yy) * W + 2 * xx) * C + c;
+        const float s = bf2f(x[b]) + bf2f(x[b + C]) + bf2f(x[b + (size_t)W * C]) + bf2f(x[b + (size_t)W * C + C]);
+        y[i] = f2bf(0.25f * s);
+    }
+}
+
+// Gradient of the pooling: dx[img][y][x][c] = dy[img][y/2][x/2][c] / 4, added
+// to dx (FP32) when accumulate != 0.
+__global__ __launch_bounds__(256) void k_pool2_back(const float* __restrict__ dy, int imgs, int H, int W, int C,
+                                                    float* __restrict__ dx, int accumulate) {
+    const size_t n = (size_t)imgs * H * W * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        size_t r = i / C;
+        const int xx = (int)(r % W);
+        r /= W;
+        const int yy = (int)(r % H);
+        const size_t img = r / H;
+        const float v = 0.25f * dy[((img * (H / 2) + yy / 2) * (W / 2) + xx / 2) * C + c];
+        dx[i] = accumulate ? dx[i] + v : v;
+    }
+}
+
+// Nearest 2x upsampling into channels [c0, c0 + C) of a Ct-channel tensor:
+// y[img][y][x][c0 + c] = x[img][y/2][x/2][c] (x is h x w, y is 2h x 2w).
+__global__ __launch_bounds__(256) void k_up2_into(const uint16_t* __restrict__ x, int imgs, int h, int w, int C,
+                                                  uint16_t* __restrict__ y, int Ct, int c0) {
+    const size_t n = (size_t)imgs * 4 * h * w * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        size_t r = i / C;
+        const int xx = (int)(r % (2 * w));
+        r /= 2 * w;
+        const int yy = (int)(r % (2 * h));
+        const size_t img = r / (2 * h);
+        y[((img * 2 * h + yy) * 2 * w + xx) * Ct + c0 + c] = x[((img * h + yy / 2) * w + xx / 2) * C + c];
+    }
+}
+
+// Copy into channels [c0, c0 + C) of a Ct-channel tensor (the skip half of a concatenation).
+__global__ __launch_bounds__(256) void k_copy_into(const uint16_t* __restrict__ x, size_t pixels, int C,
+                                                   uint16_t* __restrict__ y, int Ct, int c0) {
+    const size_t n = pixels * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t p = i / C;
+        y[p * Ct + c0 + (i - p * C)] = x[i];
+    }
+}
+
+// Gradients through a concatenation [up(a) | b]: da[img][y][x][c] = sum of
+// the 2 x 2 block of dy[...][c] (channels [0, Ca)); db (channels [Ca, Ca+Cb))
+// is added to db_acc (FP32) when accumulate != 0, else stored.
+__global__ __launch_bounds__(256) void k_up2_back(const float* __restrict__ dy, int imgs, int h, int w, int Ct,
+                                                  int Ca, float* __restrict__ da) {
+    const size_t n = (size_t)imgs * h * w * Ca;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % Ca);
+        size_t r = i / Ca;
+        const int xx = (int)(r % w);
+        r /= w;
+        const int yy = (int)(r % h);
+        const size_t img = r / h;
+        const size_t b = ((img * 2 * h + 2 * yy) * 2 * w + 2 * xx) * Ct + c;
+        const size_t row = (size_t)2 * w * Ct;
+        da[i] = dy[b] + dy[b + Ct] + dy[b + row] + dy[b + row + Ct];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_take_channels(const float* __restrict__ dy, size_t pixels, int Ct, int c0,
+                                                       int C, float* __restrict__ out, int accumulate) {
+    const size_t n = pixels * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t p = i / C;
+        const float v = dy[p * Ct + c0 + (i - p * C)];
+        out[i] = accumulate ? out[i] + v : v;
+    }
+}
+
+// ReLU gradient and BF16 cast: g16[i] = bf16(g[i] * (act[i] > 0)) (act = the
+// layer's ReLU output); act == nullptr: no mask.
+__global__ __launch_bounds__(256) void k_relu_back(const float* __restrict__ g, const uint16_t* __restrict__ act, size_t n,
+                                                   uint16_t* __restrict__ g16) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        float v = g[i];
+        if (act && !(bf2f(act[i]) > 0.0f)) v = 0.0f;
+        g16[i] = f2bf(v);
+    }
+}
+
+// Mean-squared error of the first Ct of Cp predicted channels against the
+// target [P][Ct]: loss_part[block] = sum of (pred - target)^2 over the
+// block's elements; grad[p][c] = 2 (pred - target) / (P Ct) as BF16 for
+// c < Ct and 0 for the other channels (grad may be null).
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ pred, int Cp, const float* __restrict__ target,
+                                             int Ct, size_t P, float* __restrict__ loss_part,
+                                             uint16_t* __restrict__ grad) {
+    __shared__ float red[256];
+    float s = 0.0f;
+    const size_t n = P * Cp;
+    const float sc = 2.0f / (float)(P * Ct);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t p = i / Cp;
+        const int c = (int)(i - p * Cp);
+        float d = 0.0f;
+        if (c < Ct) d = pred[i] - target[p * Ct + c];
+        s += d * d;
+        if (grad) grad[i] = f2bf(sc * d);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
+}
+
+// Adam (bias-corrected) on FP32 master weights; also writes their BF16 copy.
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, size_t n, AdamArgs a, uint16_t* __restrict__ w16) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
+        const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float wi = w[i] - a.lr * (mi * a.c1) / (sqrtf(vi * a.c2) + a.eps);
+        w[i] = wi;
+        if (w16) w16[i] = f2bf(wi);
+    }
+}
+
+// ------------------------------------------------------------------ surrogate input, target and output
+// Network input: channel 0 = density * scale (the density relative to its
+// mean), channels 1..C-1 = 0.
+__global__ __launch_bounds__(256) void k_pack_density(const float* __restrict__ d, size_t pixels, float scale, int C,
+                                                      uint16_t* __restrict__ x) {
+    const size_t n = pixels * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t p = i / C;
+        x[i] = (i - p * C) == 0 ? f2bf(d[p] * scale) : (uint16_t)0;
+    }
+}
+
+// Training target: the displacement of every texel centre in texel units,
+// out[p][c] = (probe[p][c] - ((i or j) + 1/2) / N) * N, p = j N + i.
+__global__ __launch_bounds__(256) void k_displacement(const float2* __restrict__ probe, int N, float* __restrict__ out) {
+    const size_t n = (size_t)N * N;
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        const int j = (int)(p / N), i = (int)(p - (size_t)j * N);
+        const float2 q = probe[p];
+        out[2 * p] = (q.x - ((float)i + 0.5f) / (float)N) * (float)N;
+        out[2 * p + 1] = (q.y - ((float)j + 0.5f) / (float)N) * (float)N;
+    }
+}
+
+// The deformation field of the network's output: field[p] = texel centre +
+// output[p][0..1] / N (channels beyond the first two are ignored).
+__global__ __launch_bounds__(256) void k_field_from_output(const float* __restrict__ y, int C, int N,
+                                                           float2* __restrict__ field) {
+    const size_t n = (size_t)N * N;
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        const int j = (int)(p / N), i = (int)(p - (size_t)j * N);
+        field[p] = make_float2(((float)i + 0.5f + y[p * C]) / (float)N, ((float)j + 0.5f + y[p * C + 1]) / (float)N);
+    }
+}
+
+// Orientation check of a deformed lattice (field[j][i] = image of texel
+// centre (i, j)): counts the triangles (two per cell) whose signed area is not
+// positive, i.e. folds.  One atomic add per block.
+__global__ __launch_bounds__(256) void k_count_folds(const float2* __restrict__ f, int N, unsigned* __restrict__ count) {
+    __shared__ unsigned red[256];
+    unsigned c = 0;
+    const size_t cells = (size_t)(N - 1) * (N - 1);
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < cells; k += (size_t)gridDim.x * blockDim.x) {
+        const int j = (int)(k / (N - 1)), i = (int)(k - (size_t)j * (N - 1));
+        const float2 a = f[(size_t)j * N + i], b = f[(size_t)j * N + i + 1];
+        const float2 cc = f[(size_t)(j + 1) * N + i], d = f[(size_t)(j + 1) * N + i + 1];
+        const double c1 = ((double)b.x - a.x) * ((double)cc.y - a.y) - ((double)b.y - a.y) * ((double)cc.x - a.x);
+        const double c2 = ((double)cc.x - d.x) * ((double)b.y - d.y) - ((double)cc.y - d.y) * ((double)b.x - d.x);
+        c += (c1 <= 0.0) + (c2 <= 0.0);
+    }
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0]) atomicAdd(count, red[0]);
+}
+
+// Sums of the counts of bin x bin texel blocks and of their squares (for the
+// standard deviation of the per-bin counts), as two doubles.  One atomic pair
+// per block.
+__global__ __launch_bounds__(256) void k_bin_moments(const uint32_t* __restrict__ counts, int N, int bin,
+                                                     double* __restrict__ out) {
+    __shared__ double r1[256], r2[256];
+    const int nb = N / bin;
+    double s1 = 0.0, s2 = 0.0;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nb * nb; k += gridDim.x * blockDim.x) {
+        const int by = k / nb, bx = k - by * nb;
+        double s = 0.0;
+        for (int y = 0; y < bin; ++y)
+            for (int x = 0; x < bin; ++x) s += counts[(size_t)(by * bin + y) * N + bx * bin + x];
+        s1 += s;
+        s2 += s * s;
+    }
+    r1[threadIdx.x] = s1;
+    r2[threadIdx.x] = s2;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            r1[threadIdx.x] += r1[threadIdx.x + o];
+            r2[threadIdx.x] += r2[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(out, r1[0]);
+        atomicAdd(out + 1, r2[0]);
+    }
+}
+
+}  // namespace nn
+}  // namespace inim
+
+// ------------------------------------------------------------------ C ABI (inim_nn.h)
+using namespace inim::nn;
+
+namespace {
+
+thread_local std::string g_nn_error;
+
+int nfail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int nfail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_nn_error = buf;
+    return code;
+}
+
+int launched(const char* what) {
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? INIM_OK : nfail(INIM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+unsigned grid_1d(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    return (unsigned)(g > 8192 ? 8192 : g);
+}
+
+constexpr int kTile = 128, kStepK = 32, kMsePartials = 256, kBiasPixels = 2048;
+
+int check_conv(int32_t imgs, int32_t h, int32_t w, int32_t cin, int32_t cout, int32_t ks) {
+    if (imgs < 1 || h < 1 || w < 1) return nfail(INIM_EINVAL, "empty image batch %d x %d x %d", imgs, h, w);
+    if ((int64_t)imgs * h * w >= ((int64_t)1 << 31)) return nfail(INIM_ERANGE, "too many pixels");
+    if (ks != 1 && ks != 3) return nfail(INIM_EINVAL, "kernel size %d is not 1 or 3", ks);
+    if (cin < 8 || cin % 8 || cout < 8 || cout % 8)
+        return nfail(INIM_EINVAL, "channels %d -> %d must be positive multiples of 8", cin, cout);
+    return INIM_OK;
+}
+
+int wgrad_slices(int64_t P, int cout, int cin, int ks) {
+    const int64_t tiles = ((cout + kTile - 1) / kTile) * ((int64_t)(ks * ks * cin + kTile - 1) / kTile);
+    int64_t s = (512 + tiles - 1) / tiles;
+    const int64_t steps = (P + kStepK - 1) / kStepK;
+    if (s > steps) s = steps;
+    return (int)(s < 1 ? 1 : s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* inim_nn_last_error(void) { return g_nn_error.c_str(); }
+
+int inim_conv_forward(const inim_bf16* x, int32_t imgs, int32_t h, int32_t w, int32_t cin, const inim_bf16* weight,
+                      const float* bias, int32_t cout, int32_t ks, int32_t relu, inim_bf16* y16, float* y32,
+                      hipStream_t stream) {
+    int s = check_conv(imgs, h, w, cin, cout, ks);
+    if (s != INIM_OK) return s;
+    if (!x || !weight || (!y16 && !y32)) return nfail(INIM_EINVAL, "x, weight or both outputs NULL");
+    ConvArgs a{};
+    a.x = x; a.w = weight; a.bias = bias; a.y16 = y16; a.y32 = y32;
+    a.H = h; a.W = w; a.P = imgs * h * w; a.Cin = cin; a.Cout = cout; a.ks = ks; a.relu = relu ? 1 : 0;
+    hipLaunchKernelGGL(k_conv_fwd, dim3((a.P + kTile - 1) / kTile, (cout + kTile - 1) / kTile), dim3(256), 0, stream, a);
+    return launched("conv forward");
+}
+
+int inim_conv_backward_data(const inim_bf16* dy, int32_t imgs, int32_t h, int32_t w, int32_t cin,
+                            const inim_bf16* weight_t, int32_t cout, int32_t ks, float* dx, hipStream_t stream) {
+    int s = check_conv(imgs, h, w, cin, cout, ks);
+    if (s != INIM_OK) return s;
+    if (!dy || !weight_t || !dx) return nfail(INIM_EINVAL, "dy, weight_t or dx NULL");
+    ConvArgs a{};
+    a.dy = dy; a.wT = weight_t; a.dx = dx;
+    a.H = h; a.W = w; a.P = imgs * h * w; a.Cin = cin; a.Cout = cout; a.ks = ks;
+    hipLaunchKernelGGL(k_conv_dgrad, dim3((a.P + kTile - 1) / kTile, (cin + kTile - 1) / kTile), dim3(256), 0, stream, a);
+    return launched("conv input gradient");
+}
+
+int inim_conv_backward_weight_workspace(int32_t imgs, int32_t h, int32_t w, int32_t cin, int32_t cout, int32_t ks,
+                                        size_t* bytes) {
+    int s = check_conv(imgs, h, w, cin, cout, ks);
+    if (s != INIM_OK) return s;
+    if (!bytes) return nfail(INIM_EINVAL, "bytes NULL");
+    const int64_t P = (int64_t)imgs * h * w;
+    const size_t wlen = (size_t)cout * ks * ks * cin;
+    const size_t bparts = (size_t)((P + kBiasPixels - 1) / kBiasPixels);
+    *bytes = ((size_t)wgrad_slices(P, cout, cin, ks) * wlen + bparts * cout) * sizeof(float);
+    return INIM_OK;
+}
+
+int inim_conv_backward_weight(const inim_bf16* dy, const inim_bf16* x, int32_t imgs, int32_t h, int32_t w, int32_t cin,
+                              int32_t cout, int32_t ks, float* dweight, float* dbias, void* work, size_t work_bytes,
+                              hipStream_t stream) {
+    size_t need;
+    int s = inim_conv_backward_weight_workspace(imgs, h, w, cin, cout, ks, &need);
+    if (s != INIM_OK) return s;
+    if (!dy || !x || !dweight) return nfail(INIM_EINVAL, "dy, x or dweight NULL");
+    if (!work || work_bytes < need) return nfail(INIM_EWORKSPACE, "work has %zu bytes, needs %zu", work_bytes, need);
+    ConvArgs a{};
+    a.dy = dy; a.x = x;
+    a.H = h; a.W = w; a.P = imgs * h * w; a.Cin = cin; a.Cout = cout; a.ks = ks;
+    const int slices = wgrad_slices(a.P, cout, cin, ks);
+    const int64_t steps = (a.P + kStepK - 1) / kStepK;
+    const int kslice = (int)((steps + slices - 1) / slices) * kStepK;
+    const size_t wlen = (size_t)cout * ks * ks * cin;
+    a.dw = static_cast<float*>(work);
+    hipLaunchKernelGGL(k_conv_wgrad, dim3((cout + kTile - 1) / kTile, (unsigned)((ks * ks * cin + kTile - 1) / kTile), slices),
+                       dim3(256), 0, stream, a, kslice);
+    hipLaunchKernelGGL(k_sum_parts, dim3(grid_1d((int64_t)wlen)), dim3(256), 0, stream, a.dw, slices, wlen, dweight);
+    if (dbias) {
+        float* bp = a.dw + (size_t)slices * wlen;
+        const int parts = (a.P + kBiasPixels - 1) / kBiasPixels;
+        hipLaunchKernelGGL(k_bias_grad, dim3(parts), dim3(256), 0, stream, dy, a.P, cout, kBiasPixels, bp);
+        hipLaunchKernelGGL(k_sum_parts, dim3(grid_1d(cout)), dim3(256), 0, stream, bp, parts, (size_t)cout, dbias);
+    }
+    return launched("conv weight gradient");
+}
+
+int inim_weight_transpose(const inim_bf16* weight, int32_t cout, int32_t ks, int32_t cin, inim_bf16* weight_t,
+                          hipStream_t stream) {
+    if (!weight || !weight_t || cout < 1 || cin < 1 || (ks != 1 && ks != 3))
+        return nfail(INIM_EINVAL, "bad weight transpose arguments");
+    hipLaunchKernelGGL(k_wtrans, dim3(grid_1d((int64_t)cout * ks * ks * cin)), dim3(256), 0, stream, weight, cout,
+                       ks * ks, cin, weight_t);
+    return launched("weight transpose");
+}
+
+int inim_f32_to_bf16(const float* a, int64_t n, inim_bf16* b, hipStream_t stream) {
+    if (n < 0 || (n > 0 && (!a || !b))) return nfail(INIM_EINVAL, "bad cast arguments");
+    if (n == 0) return INIM_OK;
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid_1d(n)), dim3(256), 0, stream, a, (size_t)n, b);
+    return launched("cast");
+}
+
+int inim_pool2(const inim_bf16* x, int32_t imgs, int32_t h, int32_t w, int32_t c, inim_bf16* y, hipStream_t stream) {
+    if (!x || !y || imgs < 1 || h < 2 || w < 2 || h % 2 || w % 2 || c < 1)
+        return nfail(INIM_EINVAL, "bad pooling arguments");
+    hipLaunchKernelGGL(k_pool2, dim3(grid_1d((int64_t)imgs * (h / 2) * (w / 2) * c)), dim3(256), 0, stream, x, imgs, h, w,
+                       c, y);
+    return launched("pool");
+}
+
+int inim_pool2_backward(const float* dy, int32_t imgs, int32_t h, int32_t w, int32_t c, float* dx, int32_t accumulate,
+                        hipStream_t stream) {
+    if (!dy || !dx || imgs < 1 || h < 2 || w < 2 || h % 2 || w % 2 || c < 1)
+        return nfail(INIM_EINVAL, "bad pooling-gradient arguments");
+    hipLaunchKernelGGL(k_pool2_back, dim3(grid_1d((int64_t)imgs * h * w * c)), dim3(256), 0, stream, dy, imgs, h, w, c, dx,
+                       accumulate ? 1 : 0);
+    return launched("pool gradient");
+}
+
+int inim_upsample2_into(const inim_bf16* x, int32_t imgs, int32_t h, int32_t w, int32_t c, inim_bf16* y, int32_t ct,
+                        int32_t c0, hipStream_t stream) {
+    if (!x || !y || imgs < 1 || h < 1 || w < 1 || c < 1 || c0 < 0 || c0 + c > ct)
+        return nfail(INIM_EINVAL, "bad upsampling arguments");
+    hipLaunchKernelGGL(k_up2_into, dim3(grid_1d((int64_t)imgs * 4 * h * w * c)), dim3(256), 0, stream, x, imgs, h, w, c, y,
+                       ct, c0);
+    return launched("upsample");
+}
+
+int inim_copy_channels_into(const inim_bf16* x, int64_t pixels, int32_t c, inim_bf16* y, int32_t ct, int32_t c0,
+                            hipStream_t stream) {
+    if (!x || !y || pixels < 1 || c < 1 || c0 < 0 || c0 + c > ct) return nfail(INIM_EINVAL, "bad channel copy arguments");
+    hipLaunchKernelGGL(k_copy_into, dim3(grid_1d(pixels * c)), dim3(256), 0, stream, x, (size_t)pixels, c, y, ct, c0);
+    return launched("channel copy");
+}
+
+int inim_upsample2_backward(const float* dy, int32_t imgs, int32_t h, int32_t w, int32_t ct, int32_t ca, float* da,
+                            hipStream_t stream) {
+    if (!dy || !da || imgs < 1 || h < 1 || w < 1 || ca < 1 || ca > ct)
+        return nfail(INIM_EINVAL, "bad upsampling-gradient arguments");
+    hipLaunchKernelGGL(k_up2_back, dim3(grid_1d((int64_t)imgs * h * w * ca)), dim3(256), 0, stream, dy, imgs, h, w, ct, ca,
+                       da);
+    return launched("upsample gradient");
+}
+
+int inim_take_channels(const float* dy, int64_t pixels, int32_t ct, int32_t c0, int32_t c, float* out,
+                       int32_t accumulate, hipStream_t stream) {
+    if (!dy || !out || pixels < 1 || c < 1 || c0 < 0 || c0 + c > ct) return nfail(INIM_EINVAL, "bad channel arguments");
+    hipLaunchKernelGGL(k_take_channels, dim3(grid_1d(pixels * c)), dim3(256), 0, stream, dy, (size_t)pixels, ct, c0, c,
+                       out, accumulate ? 1 : 0);
+    return launched("channel gradient");
+}
+
+int inim_relu_backward(const float* g, const inim_bf16* act, int64_t n, inim_bf16* g16, hipStream_t stream) {
+    if (!g || !g16 || n < 1) return nfail(INIM_EINVAL, "bad ReLU-gradient arguments");
+    hipLaunchKernelGGL(k_relu_back, dim3(grid_1d(n)), dim3(256), 0, stream, g, act, (size_t)n, g16);
+    return launched("ReLU gradient");
+}
+
+int inim_mse(const float* pred, int32_t cp, const float* target, int32_t ct, int64_t pixels, float* loss,
+             inim_bf16* grad, void* work, size_t work_bytes, hipStream_t stream) {
+    if (!pred || !target || !loss || pixels < 1 || ct < 1 || ct > cp) return nfail(INIM_EINVAL, "bad loss arguments");
+    if (!work || work_bytes < kMsePartials * sizeof(float)) return nfail(INIM_EWORKSPACE, "loss work too small");
+    float* parts = static_cast<float*>(work);
+    hipLaunchKernelGGL(k_mse, dim3(kMsePartials), dim3(256), 0, stream, pred, cp, target, ct, (size_t)pixels, parts, grad);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, stream, parts, kMsePartials, (size_t)1, loss);
+    return launched("loss");
+}
+
+int inim_nn_pack_density(const float* density, int32_t res, float scale, int32_t c, inim_bf16* x, hipStream_t stream) {
+    if (!density || !x || res < 2 || c < 1) return nfail(INIM_EINVAL, "bad input-packing arguments");
+    const size_t px = (size_t)res * res;
+    hipLaunchKernelGGL(k_pack_density, dim3(grid_1d((int64_t)(px * c))), dim3(256), 0, stream, density, px, scale, c, x);
+    return launched("pack density");
+}
+
+int inim_nn_displacement(const float* probe, int32_t res, float* out, hipStream_t stream) {
+    if (!probe || !out || res < 2) return nfail(INIM_EINVAL, "bad displacement arguments");
+    hipLaunchKernelGGL(k_displacement, dim3(grid_1d((int64_t)res * res)), dim3(256), 0, stream,
+                       reinterpret_cast<const float2*>(probe), res, out);
+    return launched("displacement");
+}
+
+int inim_nn_field(const float* y, int32_t c, int32_t res, float* field, hipStream_t stream) {
+    if (!y || !field || res < 2 || c < 2) return nfail(INIM_EINVAL, "bad field arguments");
+    hipLaunchKernelGGL(k_field_from_output, dim3(grid_1d((int64_t)res * res)), dim3(256), 0, stream, y, c, res,
+                       reinterpret_cast<float2*>(field));
+    return launched("field");
+}
+
+int inim_nn_count_folds(const float* field, int32_t res, uint32_t* count, hipStream_t stream) {
+    if (!field || !count || res < 2) return nfail(INIM_EINVAL, "bad fold-count arguments");
+    hipLaunchKernelGGL(k_count_folds, dim3(grid_1d((int64_t)(res - 1) * (res - 1))), dim3(256), 0, stream,
+                       reinterpret_cast<const float2*>(field), res, count);
+    return launched("fold count");
+}
+
+int inim_nn_bin_moments(const uint32_t* counts, int32_t res, int32_t bin, double* out, hipStream_t stream) {
+    if (!counts || !out || res < 2 || bin < 1 || res % bin) return nfail(INIM_EINVAL, "bad bin-moment arguments");
+    const int64_t nb = (int64_t)(res / bin) * (res / bin);
+    hipLaunchKernelGGL(k_bin_moments, dim3(grid_1d(nb)), dim3(256), 0, stream, counts, res, bin, out);
+    return launched("bin moments");
+}
+
+int inim_adam(float* weight, const float* grad, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+              int32_t step, inim_bf16* weight16, hipStream_t stream) {
+    if (!weight || !grad || !m || !v || n < 1 || step < 1) return nfail(INIM_EINVAL, "bad Adam arguments");
+    AdamArgs a{lr, b1, b2, eps, 1.0f / (1.0f - powf(b1, (float)step)), 1.0f / (1.0f - powf(b2, (float)step))};
+    hipLaunchKernelGGL(k_adam, dim3(grid_1d(n)), dim3(256), 0, stream, weight, grad, m, v, (size_t)n, a, weight16);
+    return launched("Adam");
+}
+
+}  // extern "C"

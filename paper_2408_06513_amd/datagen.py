@@ -26,6 +26,7 @@ __all__ = [
     "lattice_points",
     "splom_table",
     "splom_plots",
+    "surrogate_mixture",
 ]
 
 
@@ -174,3 +175,15 @@ def splom_plots(seed: int = 0, n: int = 200_000, dims: int = 10, sizes=(256, 512
             res = int(g.choice(np.asarray(sizes)))
             out.append((np.ascontiguousarray(t[:, [a, b]]), res))
     return out
+
+
+def surrogate_mixture(seed: int, n_lo: int = 10_000, n_hi: int = 500_000) -> np.ndarray:
+    """A training or held-out input of the learned surrogate: K ~ U{2..12}
+    Gaussian components (the small-configuration shapes: means U[.15,.85]^2,
+    axis stds U[.02,.15], random rotations, Dirichlet(1) sizes) and
+    n ~ log-uniform[n_lo, n_hi] points."""
+    g = rng(100_000 + seed)
+    k = int(g.integers(2, 13))
+    n = int(np.exp(g.uniform(np.log(n_lo), np.log(n_hi))))
+    counts = _dirichlet_counts(g, n, k)
+    return gaussian_mixture(110_000 + seed, [c for c in counts if c > 0], 0.15, 0.85, 0.02, 0.15)

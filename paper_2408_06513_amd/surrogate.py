@@ -1,0 +1,280 @@
+"""The learned surrogate of the iterated regularisation.
+
+A five-level convolutional U-Net (channels 32/64/128/256/256, two 3x3
+convolutions with ReLU per level, 2x2 average pooling, nearest upsampling,
+concatenated skips, a 1x1 output convolution) maps the smoothed density of a
+256 x 256 raster to the displacement that `iters` iterations of the method
+give every texel centre (the composite map of Sec. 4.3 minus the identity,
+in texels).  The samples are then moved by one bilinear advection of that
+field.  It is trained on fields that the method itself computes, and the
+method remains the judge and the fallback: a prediction whose deformed
+lattice folds, or that does not make the samples more uniform, is replaced by
+the plain regularisation.
+
+Every layer runs in the HIP kernels of libinim.so (BF16 matrix-core
+convolutions with FP32 accumulation; include/inim_nn.h); PyTorch only holds
+the device memory.  Weights are kept in FP32 (updated by Adam) with BF16
+copies for the convolutions.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import capi, datagen, nn
+
+BF16, F32 = torch.bfloat16, torch.float32
+CIN, COUT = 8, 8  # input channel 0 = relative density; output channels 0, 1 = displacement
+
+
+def conv_shapes(chans=(32, 64, 128, 256, 256)):
+    """(name, cin, cout, ks) of every convolution in forward order."""
+    out, prev = [], CIN
+    for lvl, c in enumerate(chans):
+        out += [(f"e{lvl}a", prev, c, 3), (f"e{lvl}b", c, c, 3)]
+        prev = c
+    for lvl in range(len(chans) - 2, -1, -1):
+        c = chans[lvl]
+        out += [(f"d{lvl}a", prev + c, c, 3), (f"d{lvl}b", c, c, 3)]
+        prev = c
+    out.append(("head", prev, COUT, 1))
+    return out
+
+
+class Conv:
+    def __init__(self, name, cin, cout, ks, w32: torch.Tensor, dev):
+        self.name, self.cin, self.cout, self.ks = name, cin, cout, ks
+        self.w = w32.to(dev).contiguous()
+        self.b = torch.zeros(cout, dtype=F32, device=dev)
+        self.w16 = torch.empty(self.w.shape, dtype=BF16, device=dev)
+        self.wT = torch.empty((cin, ks * ks, cout), dtype=BF16, device=dev)
+        self.gw, self.gb = torch.zeros_like(self.w), torch.zeros_like(self.b)
+        self.mw, self.vw = torch.zeros_like(self.w), torch.zeros_like(self.w)
+        self.mb, self.vb = torch.zeros_like(self.b), torch.zeros_like(self.b)
+        self.refresh()
+
+    def refresh(self):
+        nn.to_bf16(self.w, self.w16)
+        nn.weight_transpose(self.w16, self.wT)
+
+    def step(self, t, lr):
+        nn.adam(self.w, self.gw, self.mw, self.vw, t, lr=lr, w16=self.w16)
+        nn.adam(self.b, self.gb, self.mb, self.vb, t, lr=lr)
+        nn.weight_transpose(self.w16, self.wT)
+
+
+class UNet:
+    """The network on one device; forward() keeps what backward() needs."""
+
+    def __init__(self, dev, seed: int = 0, chans=(32, 64, 128, 256, 256)):
+        self.dev, self.chans, self.levels = dev, tuple(chans), len(chans)
+        g = np.random.Generator(np.random.PCG64(seed))
+        self.convs = {}
+        for name, ci, co, ks in conv_shapes(chans):
+            std = math.sqrt((2.0 if name != "head" else 1.0) / (ci * ks * ks))
+            w = torch.tensor(g.standard_normal((co, ks * ks, ci)) * std, dtype=F32)
+            self.convs[name] = Conv(name, ci, co, ks, w, dev)
+        self.t = 0
+        self._work = None
+
+    def params_f64(self) -> dict:
+        """The FP32 master weights as FP64 CPU tensors (for the oracle)."""
+        out = {}
+        for k, c in self.convs.items():
+            out[k + ".w"] = c.w.detach().double().cpu()
+            out[k + ".b"] = c.b.detach().double().cpu()
+        return out
+
+    # ------------------------------------------------------------------ forward
+    def _conv(self, name, x, relu=True, out32=False):
+        c = self.convs[name]
+        n, h, w, _ = x.shape
+        if out32:
+            y = torch.empty((n, h, w, c.cout), dtype=F32, device=self.dev)
+            nn.conv_forward(x, c.w16, c.b, relu, y32=y)
+        else:
+            y = torch.empty((n, h, w, c.cout), dtype=BF16, device=self.dev)
+            nn.conv_forward(x, c.w16, c.b, relu, y16=y)
+        return y
+
+    def forward(self, x16: torch.Tensor) -> torch.Tensor:
+        """x16 [n, H, W, 8] bf16 -> [n, H, W, 8] f32 (H, W divisible by 16)."""
+        L = self.levels
+        self.inp, self.mid, self.out = {}, {}, {}
+        h = x16
+        for lvl in range(L):
+            if lvl:
+                n, hh, ww, c = h.shape
+                p = torch.empty((n, hh // 2, ww // 2, c), dtype=BF16, device=self.dev)
+                h = nn.pool2(h, p)
+            self.inp[f"e{lvl}"] = h
+            a = self._conv(f"e{lvl}a", h)
+            b = self._conv(f"e{lvl}b", a)
+            self.mid[f"e{lvl}"], self.out[f"e{lvl}"] = a, b
+            h = b
+        for lvl in range(L - 2, -1, -1):
+            skip = self.out[f"e{lvl}"]
+            n, hh, ww, cs = skip.shape
+            cu = h.shape[3]
+            cat = torch.empty((n, hh, ww, cu + cs), dtype=BF16, device=self.dev)
+            nn.upsample2_into(h, cat, 0)
+            nn.copy_channels_into(skip, cat, cu)
+            self.inp[f"d{lvl}"] = cat
+            a = self._conv(f"d{lvl}a", cat)
+            b = self._conv(f"d{lvl}b", a)
+            self.mid[f"d{lvl}"], self.out[f"d{lvl}"] = a, b
+            h = b
+        self.inp["head"] = h
+        return self._conv("head", h, relu=False, out32=True)
+
+    # ------------------------------------------------------------------ backward
+    def _wgrad(self, c: Conv, gz16, x16):
+        n, h, w, _ = x16.shape
+        need = nn.weight_workspace(n, h, w, c.cin, c.cout, c.ks)
+        if self._work is None or self._work.numel() < need:
+            self._work = torch.empty(need, dtype=torch.uint8, device=self.dev)
+        nn.conv_backward_weight(gz16, x16, c.ks, c.gw, c.gb, self._work)
+
+    def _dgrad(self, c: Conv, gz16):
+        n, h, w, _ = gz16.shape
+        dx = torch.empty((n, h, w, c.cin), dtype=F32, device=self.dev)
+        return nn.conv_backward_data(gz16, c.wT, dx)
+
+    def _relu_back(self, g32, act16):
+        g16 = torch.empty(g32.shape, dtype=BF16, device=self.dev)
+        return nn.relu_backward(g32, act16, g16)
+
+    def backward(self, gy16: torch.Tensor):
+        """gy16: gradient of the loss w.r.t. the forward output, bf16 [n, H, W, 8]."""
+        L = self.levels
+        c = self.convs["head"]
+        self._wgrad(c, gy16, self.inp["head"])
+        g = self._dgrad(c, gy16)  # d loss / d (output of the last decoder level)
+        skip_grad = {}
+        for lvl in range(L - 1):  # decoder levels, top (0) first
+            a, b, cat = self.mid[f"d{lvl}"], self.out[f"d{lvl}"], self.inp[f"d{lvl}"]
+            gz = self._relu_back(g, b)
+            cb = self.convs[f"d{lvl}b"]
+            self._wgrad(cb, gz, a)
+            g = self._dgrad(cb, gz)
+            gz = self._relu_back(g, a)
+            ca = self.convs[f"d{lvl}a"]
+            self._wgrad(ca, gz, cat)
+            gcat = self._dgrad(ca, gz)
+            n, hh, ww, ct = gcat.shape
+            cs = self.out[f"e{lvl}"].shape[3]
+            cu = ct - cs
+            sg = torch.empty((n, hh, ww, cs), dtype=F32, device=self.dev)
+            skip_grad[lvl] = nn.take_channels(gcat, cu, sg)
+            g = torch.empty((n, hh // 2, ww // 2, cu), dtype=F32, device=self.dev)
+            nn.upsample2_backward(gcat, g)
+        for lvl in range(L - 1, -1, -1):  # encoder, bottom first
+            a, b, x = self.mid[f"e{lvl}"], self.out[f"e{lvl}"], self.inp[f"e{lvl}"]
+            gz = self._relu_back(g, b)
+            cb = self.convs[f"e{lvl}b"]
+            self._wgrad(cb, gz, a)
+            g = self._dgrad(cb, gz)
+            gz = self._relu_back(g, a)
+            ca = self.convs[f"e{lvl}a"]
+            self._wgrad(ca, gz, x)
+            if lvl == 0:
+                break
+            gx = self._dgrad(ca, gz)  # gradient of the pooled input
+            g = nn.pool2_backward(gx, skip_grad[lvl - 1], accumulate=True)
+
+    def step(self, lr: float):
+        self.t += 1
+        for c in self.convs.values():
+            c.step(self.t, lr)
+
+
+# ------------------------------------------------------------------ data
+def example(xy_np: np.ndarray, res: int, iters: int, dev, radius: int = 8):
+    """Input [res, res, 8] bf16 and target [res, res, 2] f32 (the displacement
+    of the texel centres by `iters` iterations, in texels) of one point set."""
+    xy = torch.from_numpy(xy_np).to(dev)
+    n = xy.shape[0]
+    counts = torch.empty((res, res), dtype=torch.uint32, device=dev)
+    dens = torch.empty((res, res), dtype=F32, device=dev)
+    capi.rasterize(xy, res, radius=radius, counts=counts, density=dens)
+    x16 = torch.empty((res, res, CIN), dtype=BF16, device=dev)
+    nn.pack_density(dens, res * res / n, x16)
+    lat = torch.from_numpy(datagen.lattice_points(res)).to(dev)
+    capi.regularize_probes(xy.clone(), lat, res, iters, radius=radius)
+    tgt = torch.empty((res, res, 2), dtype=F32, device=dev)
+    nn.displacement(lat, res, tgt)
+    return x16, tgt
+
+
+def dataset(seeds, res: int, iters: int, dev, n_hi: int = 500_000):
+    xs, ts = [], []
+    for s in seeds:
+        x, t = example(datagen.surrogate_mixture(s, n_hi=n_hi), res, iters, dev)
+        xs.append(x)
+        ts.append(t)
+    return torch.stack(xs), torch.stack(ts)
+
+
+def train(net: UNet, X, T, steps: int, batch: int, lr: float = 1e-3, seed: int = 0, log=None) -> list:
+    """Adam on mini-batches drawn (seeded) from X, T; returns the losses."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    loss = torch.zeros(1, dtype=F32, device=net.dev)
+    losses = []
+    for s in range(steps):
+        idx = torch.from_numpy(g.choice(X.shape[0], size=batch, replace=False)).to(net.dev)
+        x, t = X[idx].contiguous(), T[idx].contiguous()
+        y = net.forward(x)
+        gy = torch.empty(y.shape, dtype=BF16, device=net.dev)
+        nn.mse(y, t, loss, gy)
+        net.backward(gy)
+        cur = lr * 0.5 * (1.0 + math.cos(math.pi * s / steps))  # cosine decay
+        net.step(cur)
+        losses.append(float(loss.item()) / t.numel())
+        if log and (s % 50 == 0 or s == steps - 1):
+            log(f"step {s} loss {losses[-1]:.4f}")
+    return losses
+
+
+# ------------------------------------------------------------------ use
+def bin_std(xy: torch.Tensor, res: int, bin_px: int = 4) -> float:
+    """Standard deviation of the sample counts over bin x bin texel blocks."""
+    counts = torch.empty((res, res), dtype=torch.uint32, device=xy.device)
+    capi.rasterize(xy, res, radius=0, counts=counts, want_density=False)
+    mom = torch.zeros(2, dtype=torch.float64, device=xy.device)
+    nn.bin_moments(counts, res, bin_px, mom)
+    s1, s2 = mom.tolist()
+    k = (res // bin_px) ** 2
+    return math.sqrt(max(s2 / k - (s1 / k) ** 2, 0.0))
+
+
+def predict_field(net: UNet, xy: torch.Tensor, res: int, radius: int = 8) -> torch.Tensor:
+    n = xy.shape[0]
+    dens = torch.empty((res, res), dtype=F32, device=xy.device)
+    counts = torch.empty((res, res), dtype=torch.uint32, device=xy.device)
+    capi.rasterize(xy, res, radius=radius, counts=counts, density=dens)
+    x16 = torch.empty((1, res, res, CIN), dtype=BF16, device=xy.device)
+    nn.pack_density(dens, res * res / n, x16)
+    y = net.forward(x16)
+    field = torch.empty((res, res, 2), dtype=F32, device=xy.device)
+    return nn.field(y[0], res, field)
+
+
+def regularize(net: UNet, xy: torch.Tensor, res: int, iters: int, min_gain: float = 0.2):
+    """Moves xy (in place) by the surrogate's field when its deformed lattice
+    has no fold and it lowers the bin standard deviation by at least
+    `min_gain`; otherwise runs the plain method.  Returns 'surrogate' or
+    'fallback'."""
+    before = bin_std(xy, res)
+    field = predict_field(net, xy, res)
+    folds = torch.zeros(1, dtype=torch.uint32, device=xy.device)
+    nn.count_folds(field, res, folds)
+    moved = xy.clone()
+    capi.advect(field, moved)
+    if int(folds.item()) == 0 and bin_std(moved, res) <= (1.0 - min_gain) * before:
+        xy.copy_(moved)
+        return "surrogate"
+    capi.regularize(xy, res, iters)
+    return "fallback"

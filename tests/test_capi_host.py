@@ -14,18 +14,22 @@ from paper_2408_06513_amd import capi
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_symbols() -> set[str]:
-    src = open(os.path.join(ROOT, "include", "inim.h")).read()
+def declared_symbols(header: str = "inim.h") -> set[str]:
+    src = open(os.path.join(ROOT, "include", header)).read()
     return set(re.findall(r"\b(inim_[a-z0-9_]+)\s*\(", src))
 
 
 def test_header_and_binding_agree():
+    from paper_2408_06513_amd import nn
     assert declared_symbols() == set(capi.EXPORTS)
+    assert declared_symbols("inim_nn.h") == set(nn.NN_EXPORTS)
+    headers = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    assert headers == ["inim.h", "inim_nn.h"]
 
 
 def test_library_exports_every_declared_symbol():
     L = capi.lib()
-    for name in declared_symbols():
+    for name in declared_symbols() | declared_symbols("inim_nn.h"):
         assert hasattr(L, name), name
 
 

@@ -1,0 +1,177 @@
+"""The surrogate's layers through the C ABI (marked gpu), against the FP64
+oracle (oracle/nn_oracle.py).  Convolutions of small integers are exact in
+FP32, so those comparisons are bit for bit (they pin the matrix-core lane
+layout and every index); random operands are held to the FP32 accumulation
+bound |err| <= 1e-3 * sum |x| |w|."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import nn_oracle as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+D, BF = torch.float64, torch.bfloat16
+
+CONV_SHAPES = [(2, 16, 16, 8, 8, 3), (1, 20, 13, 16, 40, 3), (2, 8, 8, 24, 136, 3), (1, 32, 32, 64, 8, 1),
+               (3, 5, 7, 8, 16, 3), (1, 64, 64, 32, 32, 3)]
+
+
+def note(msg):
+    print(f"[nn] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def nn():
+    from paper_2408_06513_amd import nn as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return torch.device("cuda:0")
+
+
+def ints(seed, shape, lo=-3, hi=3):
+    return torch.tensor(np.random.Generator(np.random.PCG64(seed)).integers(lo, hi + 1, size=shape), dtype=D)
+
+
+def normal(seed, shape, scale=1.0):
+    return O.bf16_round(torch.tensor(np.random.Generator(np.random.PCG64(seed)).standard_normal(shape) * scale, dtype=D))
+
+
+def g16(t, dev):
+    return t.to(torch.float32).to(BF).to(dev).contiguous()
+
+
+def g32(t, dev):
+    return t.to(torch.float32).to(dev).contiguous()
+
+
+@pytest.mark.parametrize("shape", CONV_SHAPES)
+def test_conv_forward_exact(nn, dev, shape):
+    n, h, w, cin, cout, ks = shape
+    note(f"conv forward {shape}")
+    x, wt, b = ints(1, (n, h, w, cin)), ints(2, (cout, ks * ks, cin)), ints(3, (cout,), -20, 20)
+    y32 = torch.empty((n, h, w, cout), dtype=torch.float32, device=dev)
+    y16 = torch.empty((n, h, w, cout), dtype=BF, device=dev)
+    nn.conv_forward(g16(x, dev), g16(wt, dev), g32(b, dev), relu=True, y16=y16, y32=y32)
+    ref = O.conv(x, wt, b, relu=True)
+    assert torch.equal(y32.cpu().double(), ref)
+    assert torch.equal(y16.cpu().double(), O.bf16_round(ref))
+
+
+@pytest.mark.parametrize("shape", CONV_SHAPES)
+def test_conv_backward_exact(nn, dev, shape):
+    n, h, w, cin, cout, ks = shape
+    note(f"conv backward {shape}")
+    x, wt, dy = ints(4, (n, h, w, cin)), ints(5, (cout, ks * ks, cin)), ints(6, (n, h, w, cout))
+    xr, wr = x.clone().requires_grad_(True), wt.clone().requires_grad_(True)
+    br = torch.zeros(cout, dtype=D, requires_grad=True)
+    (O.conv(xr, wr, br) * dy).sum().backward()
+    w16 = g16(wt, dev)
+    wT = torch.empty((cin, ks * ks, cout), dtype=BF, device=dev)
+    nn.weight_transpose(w16, wT)
+    assert torch.equal(wT.cpu(), w16.cpu().permute(2, 1, 0).contiguous())
+    dx = torch.empty((n, h, w, cin), dtype=torch.float32, device=dev)
+    nn.conv_backward_data(g16(dy, dev), wT, dx)
+    assert torch.equal(dx.cpu().double(), xr.grad)
+    dw = torch.empty((cout, ks * ks, cin), dtype=torch.float32, device=dev)
+    db = torch.empty(cout, dtype=torch.float32, device=dev)
+    nn.conv_backward_weight(g16(dy, dev), g16(x, dev), ks, dw, db)
+    assert torch.equal(dw.cpu().double(), wr.grad)
+    assert torch.equal(db.cpu().double(), br.grad)
+
+
+def test_conv_random_operands_within_fp32_bound(nn, dev):
+    n, h, w, cin, cout, ks = 2, 32, 32, 256, 128, 3
+    x, wt = normal(7, (n, h, w, cin)), normal(8, (cout, ks * ks, cin), 0.05)
+    y = torch.empty((n, h, w, cout), dtype=torch.float32, device=dev)
+    nn.conv_forward(g16(x, dev), g16(wt, dev), None, y32=y)
+    ref = O.conv(x, wt)
+    bound = O.conv(x.abs(), wt.abs())
+    assert ((y.cpu().double() - ref).abs() <= 1e-3 * bound + 1e-6).all()
+
+
+def test_elementwise_layers(nn, dev):
+    n, h, w, c = 2, 8, 12, 16
+    x = normal(9, (n, h, w, c))
+    p = torch.empty((n, h // 2, w // 2, c), dtype=BF, device=dev)
+    nn.pool2(g16(x, dev), p)
+    assert torch.allclose(p.cpu().double(), O.bf16_round(O.pool2(x)), rtol=0, atol=0)
+    dy = normal(10, (n, h // 2, w // 2, c))
+    dx = g32(normal(11, (n, h, w, c)), dev)
+    base = dx.cpu().double()
+    nn.pool2_backward(g32(dy, dev), dx, accumulate=True)
+    ref = base + torch.repeat_interleave(torch.repeat_interleave(dy, 2, 1), 2, 2) / 4
+    assert torch.allclose(dx.cpu().double(), ref, rtol=1e-6, atol=1e-6)
+    # concatenation [up(a) | b] and its gradient
+    a, b = normal(12, (n, h // 2, w // 2, 8)), normal(13, (n, h, w, 24))
+    cat = torch.empty((n, h, w, 32), dtype=BF, device=dev)
+    nn.upsample2_into(g16(a, dev), cat, 0)
+    nn.copy_channels_into(g16(b, dev), cat, 8)
+    assert torch.equal(cat.cpu().double(), torch.cat([O.up2(a), b], dim=-1))
+    gcat = normal(14, (n, h, w, 32))
+    da = torch.empty((n, h // 2, w // 2, 8), dtype=torch.float32, device=dev)
+    nn.upsample2_backward(g32(gcat, dev), da)
+    assert torch.allclose(da.cpu().double(), gcat[..., :8].reshape(n, h // 2, 2, w // 2, 2, 8).sum(dim=(2, 4)),
+                          rtol=1e-6, atol=1e-6)
+    db = torch.empty((n, h, w, 24), dtype=torch.float32, device=dev)
+    nn.take_channels(g32(gcat, dev), 8, db)
+    assert torch.equal(db.cpu().double(), gcat[..., 8:].float().double())
+    # ReLU gradient with the mask of the layer's output, BF16 cast
+    g = normal(15, (n, h, w, c))
+    act = normal(16, (n, h, w, c)).clamp(min=0)
+    out = torch.empty((n, h, w, c), dtype=BF, device=dev)
+    nn.relu_backward(g32(g, dev), g16(act, dev), out)
+    assert torch.equal(out.cpu().double(), O.bf16_round(g * (act > 0)))
+    f = torch.tensor([1.0, 1.00390625, 1.01171875, -3.3e-5, 65504.0, 1e-40], dtype=torch.float32)
+    b16 = torch.empty(6, dtype=BF, device=dev)
+    nn.to_bf16(f.to(dev), b16)
+    assert torch.equal(b16.cpu(), f.to(BF))
+
+
+def test_mse_and_adam(nn, dev):
+    pred, tgt = normal(17, (2, 8, 8, 8)), normal(18, (2, 8, 8, 2))
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    grad = torch.empty((2, 8, 8, 8), dtype=BF, device=dev)
+    nn.mse(g32(pred, dev), g32(tgt, dev), loss, grad)
+    assert abs(float(loss.item()) - float(O.mse(pred, tgt))) <= 1e-5 * float(O.mse(pred, tgt))
+    gref = torch.zeros_like(pred)
+    gref[..., :2] = 2 * (pred[..., :2] - tgt) / tgt.numel()
+    assert torch.allclose(grad.cpu().double(), O.bf16_round(gref), rtol=1e-2, atol=1e-7)
+    w0, gr = normal(19, (1000,)), normal(20, (1000,))
+    w, m, v = g32(w0, dev), torch.zeros(1000, device=dev), torch.zeros(1000, device=dev)
+    wr, mr, vr = w0.clone(), torch.zeros(1000, dtype=D), torch.zeros(1000, dtype=D)
+    for step in (1, 2, 3):
+        nn.adam(w, g32(gr, dev), m, v, step, lr=0.01)
+        wr, mr, vr = O.adam_step(wr, gr, mr, vr, step, lr=0.01)
+    assert torch.allclose(w.cpu().double(), wr, rtol=0, atol=1e-5)
+
+
+def test_unet_forward_and_gradients_match_oracle(dev):
+    from paper_2408_06513_amd import surrogate as S
+    chans = (8, 16, 16)
+    net = S.UNet(dev, seed=3, chans=chans)
+    x = normal(21, (2, 16, 16, 8))
+    t = normal(22, (2, 16, 16, 2))
+    y = net.forward(g16(x, dev))
+    p = net.params_f64()
+    loss, grads, yref = O.unet_loss_grads(p, x, t, levels=3, bf16=True)
+    yg = y.cpu().double()
+    assert (yg - yref).abs().max() <= 2e-2 * yref.abs().max()
+    lo = torch.zeros(1, dtype=torch.float32, device=dev)
+    gy = torch.empty(y.shape, dtype=BF, device=dev)
+    from paper_2408_06513_amd import nn as m
+    m.mse(y, g32(t, dev), lo, gy)
+    net.backward(gy)
+    for name, c in net.convs.items():
+        for key, gpu in ((name + ".w", c.gw), (name + ".b", c.gb)):
+            a, b = gpu.cpu().double().reshape(-1), grads[key].reshape(-1)
+            cos = float((a @ b) / (a.norm() * b.norm() + 1e-300))
+            assert cos >= 0.995, (key, cos)
+            assert abs(float(a.norm() / b.norm()) - 1.0) <= 0.03, (key, float(a.norm() / b.norm()))
