@@ -11,6 +11,8 @@ Also reported:
     texel lattice moved along as probe points (composite map output);
   - a 45-plot scatterplot matrix (200,000 samples x 10 dims, rasters of
     256/512/1024, 6 iterations) in one batched call against 45 single calls;
+  - the learned surrogate at 256 x 256 (trained here by the project's
+    kernels), against the method on held-out point sets;
   - the integral images alone on 8192 x 8192 rasters (uint32 Poisson(4) and
     float32 lognormal, all eight planes): Gpixel/s and GB/s;
   - the FP64 CPU oracle timed on the same workload (cpu_baseline).
@@ -288,6 +290,81 @@ def bench_splom(dev, reps: int = 5) -> dict:
             "speedup_vs_sequential": round(t_seq / best, 2)}
 
 
+def bench_surrogate(dev, train_sets: int = 1024, steps: int = 2500, held_out: int = 16) -> dict:
+    """Learned surrogate at 256 x 256, 8 iterations: trained here on the GPU
+    by the project's kernels from point sets of 2-12 Gaussian components
+    (10k-500k points) labelled by the method itself, then compared with the
+    method on held-out point sets (uniformity, folds, gate decisions) and
+    timed per raster (events around the calls)."""
+    import numpy as np
+    import torch
+
+    from paper_2408_06513_amd import capi, datagen, nn
+    from paper_2408_06513_amd import surrogate as S
+    res, iters = 256, 8
+    log(f"surrogate: {train_sets} training sets")
+    t0 = time.perf_counter()
+    X, T = S.dataset(range(train_sets), res, iters, dev)
+    t_data = time.perf_counter() - t0
+    net = S.UNet(dev, seed=0)
+    log(f"surrogate: {steps} training steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = S.train(net, X, T, steps=steps, batch=8, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del X, T
+    seeds = range(100_000, 100_000 + held_out)
+    ev = S.evaluate(net, seeds, res, iters, dev)
+
+    def ev_time(fn, reps=5):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    plain_ms, sur_ms = [], []
+    for s in seeds:
+        xy0 = torch.from_numpy(datagen.surrogate_mixture(s)).to(dev)
+        xy = xy0.clone()
+        ws = capi.workspace(capi.workspace_size(res, xy.shape[0]), dev)
+        plain_ms.append(ev_time(lambda: (xy.copy_(xy0), capi.regularize(xy, res, iters, ws=ws, check=False))))
+
+        def sur():
+            xy.copy_(xy0)
+            f = S.predict_field(net, xy, res)
+            capi.advect(f, xy)
+        sur_ms.append(ev_time(sur))
+    # the held-out sets together: one batched forward pass
+    xs0 = [torch.from_numpy(datagen.surrogate_mixture(s)).to(dev) for s in seeds]
+    xs = [x.clone() for x in xs0]
+
+    def many():
+        for x, x0 in zip(xs, xs0):
+            x.copy_(x0)
+        S.regularize_many(net, xs, res)
+    t_batch = ev_time(many, 3) / len(xs)
+    t_plain_all = float(np.sum(plain_ms)) / len(xs)
+    rec = {"res": res, "iters": iters, "train_sets": train_sets, "train_steps": steps, "batch": 8,
+           "data_s": round(t_data, 1), "train_s": round(t_train, 1),
+           "loss_first10": round(float(np.mean(losses[:10])), 4), "loss_last10": round(float(np.mean(losses[-10:])), 4),
+           "held_out": held_out, "explained_variance": round(ev["explained"], 4),
+           "bin_std_gain_plain": round(ev["plain_gain"], 4), "bin_std_gain_surrogate": round(ev["surrogate_gain"], 4),
+           "folded_triangles": ev["folds"], "gate_fallbacks": ev["fallbacks"],
+           "plain_ms_per_raster": round(float(np.mean(plain_ms)), 4),
+           "surrogate_ms_per_raster": round(float(np.mean(sur_ms)), 4),
+           f"surrogate_ms_per_raster_batch{held_out}": round(t_batch, 4)}
+    rec["speedup_vs_plain"] = round(rec["plain_ms_per_raster"] / rec["surrogate_ms_per_raster"], 3)
+    rec[f"speedup_vs_plain_batch{held_out}"] = round(t_plain_all / t_batch, 3)
+    return rec
+
+
 def cpu_baseline(xy0_np, res: int, iters: int, budget_s: float) -> dict:
     import oracle
     log("cpu baseline (oracle)")
@@ -314,6 +391,7 @@ def main():
     ap.add_argument("--no-inim", action="store_true", help="skip the 8192^2 integral-image measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-splom", action="store_true", help="skip the 45-plot scatterplot-matrix measurement")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip training and timing the learned surrogate")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--only-inim", action="store_true",
                     help="print only the 8192^2 integral-image measurement (for profiling)")
@@ -366,6 +444,8 @@ def main():
         rec["inim_8192_all_planes"] = bench_inim(dev)
     if not args.no_splom:
         rec["splom_45_plots"] = bench_splom(dev)
+    if not args.no_surrogate:
+        rec["surrogate_256"] = bench_surrogate(dev)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(xy0_np, args.res, args.iters, args.cpu_seconds)
     print(json.dumps(rec), flush=True)

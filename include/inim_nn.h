@@ -37,24 +37,30 @@ typedef uint16_t inim_bf16;
 
 const char* inim_nn_last_error(void);
 
+/* Device work buffer for the three calls below on a layer of this shape:
+ * FP32 partial sums of the K range split into slices when the output alone
+ * has too few 128 x 128 tiles to fill the GPU.  The slices are added in a
+ * fixed order, so results do not depend on timing. */
+int inim_conv_workspace(int32_t imgs, int32_t h, int32_t w, int32_t cin, int32_t cout, int32_t ks, size_t* bytes);
+
 /* y[p][co] = act(bias[co] + sum over taps t and cin of x[p + off_t][ci] w[co][t][ci]);
  * act = max(., 0) when relu != 0.  bias may be NULL.  Writes y16 (BF16) and/or
- * y32 (FP32) when not NULL. */
+ * y32 (FP32) when not NULL.  work may be NULL (no split of the K range). */
 int inim_conv_forward(const inim_bf16* x, int32_t imgs, int32_t h, int32_t w, int32_t cin, const inim_bf16* weight,
-                      const float* bias, int32_t cout, int32_t ks, int32_t relu, inim_bf16* y16, float* y32,
-                      hipStream_t stream);
+                      const float* bias, int32_t cout, int32_t ks, int32_t relu, inim_bf16* y16, float* y32, void* work,
+                      size_t work_bytes, hipStream_t stream);
 
 /* Gradient of the input: dx[q][ci] = sum over t and co of dy[q - off_t][co] w[co][t][ci],
- * with weight_t = inim_weight_transpose(weight) = [cin][ks*ks][cout].  FP32 dx. */
+ * with weight_t = inim_weight_transpose(weight) = [cin][ks*ks][cout].  FP32 dx.
+ * work may be NULL (no split of the K range). */
 int inim_conv_backward_data(const inim_bf16* dy, int32_t imgs, int32_t h, int32_t w, int32_t cin,
-                            const inim_bf16* weight_t, int32_t cout, int32_t ks, float* dx, hipStream_t stream);
+                            const inim_bf16* weight_t, int32_t cout, int32_t ks, float* dx, void* work,
+                            size_t work_bytes, hipStream_t stream);
 
 /* Gradient of the weights and bias: dweight[co][t][ci] = sum over pixels p of
  * dy[p][co] x[p + off_t][ci]; dbias[co] = sum over p of dy[p][co] (dbias may be
- * NULL).  FP32; `work` (device) of inim_conv_backward_weight_workspace bytes
- * holds partial sums, reduced in a fixed order. */
-int inim_conv_backward_weight_workspace(int32_t imgs, int32_t h, int32_t w, int32_t cin, int32_t cout, int32_t ks,
-                                        size_t* bytes);
+ * NULL).  FP32; work of inim_conv_workspace bytes (required) holds the partial
+ * sums over slices of the pixels. */
 int inim_conv_backward_weight(const inim_bf16* dy, const inim_bf16* x, int32_t imgs, int32_t h, int32_t w, int32_t cin,
                               int32_t cout, int32_t ks, float* dweight, float* dbias, void* work, size_t work_bytes,
                               hipStream_t stream);
@@ -108,12 +114,16 @@ int inim_nn_pack_density(const float* density, int32_t res, float scale, int32_t
 
 /* Training target from probes started at the texel centres and moved by the
  * whole iteration (inim_regularize_probes): out [res][res][2] = (probe -
- * texel centre) * res, the displacement in texels. */
+ * texel centre) * 64, the displacement in units of 1/64 of the unit square
+ * (the same scale at every raster size). */
 int inim_nn_displacement(const float* probe, int32_t res, float* out, hipStream_t stream);
 
 /* The deformation field of a network output y [res][res][c] (c >= 2):
- * field [res][res][2] = texel centre + y[..][0..1] / res, for inim_advect. */
-int inim_nn_field(const float* y, int32_t c, int32_t res, float* field, hipStream_t stream);
+ * field [res][res][2] = texel centre + (y[..][0..1] smoothed) / 64, for
+ * inim_advect.  The smoothing is the normalised Gaussian of standard
+ * deviation radius / 2 over |dx|, |dy| <= radius (indices clamped to the
+ * raster); radius 0..16, 0 = none. */
+int inim_nn_field(const float* y, int32_t c, int32_t res, int32_t radius, float* field, hipStream_t stream);
 
 /* Adds to *count (device) the number of lattice triangles (two per cell) of
  * the deformed texel lattice `field` with non-positive signed area (folds). */

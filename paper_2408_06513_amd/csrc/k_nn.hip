@@ -92,22 +92,40 @@ struct WeightLoader {  // B of forward / input gradient: rows of [N][K] contiguo
     }
 };
 
+// One K step of 32 in flight: the four 8-element chunks this thread moves
+// (two of A, two of B), loaded from global memory into registers while the
+// matrix cores work on the previous step, then written to LDS.
+struct Chunks {
+    u16x8 a[2], b[2];
+};
+
 template <class LA, class LB>
-__device__ __forceinline__ void stage_vec(GemmLds& s, const LA& la, const LB& lb, int bm, int bn, int k0) {
-    // 128 x 32 of A and of B: 512 chunks of 8 each, two per thread
+__device__ __forceinline__ void load_vec(Chunks& c, const LA& la, const LB& lb, int bm, int bn, int k0) {
+    // 128 rows x 32 k of A and of B: 512 chunks of 8 each, two per thread
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int c = threadIdx.x + 256 * h;
-        const int r = c >> 2, kc = (c & 3) * 8;
-        *reinterpret_cast<u16x8*>(&s.a[r][kc]) = la.load8(bm + r, k0 + kc);
-        *reinterpret_cast<u16x8*>(&s.b[r][kc]) = lb.load8(bn + r, k0 + kc);
+        const int e = threadIdx.x + 256 * h;
+        const int r = e >> 2, kc = (e & 3) * 8;
+        c.a[h] = la.load8(bm + r, k0 + kc);
+        c.b[h] = lb.load8(bn + r, k0 + kc);
+    }
+}
+
+__device__ __forceinline__ void store_vec(const Chunks& c, GemmLds& s) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int e = threadIdx.x + 256 * h;
+        const int r = e >> 2, kc = (e & 3) * 8;
+        *reinterpret_cast<u16x8*>(&s.a[r][kc]) = c.a[h];
+        *reinterpret_cast<u16x8*>(&s.b[r][kc]) = c.b[h];
     }
 }
 
 // Weight gradient: dW[co][(t, ci)] = sum_p dy[p][co] x[p + off_t][ci], i.e.
-// A[co][p] = dy[p][co] and B[p][(t, ci)] = x[p + off_t][ci]: element-wise
-// loads with consecutive threads on consecutive channels (coalesced),
-// transposed into the [row][k] LDS layout.
+// A[co][p] = dy[p][co] and B[p][(t, ci)] = x[p + off_t][ci].  Each chunk is
+// 8 channels of one pixel (a 16-byte load, Cout and Cin multiples of 8, so a
+// chunk of (t, ci) stays in one tap), written transposed into the [row][k]
+// LDS layout.
 struct WgradSrc {
     const uint16_t* dy;  // [P][Cout]
     const uint16_t* x;   // [P][Cin]
@@ -115,28 +133,35 @@ struct WgradSrc {
     ConvGeom g;
 };
 
-__device__ __forceinline__ void stage_wgrad(GemmLds& s, const WgradSrc& w, int bm, int bn, int k0) {
-    // A: 128 co x 32 p, co fastest
-#pragma unroll 4
-    for (int h = 0; h < (kBM * kBK) / 256; ++h) {
+__device__ __forceinline__ void load_wgrad(Chunks& c, const WgradSrc& w, int bm, int bn, int k0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
         const int e = threadIdx.x + 256 * h;
-        const int r = e % kBM, k = e / kBM;
-        const int co = bm + r, p = k0 + k;
-        s.a[r][k] = (co < w.Cout && p < w.g.P) ? w.dy[(size_t)p * w.Cout + co] : (uint16_t)0;
-    }
-    // B: 32 p x 128 (t, ci), (t, ci) fastest
-#pragma unroll 4
-    for (int h = 0; h < (kBN * kBK) / 256; ++h) {
-        const int e = threadIdx.x + 256 * h;
-        const int r = e % kBN, k = e / kBN;
-        const int n = bn + r, p = k0 + k;
-        uint16_t v = 0;
-        if (n < w.N && p < w.g.P) {
+        const int kk = e >> 4, rc = (e & 15) * 8;  // pixel k0 + kk; rows rc .. rc + 7 of the tile
+        const int p = k0 + kk;
+        const int co = bm + rc;
+        c.a[h] = (p < w.g.P && co < w.Cout) ? *reinterpret_cast<const u16x8*>(w.dy + (size_t)p * w.Cout + co) : zero8();
+        const int n = bn + rc;
+        u16x8 v = zero8();
+        if (p < w.g.P && n < w.N) {
             const int t = n / w.Cin, ci = n - t * w.Cin;
             int q;
-            if (w.g.shift(p, t, 1, q)) v = w.x[(size_t)q * w.Cin + ci];
+            if (w.g.shift(p, t, 1, q)) v = *reinterpret_cast<const u16x8*>(w.x + (size_t)q * w.Cin + ci);
         }
-        s.b[r][k] = v;
+        c.b[h] = v;
+    }
+}
+
+__device__ __forceinline__ void store_wgrad(const Chunks& c, GemmLds& s) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int e = threadIdx.x + 256 * h;
+        const int kk = e >> 4, rc = (e & 15) * 8;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            s.a[rc + j][kk] = c.a[h][j];
+            s.b[rc + j][kk] = c.b[h][j];
+        }
     }
 }
 
@@ -159,10 +184,33 @@ __device__ __forceinline__ void mma_step(const GemmLds& s, f32x16 (&acc)[2][2], 
     }
 }
 
+// The K loop over [kbeg, kend) with two LDS buffers: the global loads of
+// step i+1 are issued before the MFMAs of step i and written to the other
+// buffer after them; one barrier per step.
+template <class Load, class Store>
+__device__ __forceinline__ void gemm_loop(GemmLds (&s)[2], f32x16 (&acc)[2][2], int kbeg, int kend, Load load,
+                                          Store store) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
+    Chunks c;
+    if (kbeg >= kend) return;
+    load(c, kbeg);
+    store(c, s[0]);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += kBK) {
+        const bool more = k0 + kBK < kend;
+        if (more) load(c, k0 + kBK);
+        mma_step(s[cur], acc, wm, wn, lane);
+        if (more) store(c, s[cur ^ 1]);
+        __syncthreads();
+        cur ^= 1;
+    }
+}
+
 // Epilogue over this wave's results: f(m, n, value).
 template <class F>
-__device__ __forceinline__ void for_each_result(const f32x16 (&acc)[2][2], int bm, int bn, int wm, int wn, int lane,
-                                                F f) {
+__device__ __forceinline__ void for_each_result(const f32x16 (&acc)[2][2], int bm, int bn, F f) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -175,24 +223,36 @@ __device__ __forceinline__ void for_each_result(const f32x16 (&acc)[2][2], int b
             }
 }
 
-// Forward convolution: y[p][co] = act(b[co] + sum x w), stored as BF16
-// (y16) and/or FP32 (y32); relu != 0 applies max(., 0).
-__global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
-    __shared__ GemmLds s;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
+// K range of split slice z (slices of `kslice`, a multiple of 32).
+__device__ __forceinline__ void k_range(int K, int kslice, int& kbeg, int& kend) {
+    kbeg = blockIdx.z * kslice;
+    kend = min(K, kbeg + kslice);
+}
+
+// Forward convolution.  With gridDim.z == 1 the epilogue writes
+// y = act(b + sum x w) as BF16 (y16) and/or FP32 (y32); with gridDim.z > 1
+// slice z of the K range writes its FP32 partial sums to part[z][p][co] and
+// k_conv_finish completes the layer.
+__global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a, int kslice, float* part) {
+    __shared__ GemmLds s[2];
     const int bm = blockIdx.x * kBM, bn = blockIdx.y * kBN;
     const ConvGeom g{a.H, a.W, a.P, a.ks, a.ks * a.ks, a.ks / 2};
     const int K = g.taps * a.Cin;
     const RowShiftLoader la{a.x, a.Cin, 1, a.P, K, g};
     const WeightLoader lb{a.w, a.Cout, K};
+    int kbeg, kend;
+    k_range(K, kslice, kbeg, kend);
     f32x16 acc[2][2] = {};
-    for (int k0 = 0; k0 < K; k0 += kBK) {
-        stage_vec(s, la, lb, bm, bn, k0);
-        __syncthreads();
-        mma_step(s, acc, wm, wn, lane);
-        __syncthreads();
+    gemm_loop(s, acc, kbeg, kend, [&](Chunks& c, int k0) { load_vec(c, la, lb, bm, bn, k0); },
+              [&](const Chunks& c, GemmLds& l) { store_vec(c, l); });
+    if (gridDim.z > 1) {
+        float* out = part + (size_t)blockIdx.z * a.P * a.Cout;
+        for_each_result(acc, bm, bn, [&](int m, int n, float v) {
+            if (m < a.P && n < a.Cout) out[(size_t)m * a.Cout + n] = v;
+        });
+        return;
     }
-    for_each_result(acc, bm, bn, wm, wn, lane, [&](int m, int n, float v) {
+    for_each_result(acc, bm, bn, [&](int m, int n, float v) {
         if (m >= a.P || n >= a.Cout) return;
         v += a.bias ? a.bias[n] : 0.0f;
         if (a.relu) v = v > 0.0f ? v : 0.0f;
@@ -202,49 +262,56 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
     });
 }
 
-// Input gradient: dx[q][ci] = sum_{t, co} dy[q - off_t][co] wT[ci][t][co], FP32.
-__global__ __launch_bounds__(256) void k_conv_dgrad(ConvArgs a) {
-    __shared__ GemmLds s;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
+// Completion of a split forward convolution: sum of the slices in order,
+// bias, ReLU, stores.
+__global__ __launch_bounds__(256) void k_conv_finish(ConvArgs a, int slices, const float* __restrict__ part) {
+    const size_t n = (size_t)a.P * a.Cout;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        float v = 0.0f;
+        for (int z = 0; z < slices; ++z) v += part[(size_t)z * n + i];
+        v += a.bias ? a.bias[i % a.Cout] : 0.0f;
+        if (a.relu) v = v > 0.0f ? v : 0.0f;
+        if (a.y16) a.y16[i] = f2bf(v);
+        if (a.y32) a.y32[i] = v;
+    }
+}
+
+// Input gradient: dx[q][ci] = sum_{t, co} dy[q - off_t][co] wT[ci][t][co],
+// FP32; split slices write part[z] and k_sum_parts adds them.
+__global__ __launch_bounds__(256) void k_conv_dgrad(ConvArgs a, int kslice, float* part) {
+    __shared__ GemmLds s[2];
     const int bm = blockIdx.x * kBM, bn = blockIdx.y * kBN;
     const ConvGeom g{a.H, a.W, a.P, a.ks, a.ks * a.ks, a.ks / 2};
     const int K = g.taps * a.Cout;
     const RowShiftLoader la{a.dy, a.Cout, -1, a.P, K, g};
     const WeightLoader lb{a.wT, a.Cin, K};
+    int kbeg, kend;
+    k_range(K, kslice, kbeg, kend);
     f32x16 acc[2][2] = {};
-    for (int k0 = 0; k0 < K; k0 += kBK) {
-        stage_vec(s, la, lb, bm, bn, k0);
-        __syncthreads();
-        mma_step(s, acc, wm, wn, lane);
-        __syncthreads();
-    }
-    for_each_result(acc, bm, bn, wm, wn, lane, [&](int m, int n, float v) {
-        if (m >= a.P || n >= a.Cin) return;
-        a.dx[(size_t)m * a.Cin + n] = v;
+    gemm_loop(s, acc, kbeg, kend, [&](Chunks& c, int k0) { load_vec(c, la, lb, bm, bn, k0); },
+              [&](const Chunks& c, GemmLds& l) { store_vec(c, l); });
+    float* out = gridDim.z > 1 ? part + (size_t)blockIdx.z * a.P * a.Cin : a.dx;
+    for_each_result(acc, bm, bn, [&](int m, int n, float v) {
+        if (m < a.P && n < a.Cin) out[(size_t)m * a.Cin + n] = v;
     });
 }
 
 // Weight gradient, FP32 [Cout][taps][Cin]; K (pixels) split over gridDim.z
 // slices of `kslice` pixels, each slice writing its own partial [slice][...].
 __global__ __launch_bounds__(256) void k_conv_wgrad(ConvArgs a, int kslice) {
-    __shared__ GemmLds s;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
+    __shared__ GemmLds s[2];
     const int bm = blockIdx.x * kBM, bn = blockIdx.y * kBN;
     const ConvGeom g{a.H, a.W, a.P, a.ks, a.ks * a.ks, a.ks / 2};
     const int N = g.taps * a.Cin;
     const WgradSrc src{a.dy, a.x, a.Cout, a.Cin, N, g};
-    const int kbeg = blockIdx.z * kslice, kend = min(a.P, kbeg + kslice);
+    int kbeg, kend;
+    k_range(a.P, kslice, kbeg, kend);
     f32x16 acc[2][2] = {};
-    for (int k0 = kbeg; k0 < kend; k0 += kBK) {
-        stage_wgrad(s, src, bm, bn, k0);
-        __syncthreads();
-        mma_step(s, acc, wm, wn, lane);
-        __syncthreads();
-    }
+    gemm_loop(s, acc, kbeg, kend, [&](Chunks& c, int k0) { load_wgrad(c, src, bm, bn, k0); },
+              [&](const Chunks& c, GemmLds& l) { store_wgrad(c, l); });
     float* out = a.dw + (size_t)blockIdx.z * a.Cout * N;
-    for_each_result(acc, bm, bn, wm, wn, lane, [&](int m, int n, float v) {
-        if (m >= a.Cout || n >= N) return;
-        out[(size_t)m * N + n] = v;
+    for_each_result(acc, bm, bn, [&](int m, int n, float v) {
+        if (m < a.Cout && n < N) out[(size_t)m * N + n] = v;
     });
 }
 
@@ -445,26 +512,46 @@ __global__ __launch_bounds__(256) void k_pack_density(const float* __restrict__ 
     }
 }
 
-// Training target: the displacement of every texel centre in texel units,
-// out[p][c] = (probe[p][c] - ((i or j) + 1/2) / N) * N, p = j N + i.
+// Displacements are expressed in units of 1/64 of the unit square, so that
+// targets of every raster size have the same scale.
+constexpr float kDispUnit = 64.0f;
+
+// Training target: out[p][c] = (probe[p][c] - texel centre) * 64, p = j N + i.
 __global__ __launch_bounds__(256) void k_displacement(const float2* __restrict__ probe, int N, float* __restrict__ out) {
     const size_t n = (size_t)N * N;
     for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
         const int j = (int)(p / N), i = (int)(p - (size_t)j * N);
         const float2 q = probe[p];
-        out[2 * p] = (q.x - ((float)i + 0.5f) / (float)N) * (float)N;
-        out[2 * p + 1] = (q.y - ((float)j + 0.5f) / (float)N) * (float)N;
+        out[2 * p] = (q.x - ((float)i + 0.5f) / (float)N) * kDispUnit;
+        out[2 * p + 1] = (q.y - ((float)j + 0.5f) / (float)N) * kDispUnit;
     }
 }
 
 // The deformation field of the network's output: field[p] = texel centre +
-// output[p][0..1] / N (channels beyond the first two are ignored).
-__global__ __launch_bounds__(256) void k_field_from_output(const float* __restrict__ y, int C, int N,
+// (smoothed output[p][0..1]) / 64, the output first convolved with the
+// normalised Gaussian exp(-m^2 / (2 (r/2)^2)), |m| <= r, along both axes
+// (clamped at the border); r = 0: no smoothing.  Channels beyond the first
+// two are ignored.
+__global__ __launch_bounds__(256) void k_field_from_output(const float* __restrict__ y, int C, int N, int r,
                                                            float2* __restrict__ field) {
     const size_t n = (size_t)N * N;
+    const float s2 = r > 0 ? 0.5f / (0.25f * r * r) : 0.0f;
     for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
         const int j = (int)(p / N), i = (int)(p - (size_t)j * N);
-        field[p] = make_float2(((float)i + 0.5f + y[p * C]) / (float)N, ((float)j + 0.5f + y[p * C + 1]) / (float)N);
+        float ax = 0.0f, ay = 0.0f, wsum = 0.0f;
+        for (int dy = -r; dy <= r; ++dy) {
+            const int jj = min(max(j + dy, 0), N - 1);
+            for (int dx = -r; dx <= r; ++dx) {
+                const int ii = min(max(i + dx, 0), N - 1);
+                const float w = __expf(-(float)(dx * dx + dy * dy) * s2);
+                const size_t q = ((size_t)jj * N + ii) * C;
+                ax += w * y[q];
+                ay += w * y[q + 1];
+                wsum += w;
+            }
+        }
+        field[p] = make_float2(((float)i + 0.5f) / (float)N + ax / wsum / kDispUnit,
+                               ((float)j + 0.5f) / (float)N + ay / wsum / kDispUnit);
     }
 }
 
@@ -567,13 +654,24 @@ int check_conv(int32_t imgs, int32_t h, int32_t w, int32_t cin, int32_t cout, in
     return INIM_OK;
 }
 
-int wgrad_slices(int64_t P, int cout, int cin, int ks) {
-    const int64_t tiles = ((cout + kTile - 1) / kTile) * ((int64_t)(ks * ks * cin + kTile - 1) / kTile);
+// Slices of a K range of `klen` for an M x N tile grid: enough blocks to
+// fill the chip (512), each slice at least 4 steps of 32.
+int split_slices(int64_t rows, int64_t cols, int64_t klen) {
+    const int64_t tiles = ((rows + kTile - 1) / kTile) * ((cols + kTile - 1) / kTile);
     int64_t s = (512 + tiles - 1) / tiles;
-    const int64_t steps = (P + kStepK - 1) / kStepK;
-    if (s > steps) s = steps;
+    const int64_t steps = (klen + kStepK - 1) / kStepK;
+    if (s > steps / 4) s = steps / 4;
     return (int)(s < 1 ? 1 : s);
 }
+
+int slice_len(int64_t klen, int slices) {
+    const int64_t steps = (klen + kStepK - 1) / kStepK;
+    return (int)((steps + slices - 1) / slices) * kStepK;
+}
+
+int wgrad_slices(int64_t P, int cout, int cin, int ks) { return split_slices(cout, (int64_t)ks * ks * cin, P); }
+int fwd_slices(int64_t P, int cin, int cout, int ks) { return split_slices(P, cout, (int64_t)ks * ks * cin); }
+int dgrad_slices(int64_t P, int cin, int cout, int ks) { return split_slices(P, cin, (int64_t)ks * ks * cout); }
 
 }  // namespace
 
@@ -581,48 +679,68 @@ extern "C" {
 
 const char* inim_nn_last_error(void) { return g_nn_error.c_str(); }
 
-int inim_conv_forward(const inim_bf16* x, int32_t imgs, int32_t h, int32_t w, int32_t cin, const inim_bf16* weight,
-                      const float* bias, int32_t cout, int32_t ks, int32_t relu, inim_bf16* y16, float* y32,
-                      hipStream_t stream) {
-    int s = check_conv(imgs, h, w, cin, cout, ks);
-    if (s != INIM_OK) return s;
-    if (!x || !weight || (!y16 && !y32)) return nfail(INIM_EINVAL, "x, weight or both outputs NULL");
-    ConvArgs a{};
-    a.x = x; a.w = weight; a.bias = bias; a.y16 = y16; a.y32 = y32;
-    a.H = h; a.W = w; a.P = imgs * h * w; a.Cin = cin; a.Cout = cout; a.ks = ks; a.relu = relu ? 1 : 0;
-    hipLaunchKernelGGL(k_conv_fwd, dim3((a.P + kTile - 1) / kTile, (cout + kTile - 1) / kTile), dim3(256), 0, stream, a);
-    return launched("conv forward");
-}
-
-int inim_conv_backward_data(const inim_bf16* dy, int32_t imgs, int32_t h, int32_t w, int32_t cin,
-                            const inim_bf16* weight_t, int32_t cout, int32_t ks, float* dx, hipStream_t stream) {
-    int s = check_conv(imgs, h, w, cin, cout, ks);
-    if (s != INIM_OK) return s;
-    if (!dy || !weight_t || !dx) return nfail(INIM_EINVAL, "dy, weight_t or dx NULL");
-    ConvArgs a{};
-    a.dy = dy; a.wT = weight_t; a.dx = dx;
-    a.H = h; a.W = w; a.P = imgs * h * w; a.Cin = cin; a.Cout = cout; a.ks = ks;
-    hipLaunchKernelGGL(k_conv_dgrad, dim3((a.P + kTile - 1) / kTile, (cin + kTile - 1) / kTile), dim3(256), 0, stream, a);
-    return launched("conv input gradient");
-}
-
-int inim_conv_backward_weight_workspace(int32_t imgs, int32_t h, int32_t w, int32_t cin, int32_t cout, int32_t ks,
-                                        size_t* bytes) {
+int inim_conv_workspace(int32_t imgs, int32_t h, int32_t w, int32_t cin, int32_t cout, int32_t ks, size_t* bytes) {
     int s = check_conv(imgs, h, w, cin, cout, ks);
     if (s != INIM_OK) return s;
     if (!bytes) return nfail(INIM_EINVAL, "bytes NULL");
     const int64_t P = (int64_t)imgs * h * w;
     const size_t wlen = (size_t)cout * ks * ks * cin;
     const size_t bparts = (size_t)((P + kBiasPixels - 1) / kBiasPixels);
-    *bytes = ((size_t)wgrad_slices(P, cout, cin, ks) * wlen + bparts * cout) * sizeof(float);
+    size_t need = (size_t)wgrad_slices(P, cout, cin, ks) * wlen + bparts * cout;
+    const int fs = fwd_slices(P, cin, cout, ks), ds = dgrad_slices(P, cin, cout, ks);
+    if (fs > 1 && (size_t)fs * P * cout > need) need = (size_t)fs * P * cout;
+    if (ds > 1 && (size_t)ds * P * cin > need) need = (size_t)ds * P * cin;
+    *bytes = need * sizeof(float);
     return INIM_OK;
+}
+
+int inim_conv_forward(const inim_bf16* x, int32_t imgs, int32_t h, int32_t w, int32_t cin, const inim_bf16* weight,
+                      const float* bias, int32_t cout, int32_t ks, int32_t relu, inim_bf16* y16, float* y32, void* work,
+                      size_t work_bytes, hipStream_t stream) {
+    int s = check_conv(imgs, h, w, cin, cout, ks);
+    if (s != INIM_OK) return s;
+    if (!x || !weight || (!y16 && !y32)) return nfail(INIM_EINVAL, "x, weight or both outputs NULL");
+    ConvArgs a{};
+    a.x = x; a.w = weight; a.bias = bias; a.y16 = y16; a.y32 = y32;
+    a.H = h; a.W = w; a.P = imgs * h * w; a.Cin = cin; a.Cout = cout; a.ks = ks; a.relu = relu ? 1 : 0;
+    const int K = ks * ks * cin;
+    int slices = fwd_slices(a.P, cin, cout, ks);
+    if (!work || work_bytes < (size_t)slices * a.P * cout * sizeof(float)) slices = 1;  // no room: one slice
+    const dim3 grd((a.P + kTile - 1) / kTile, (cout + kTile - 1) / kTile, slices);
+    hipLaunchKernelGGL(k_conv_fwd, grd, dim3(256), 0, stream, a, slices > 1 ? slice_len(K, slices) : K,
+                       static_cast<float*>(work));
+    if (slices > 1)
+        hipLaunchKernelGGL(k_conv_finish, dim3(grid_1d((int64_t)a.P * cout)), dim3(256), 0, stream, a, slices,
+                           static_cast<const float*>(work));
+    return launched("conv forward");
+}
+
+int inim_conv_backward_data(const inim_bf16* dy, int32_t imgs, int32_t h, int32_t w, int32_t cin,
+                            const inim_bf16* weight_t, int32_t cout, int32_t ks, float* dx, void* work,
+                            size_t work_bytes, hipStream_t stream) {
+    int s = check_conv(imgs, h, w, cin, cout, ks);
+    if (s != INIM_OK) return s;
+    if (!dy || !weight_t || !dx) return nfail(INIM_EINVAL, "dy, weight_t or dx NULL");
+    ConvArgs a{};
+    a.dy = dy; a.wT = weight_t; a.dx = dx;
+    a.H = h; a.W = w; a.P = imgs * h * w; a.Cin = cin; a.Cout = cout; a.ks = ks;
+    const int K = ks * ks * cout;
+    int slices = dgrad_slices(a.P, cin, cout, ks);
+    if (!work || work_bytes < (size_t)slices * a.P * cin * sizeof(float)) slices = 1;
+    const dim3 grd((a.P + kTile - 1) / kTile, (cin + kTile - 1) / kTile, slices);
+    hipLaunchKernelGGL(k_conv_dgrad, grd, dim3(256), 0, stream, a, slices > 1 ? slice_len(K, slices) : K,
+                       static_cast<float*>(work));
+    if (slices > 1)
+        hipLaunchKernelGGL(k_sum_parts, dim3(grid_1d((int64_t)a.P * cin)), dim3(256), 0, stream,
+                           static_cast<const float*>(work), slices, (size_t)a.P * cin, dx);
+    return launched("conv input gradient");
 }
 
 int inim_conv_backward_weight(const inim_bf16* dy, const inim_bf16* x, int32_t imgs, int32_t h, int32_t w, int32_t cin,
                               int32_t cout, int32_t ks, float* dweight, float* dbias, void* work, size_t work_bytes,
                               hipStream_t stream) {
     size_t need;
-    int s = inim_conv_backward_weight_workspace(imgs, h, w, cin, cout, ks, &need);
+    int s = inim_conv_workspace(imgs, h, w, cin, cout, ks, &need);
     if (s != INIM_OK) return s;
     if (!dy || !x || !dweight) return nfail(INIM_EINVAL, "dy, x or dweight NULL");
     if (!work || work_bytes < need) return nfail(INIM_EWORKSPACE, "work has %zu bytes, needs %zu", work_bytes, need);
@@ -630,8 +748,7 @@ int inim_conv_backward_weight(const inim_bf16* dy, const inim_bf16* x, int32_t i
     a.dy = dy; a.x = x;
     a.H = h; a.W = w; a.P = imgs * h * w; a.Cin = cin; a.Cout = cout; a.ks = ks;
     const int slices = wgrad_slices(a.P, cout, cin, ks);
-    const int64_t steps = (a.P + kStepK - 1) / kStepK;
-    const int kslice = (int)((steps + slices - 1) / slices) * kStepK;
+    const int kslice = slice_len(a.P, slices);
     const size_t wlen = (size_t)cout * ks * ks * cin;
     a.dw = static_cast<float*>(work);
     hipLaunchKernelGGL(k_conv_wgrad, dim3((cout + kTile - 1) / kTile, (unsigned)((ks * ks * cin + kTile - 1) / kTile), slices),
@@ -742,9 +859,9 @@ int inim_nn_displacement(const float* probe, int32_t res, float* out, hipStream_
     return launched("displacement");
 }
 
-int inim_nn_field(const float* y, int32_t c, int32_t res, float* field, hipStream_t stream) {
-    if (!y || !field || res < 2 || c < 2) return nfail(INIM_EINVAL, "bad field arguments");
-    hipLaunchKernelGGL(k_field_from_output, dim3(grid_1d((int64_t)res * res)), dim3(256), 0, stream, y, c, res,
+int inim_nn_field(const float* y, int32_t c, int32_t res, int32_t radius, float* field, hipStream_t stream) {
+    if (!y || !field || res < 2 || c < 2 || radius < 0 || radius > 16) return nfail(INIM_EINVAL, "bad field arguments");
+    hipLaunchKernelGGL(k_field_from_output, dim3(grid_1d((int64_t)res * res)), dim3(256), 0, stream, y, c, res, radius,
                        reinterpret_cast<float2*>(field));
     return launched("field");
 }

@@ -13,7 +13,7 @@ import torch
 from . import capi
 
 NN_EXPORTS = (
-    "inim_nn_last_error", "inim_conv_forward", "inim_conv_backward_data", "inim_conv_backward_weight_workspace",
+    "inim_nn_last_error", "inim_conv_forward", "inim_conv_backward_data", "inim_conv_workspace",
     "inim_conv_backward_weight", "inim_weight_transpose", "inim_f32_to_bf16", "inim_pool2", "inim_pool2_backward",
     "inim_upsample2_into", "inim_copy_channels_into", "inim_upsample2_backward", "inim_take_channels",
     "inim_relu_backward", "inim_mse", "inim_adam", "inim_nn_pack_density", "inim_nn_displacement", "inim_nn_field",
@@ -32,9 +32,9 @@ def lib() -> ctypes.CDLL:
     L.inim_nn_last_error.argtypes = []
     L.inim_nn_last_error.restype = ctypes.c_char_p
     sig = {
-        "inim_conv_forward": [vp, i32, i32, i32, i32, vp, vp, i32, i32, i32, vp, vp, vp],
-        "inim_conv_backward_data": [vp, i32, i32, i32, i32, vp, i32, i32, vp, vp],
-        "inim_conv_backward_weight_workspace": [i32, i32, i32, i32, i32, i32, ctypes.POINTER(sz)],
+        "inim_conv_forward": [vp, i32, i32, i32, i32, vp, vp, i32, i32, i32, vp, vp, vp, sz, vp],
+        "inim_conv_backward_data": [vp, i32, i32, i32, i32, vp, i32, i32, vp, vp, sz, vp],
+        "inim_conv_workspace": [i32, i32, i32, i32, i32, i32, ctypes.POINTER(sz)],
         "inim_conv_backward_weight": [vp, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, sz, vp],
         "inim_weight_transpose": [vp, i32, i32, i32, vp, vp],
         "inim_f32_to_bf16": [vp, i64, vp, vp],
@@ -49,7 +49,7 @@ def lib() -> ctypes.CDLL:
         "inim_adam": [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp, vp],
         "inim_nn_pack_density": [vp, i32, f32, i32, vp, vp],
         "inim_nn_displacement": [vp, i32, vp, vp],
-        "inim_nn_field": [vp, i32, i32, vp, vp],
+        "inim_nn_field": [vp, i32, i32, i32, vp, vp],
         "inim_nn_count_folds": [vp, i32, vp, vp],
         "inim_nn_bin_moments": [vp, i32, i32, vp, vp],
     }
@@ -85,25 +85,40 @@ def _f(t, name):
         raise TypeError(f"{name} must be float32")
 
 
-def conv_forward(x, w, bias=None, relu=False, y16=None, y32=None):
+def conv_workspace(imgs, h, w, cin, cout, ks) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().inim_conv_workspace(imgs, h, w, cin, cout, ks, ctypes.byref(n)))
+    return n.value
+
+
+def _work(work, need, dev):
+    if work is None or work.numel() < need:
+        work = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    return work
+
+
+def conv_forward(x, w, bias=None, relu=False, y16=None, y32=None, work=None):
     """x: [imgs, h, w, cin] bf16; w: [cout, ks*ks, cin] bf16 (ks from its shape)."""
     _bf(x, "x"), _bf(w, "w"), _f(bias, "bias"), _bf(y16, "y16"), _f(y32, "y32")
     imgs, h, wd, cin = x.shape
     cout, taps, cin2 = w.shape
     ks = int(round(taps ** 0.5))
     assert cin2 == cin and ks * ks == taps and x.is_contiguous() and w.is_contiguous()
+    work = _work(work, conv_workspace(imgs, h, wd, cin, cout, ks), x.device)
     _check(lib().inim_conv_forward(_p(x), imgs, h, wd, cin, _p(w), _p(bias), cout, ks, 1 if relu else 0, _p(y16),
-                                   _p(y32), _s(x)))
+                                   _p(y32), _p(work), work.numel(), _s(x)))
     return y16, y32
 
 
-def conv_backward_data(dy, wT, dx):
+def conv_backward_data(dy, wT, dx, work=None):
     """dy: [imgs, h, w, cout] bf16; wT: [cin, ks*ks, cout] bf16; dx: [imgs, h, w, cin] f32."""
     _bf(dy, "dy"), _bf(wT, "wT"), _f(dx, "dx")
     imgs, h, wd, cout = dy.shape
     cin, taps, cout2 = wT.shape
+    ks = int(round(taps ** 0.5))
     assert cout2 == cout and dx.shape == (imgs, h, wd, cin)
-    _check(lib().inim_conv_backward_data(_p(dy), imgs, h, wd, cin, _p(wT), cout, int(round(taps ** 0.5)), _p(dx),
+    work = _work(work, conv_workspace(imgs, h, wd, cin, cout, ks), dy.device)
+    _check(lib().inim_conv_backward_data(_p(dy), imgs, h, wd, cin, _p(wT), cout, ks, _p(dx), _p(work), work.numel(),
                                          _s(dy)))
     return dx
 
@@ -112,19 +127,10 @@ def conv_backward_weight(dy, x, ks, dw, db=None, work=None):
     _bf(dy, "dy"), _bf(x, "x"), _f(dw, "dw"), _f(db, "db")
     imgs, h, wd, cout = dy.shape
     cin = x.shape[3]
-    n = ctypes.c_size_t()
-    _check(lib().inim_conv_backward_weight_workspace(imgs, h, wd, cin, cout, ks, ctypes.byref(n)))
-    if work is None or work.numel() < n.value:
-        work = torch.empty(n.value, dtype=torch.uint8, device=dy.device)
+    work = _work(work, conv_workspace(imgs, h, wd, cin, cout, ks), dy.device)
     _check(lib().inim_conv_backward_weight(_p(dy), _p(x), imgs, h, wd, cin, cout, ks, _p(dw), _p(db), _p(work),
                                            work.numel(), _s(dy)))
     return dw, db
-
-
-def weight_workspace(imgs, h, w, cin, cout, ks) -> int:
-    n = ctypes.c_size_t()
-    _check(lib().inim_conv_backward_weight_workspace(imgs, h, w, cin, cout, ks, ctypes.byref(n)))
-    return n.value
 
 
 def weight_transpose(w, wT):
@@ -201,8 +207,8 @@ def displacement(probe, res, out):
     return out
 
 
-def field(y, res, out):
-    _check(lib().inim_nn_field(_p(y), y.shape[-1], res, _p(out), _s(out)))
+def field(y, res, out, radius=0):
+    _check(lib().inim_nn_field(_p(y), y.shape[-1], res, radius, _p(out), _s(out)))
     return out
 
 

@@ -5,7 +5,7 @@ convolutions with ReLU per level, 2x2 average pooling, nearest upsampling,
 concatenated skips, a 1x1 output convolution) maps the smoothed density of a
 256 x 256 raster to the displacement that `iters` iterations of the method
 give every texel centre (the composite map of Sec. 4.3 minus the identity,
-in texels).  The samples are then moved by one bilinear advection of that
+in 1/64 of the unit square).  The samples are then moved by one bilinear advection of that
 field.  It is trained on fields that the method itself computes, and the
 method remains the judge and the fallback: a prediction whose deformed
 lattice folds, or that does not make the samples more uniform, is replaced by
@@ -89,15 +89,22 @@ class UNet:
         return out
 
     # ------------------------------------------------------------------ forward
+    def _work_for(self, c: Conv, n, h, w):
+        need = nn.conv_workspace(n, h, w, c.cin, c.cout, c.ks)
+        if self._work is None or self._work.numel() < need:
+            self._work = torch.empty(need, dtype=torch.uint8, device=self.dev)
+        return self._work
+
     def _conv(self, name, x, relu=True, out32=False):
         c = self.convs[name]
         n, h, w, _ = x.shape
+        work = self._work_for(c, n, h, w)
         if out32:
             y = torch.empty((n, h, w, c.cout), dtype=F32, device=self.dev)
-            nn.conv_forward(x, c.w16, c.b, relu, y32=y)
+            nn.conv_forward(x, c.w16, c.b, relu, y32=y, work=work)
         else:
             y = torch.empty((n, h, w, c.cout), dtype=BF16, device=self.dev)
-            nn.conv_forward(x, c.w16, c.b, relu, y16=y)
+            nn.conv_forward(x, c.w16, c.b, relu, y16=y, work=work)
         return y
 
     def forward(self, x16: torch.Tensor) -> torch.Tensor:
@@ -133,15 +140,12 @@ class UNet:
     # ------------------------------------------------------------------ backward
     def _wgrad(self, c: Conv, gz16, x16):
         n, h, w, _ = x16.shape
-        need = nn.weight_workspace(n, h, w, c.cin, c.cout, c.ks)
-        if self._work is None or self._work.numel() < need:
-            self._work = torch.empty(need, dtype=torch.uint8, device=self.dev)
-        nn.conv_backward_weight(gz16, x16, c.ks, c.gw, c.gb, self._work)
+        nn.conv_backward_weight(gz16, x16, c.ks, c.gw, c.gb, self._work_for(c, n, h, w))
 
     def _dgrad(self, c: Conv, gz16):
         n, h, w, _ = gz16.shape
         dx = torch.empty((n, h, w, c.cin), dtype=F32, device=self.dev)
-        return nn.conv_backward_data(gz16, c.wT, dx)
+        return nn.conv_backward_data(gz16, c.wT, dx, self._work_for(c, n, h, w))
 
     def _relu_back(self, g32, act16):
         g16 = torch.empty(g32.shape, dtype=BF16, device=self.dev)
@@ -250,6 +254,14 @@ def bin_std(xy: torch.Tensor, res: int, bin_px: int = 4) -> float:
     return math.sqrt(max(s2 / k - (s1 / k) ** 2, 0.0))
 
 
+# Smoothing radius of the predicted displacement: the composite map is
+# smooth on the scale of the density's Gaussian, while the network's error is
+# not, and smoothing removes the part of it that folds the lattice: 2 texels
+# at 64 x 64, res / 16 above (16 at 256 x 256, the largest radius).
+def field_radius(res: int) -> int:
+    return 2 if res <= 64 else min(16, res // 16)
+
+
 def predict_field(net: UNet, xy: torch.Tensor, res: int, radius: int = 8) -> torch.Tensor:
     n = xy.shape[0]
     dens = torch.empty((res, res), dtype=F32, device=xy.device)
@@ -259,7 +271,24 @@ def predict_field(net: UNet, xy: torch.Tensor, res: int, radius: int = 8) -> tor
     nn.pack_density(dens, res * res / n, x16)
     y = net.forward(x16)
     field = torch.empty((res, res, 2), dtype=F32, device=xy.device)
-    return nn.field(y[0], res, field)
+    return nn.field(y[0], res, field, field_radius(res))
+
+
+def regularize_many(net: UNet, xys, res: int) -> None:
+    """The surrogate's move of several point sets at once (one batched
+    forward pass), in place and without the gate."""
+    k = len(xys)
+    x16 = torch.empty((k, res, res, CIN), dtype=BF16, device=net.dev)
+    dens = torch.empty((res, res), dtype=F32, device=net.dev)
+    counts = torch.empty((res, res), dtype=torch.uint32, device=net.dev)
+    for q, xy in enumerate(xys):
+        capi.rasterize(xy, res, counts=counts, density=dens)
+        nn.pack_density(dens, res * res / xy.shape[0], x16[q])
+    y = net.forward(x16)
+    field = torch.empty((res, res, 2), dtype=F32, device=net.dev)
+    for q, xy in enumerate(xys):
+        nn.field(y[q], res, field, field_radius(res))
+        capi.advect(field, xy)
 
 
 def regularize(net: UNet, xy: torch.Tensor, res: int, iters: int, min_gain: float = 0.2):
@@ -278,3 +307,40 @@ def regularize(net: UNet, xy: torch.Tensor, res: int, iters: int, min_gain: floa
         return "surrogate"
     capi.regularize(xy, res, iters)
     return "fallback"
+
+
+def evaluate(net: UNet, seeds, res: int, iters: int, dev, n_hi: int = 500_000, min_gain: float = 0.2) -> dict:
+    """Held-out comparison on fresh point sets: bin standard deviation (4 x 4
+    texel bins) before, after the plain method, after the surrogate's field;
+    folds of the surrogate's deformed lattice; how often the gate falls back;
+    the displacement error against the method's own field."""
+    rows = []
+    for s in seeds:
+        xy_np = datagen.surrogate_mixture(s, n_hi=n_hi)
+        xy = torch.from_numpy(xy_np).to(dev)
+        before = bin_std(xy, res)
+        plain = xy.clone()
+        capi.regularize(plain, res, iters)
+        field = predict_field(net, xy, res)
+        folds = torch.zeros(1, dtype=torch.uint32, device=dev)
+        nn.count_folds(field, res, folds)
+        sur = xy.clone()
+        capi.advect(field, sur)
+        x16, tgt = example(xy_np, res, iters, dev)
+        y = net.forward(x16[None].contiguous())
+        loss = torch.zeros(1, dtype=F32, device=dev)
+        nn.mse(y, tgt[None].contiguous(), loss)
+        zero = torch.zeros_like(y)
+        base = torch.zeros(1, dtype=F32, device=dev)
+        nn.mse(zero, tgt[None].contiguous(), base)
+        gated = xy.clone()
+        which = regularize(net, gated, res, iters, min_gain)
+        rows.append({"n": int(xy.shape[0]), "before": before, "plain": bin_std(plain, res),
+                     "surrogate": bin_std(sur, res), "folds": int(folds.item()), "gate": which,
+                     "mse": float(loss.item()), "mse_zero": float(base.item())})
+    return {"rows": rows,
+            "plain_gain": float(np.mean([1 - r["plain"] / r["before"] for r in rows])),
+            "surrogate_gain": float(np.mean([1 - r["surrogate"] / r["before"] for r in rows])),
+            "explained": float(1 - sum(r["mse"] for r in rows) / sum(r["mse_zero"] for r in rows)),
+            "folds": int(sum(r["folds"] for r in rows)),
+            "fallbacks": int(sum(r["gate"] == "fallback" for r in rows))}
