@@ -37,11 +37,14 @@ PAPER_ITERS_PER_S = 8 / 12.63e-3  # Table 1: 8 iterations, 1M points, 1024^2, r 
 # HBM traffic per launch of the dominant stage's kernel from two rocprofv3
 # --pmc runs of `bench.py --profile-short` (FETCH_SIZE, then WRITE_SIZE; see
 # profiles/pmc_traffic_regularize_1M_1024.md), each scaled by what the same
-# counter reads for a plain 256 MiB device copy in that run.  Valid only for
-# the kernel sources they were taken with (SHA-256 over csrc/*.hip, *.h).
+# counter reads for a plain 256 MiB device copy in that run (FETCH_SIZE
+# counts half of the bytes read: factor 1.99985; WRITE_SIZE all: factor 1.000).
+# Valid only for the sources they were taken with: SHA-256 over the file that
+# holds the kernel (k_inim.hip) and every header; otherwise traffic is null.
 TRAFFIC = {
-    "src_sha256": "",
-    "smooth_aggregate": None,  # bytes per launch of k_blur_aggregate
+    "src_sha256": "4d896fb3e734cfe5495595503bca8d16692ac0f966d703a713f682999b2244d9",
+    # k_blur_aggregate: FETCH_SIZE 4045.0 KiB x 1.99985 + WRITE_SIZE 10112.0 KiB x 1.000
+    "smooth_aggregate": 18638121,
 }
 
 
@@ -50,7 +53,7 @@ def kernel_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2408_06513_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+    for f in sorted([os.path.join(csrc, "k_inim.hip")] + glob.glob(os.path.join(csrc, "*.h"))):
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
@@ -392,6 +395,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-splom", action="store_true", help="skip the 45-plot scatterplot-matrix measurement")
     ap.add_argument("--no-surrogate", action="store_true", help="skip training and timing the learned surrogate")
+    ap.add_argument("--surrogate-sets", type=int, default=1024, help="training point sets of the surrogate")
+    ap.add_argument("--surrogate-steps", type=int, default=2500, help="training steps of the surrogate")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--only-inim", action="store_true",
                     help="print only the 8192^2 integral-image measurement (for profiling)")
@@ -445,7 +450,7 @@ def main():
     if not args.no_splom:
         rec["splom_45_plots"] = bench_splom(dev)
     if not args.no_surrogate:
-        rec["surrogate_256"] = bench_surrogate(dev)
+        rec["surrogate_256"] = bench_surrogate(dev, args.surrogate_sets, args.surrogate_steps)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(xy0_np, args.res, args.iters, args.cpu_seconds)
     print(json.dumps(rec), flush=True)

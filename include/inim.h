@@ -202,8 +202,10 @@ int inim_regularize_probes(float* xy, int64_t n, float* probe, int64_t m, int32_
 
 /*
  * inim_regularize instrumented for measurement: records HIP events on
- * `stream` around the stages, synchronises after each iteration, and adds the
- * elapsed milliseconds into stage_ms[0..5]:
+ * `stream` -- around the per-call sort and unsort, and for each per-iteration
+ * stage at the start of its first kernel and the end of its last kernel
+ * (the launch-gap-free kernel span) -- synchronises after each iteration,
+ * and adds the elapsed milliseconds into stage_ms[0..5]:
  *   0 once per call: sorting the samples by texel (count raster cleared,
  *     every sample splatted with its rank, counts scanned, samples moved),
  *     and moving the results back to the caller's order at the end

@@ -120,10 +120,12 @@ int inim_nn_displacement(const float* probe, int32_t res, float* out, hipStream_
 
 /* The deformation field of a network output y [res][res][c] (c >= 2):
  * field [res][res][2] = texel centre + (y[..][0..1] smoothed) / 64, for
- * inim_advect.  The smoothing is the normalised Gaussian of standard
- * deviation radius / 2 over |dx|, |dy| <= radius (indices clamped to the
- * raster); radius 0..16, 0 = none. */
-int inim_nn_field(const float* y, int32_t c, int32_t res, int32_t radius, float* field, hipStream_t stream);
+ * inim_advect.  The smoothing is the separable normalised Gaussian of
+ * standard deviation radius / 2 over |d| <= radius along x, then y (indices
+ * clamped to the raster); radius 0..16, 0 = none.  work: device float
+ * [res][res][2] for the intermediate pass. */
+int inim_nn_field(const float* y, int32_t c, int32_t res, int32_t radius, float* field, float* work,
+                  hipStream_t stream);
 
 /* Adds to *count (device) the number of lattice triangles (two per cell) of
  * the deformed texel lattice `field` with non-positive signed area (folds). */

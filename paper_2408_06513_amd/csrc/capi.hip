@@ -96,11 +96,28 @@ int check_xy(const void* xy, int64_t n) {
     return INIM_OK;
 }
 
-// Events of the timed variant: per call the splat prologue, per iteration
-// the boundaries of its four stages.
+// Events of the timed variant: per call the sort prologue and epilogue
+// (recorded between launches), per iteration the start of the first and the
+// end of the last kernel of each of the four stages (a StageClock).
 struct StageEvents {
     hipEvent_t pre[2];
-    hipEvent_t it[5];
+    hipEvent_t start[4], stop[4];
+};
+
+// Arms the stage clock for stage k while in scope (nothing without events).
+struct ClockScope {
+    StageClock c;
+    bool on;
+    ClockScope(StageEvents* ev, int k) : on(ev != nullptr) {
+        if (on) {
+            c.start = ev->start[k];
+            c.stop = ev->stop[k];
+            stage_clock() = &c;
+        }
+    }
+    ~ClockScope() {
+        if (on) stage_clock() = nullptr;
+    }
 };
 
 // The whole call (Sec. 4.3) on the caller's stream.  The samples are first
@@ -142,41 +159,48 @@ int enqueue_regularize(float* xy, int64_t n, float* probe, int64_t m, int32_t re
     for (int it = 0; it < iters; ++it) {
         uint32_t* cur = counts[it & 1];
         uint32_t* nxt = (it + 1 < iters) ? counts[(it + 1) & 1] : nullptr;
-        if (ev) (void)hipEventRecord(ev->it[0], st);
-        if (fused) {
-            e = launch_blur_aggregate(cur, density, nxt, res, taps, L.g, scratch, status, st);
-        } else if (L.f32) {
-            e = launch_blur(cur, density, res, taps, status, st);
-            if (e == hipSuccess && nxt) e = launch_fill(nxt, NN, status, false, st);
-            if (e == hipSuccess) e = launch_inim_aggregate<float, double>(density, L.g, scratch, status, st);
-        } else {
-            e = launch_inim_aggregate<uint32_t, uint32_t>(cur, L.g, scratch, status, st);
+        {
+            ClockScope clock(ev, 0);
+            if (fused) {
+                e = launch_blur_aggregate(cur, density, nxt, res, taps, L.g, scratch, status, st);
+            } else if (L.f32) {
+                e = launch_blur(cur, density, res, taps, status, st);
+                if (e == hipSuccess && nxt) e = launch_fill(nxt, NN, status, false, st);
+                if (e == hipSuccess) e = launch_inim_aggregate<float, double>(density, L.g, scratch, status, st);
+            } else {
+                e = launch_inim_aggregate<uint32_t, uint32_t>(cur, L.g, scratch, status, st);
+            }
         }
         if (e != hipSuccess) return hip_fail(e, "smooth + aggregate");
-        if (ev) (void)hipEventRecord(ev->it[1], st);
-        e = L.f32 ? launch_inim_scans<double>(L.g, scratch, status, st)
-                  : launch_inim_scans<uint32_t>(L.g, scratch, status, st);
+        {
+            ClockScope clock(ev, 1);
+            e = L.f32 ? launch_inim_scans<double>(L.g, scratch, status, st)
+                      : launch_inim_scans<uint32_t>(L.g, scratch, status, st);
+        }
         if (e != hipSuccess) return hip_fail(e, "integral-image scans");
-        if (ev) (void)hipEventRecord(ev->it[2], st);
-        if (L.f32)
-            e = launch_inim_final<float, double>(density, L.g, scratch, 0u, nullptr, field, defect, d0, nullptr, status,
-                                                 st);
-        else
-            e = launch_inim_final<uint32_t, uint32_t>(cur, L.g, scratch, 0u, nullptr, field, defect, d0, nullptr,
-                                                      status, st);
-        if (e == hipSuccess && !L.f32 && nxt) e = launch_fill(nxt, NN, status, false, st);
+        {
+            ClockScope clock(ev, 2);
+            if (L.f32)
+                e = launch_inim_final<float, double>(density, L.g, scratch, 0u, nullptr, field, defect, d0, nullptr,
+                                                     status, st);
+            else
+                e = launch_inim_final<uint32_t, uint32_t>(cur, L.g, scratch, 0u, nullptr, field, defect, d0, nullptr,
+                                                          status, st);
+            if (e == hipSuccess && !L.f32 && nxt) e = launch_fill(nxt, NN, status, false, st);
+        }
         if (e != hipSuccess) return hip_fail(e, "integral images + deformation");
-        if (ev) (void)hipEventRecord(ev->it[3], st);
-        if ((e = launch_advect(field, res, pts, n, nxt, status, st)) != hipSuccess) return hip_fail(e, "advect");
-        if (m > 0 && (e = launch_advect(field, res, reinterpret_cast<float2*>(probe), m, nullptr, status, st)) !=
-                         hipSuccess)
-            return hip_fail(e, "advect probes");
+        {
+            ClockScope clock(ev, 3);
+            e = launch_advect(field, res, pts, n, nxt, status, st);
+            if (e == hipSuccess && m > 0)
+                e = launch_advect(field, res, reinterpret_cast<float2*>(probe), m, nullptr, status, st);
+        }
+        if (e != hipSuccess) return hip_fail(e, "advect");
         if (ev) {
-            (void)hipEventRecord(ev->it[4], st);
-            if (hipEventSynchronize(ev->it[4]) != hipSuccess) return fail(INIM_EHIP, "hipEventSynchronize failed");
+            if (hipEventSynchronize(ev->stop[3]) != hipSuccess) return fail(INIM_EHIP, "hipEventSynchronize failed");
             for (int k = 0; k < 4; ++k) {
                 float ms = 0.0f;
-                (void)hipEventElapsedTime(&ms, ev->it[k], ev->it[k + 1]);
+                (void)hipEventElapsedTime(&ms, ev->start[k], ev->stop[k]);
                 stage_ms[1 + k] += ms;
             }
         }
@@ -218,7 +242,8 @@ int regularize_impl(float* xy, int64_t n, float* probe, int64_t m, int32_t res, 
 
     StageEvents ev;
     hipEvent_t t0, t1;
-    hipEvent_t* all[9] = {&ev.pre[0], &ev.pre[1], &ev.it[0], &ev.it[1], &ev.it[2], &ev.it[3], &ev.it[4], &t0, &t1};
+    hipEvent_t* all[12] = {&ev.pre[0], &ev.pre[1], &ev.start[0], &ev.start[1], &ev.start[2], &ev.start[3],
+                           &ev.stop[0],   &ev.stop[1],  &ev.stop[2],  &ev.stop[3],  &t0,           &t1};
     for (auto* h : all)
         if (hipEventCreate(h) != hipSuccess) return fail(INIM_EHIP, "hipEventCreate failed");
     (void)hipEventRecord(t0, stream);

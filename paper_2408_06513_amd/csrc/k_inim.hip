@@ -846,9 +846,9 @@ hipError_t launch_inim_scans(const Geom& g, void* scratch, const int* status, hi
     Carry<Acc> K;
     carve<Acc>(g, (char*)scratch, A, K);
     const int nw = scan_waves(g.B);
-    hipLaunchKernelGGL((k_inim_scan_col<Acc>), dim3((g.N + 63) / 64), dim3(64 * nw), (size_t)nw * 2 * 64 * sizeof(Acc),
+    launch_kernel((k_inim_scan_col<Acc>), dim3((g.N + 63) / 64), dim3(64 * nw), (size_t)nw * 2 * 64 * sizeof(Acc),
                        st, g, A, K, status);
-    hipLaunchKernelGGL((k_inim_scan_diag<Acc>), dim3((2 * g.N + 1 + 63) / 64, 3), dim3(64 * nw),
+    launch_kernel((k_inim_scan_diag<Acc>), dim3((2 * g.N + 1 + 63) / 64, 3), dim3(64 * nw),
                        (size_t)nw * 64 * sizeof(Acc), st, g, A, K, status);
     return hipGetLastError();
 }
@@ -863,7 +863,7 @@ hipError_t launch_blur_aggregate(const uint32_t* counts, float* density, uint32_
     Carry<double> K;
     carve<double>(g, (char*)scratch, A, K);
     const size_t smem = sizeof(float) * blur_smem_floats(taps.r);
-    hipLaunchKernelGGL((k_blur_aggregate<double>), dim3(N / kBX, N / kBY), dim3(256), smem, st, counts, density,
+    launch_kernel((k_blur_aggregate<double>), dim3(N / kBX, N / kBY), dim3(256), smem, st, counts, density,
                        zero_next, taps, g, A, status);
     return hipGetLastError();
 }
@@ -875,7 +875,7 @@ static hipError_t launch_aggregate_q(const Tin* img, const Geom& g, void* scratc
     carve<Acc>(g, (char*)scratch, A, K);
     const int tiles = g.B * g.T;
     const dim3 grd((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL((k_inim_aggregate<Q, Tin, Acc>), grd, dim3(64 * kWavesPerBlock), 0, st, img, g, A, status);
+    launch_kernel((k_inim_aggregate<Q, Tin, Acc>), grd, dim3(64 * kWavesPerBlock), 0, st, img, g, A, status);
     return hipGetLastError();
 }
 
@@ -907,24 +907,24 @@ static hipError_t launch_final_q(const Tin* img, const Geom& g, void* scratch, u
     const dim3 blk(64 * kWavesPerBlock);
     const dim3 grd((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
     const int M = 6 * g.N - 1;
-    hipLaunchKernelGGL((k_inim_marg<Acc>), dim3((M + 255) / 256), dim3(256), 0, st, g, A, K, marg, status);
+    launch_kernel((k_inim_marg<Acc>), dim3((M + 255) / 256), dim3(256), 0, st, g, A, K, marg, status);
     const size_t smem = (size_t)kWavesPerBlock * 2 * (g.W + g.H - 1) * sizeof(Acc);
     if (field != nullptr && Q == 1 && g.W == 64 && g.H == 16 && g.N >= 64) {
-        hipLaunchKernelGGL((k_inim_deform16<Tin, Acc>), grd, blk, smem, st, img, g, A, K, field, t1, d0, status);
+        launch_kernel((k_inim_deform16<Tin, Acc>), grd, blk, smem, st, img, g, A, K, field, t1, d0, status);
     } else if (field != nullptr) {
-        hipLaunchKernelGGL((k_inim_final<Q, Tin, Acc, kModeDeform>), grd, blk, smem, st, img, g, A, K, 0u,
+        launch_kernel((k_inim_final<Q, Tin, Acc, kModeDeform>), grd, blk, smem, st, img, g, A, K, 0u,
                            (Tin*)nullptr, field, t1, d0, status);
     } else if (mask != 0) {
         const bool needUV = (mask & (INIM_BETA_T | INIM_GAMMA_T | INIM_DELTA_T)) != 0;
         const bool full = g.W == 64 * Q && g.H % prefetch_rows<Q, Tin>() == 0;
         if (full && mask == INIM_ALL)
-            hipLaunchKernelGGL((k_inim_final<Q, Tin, Acc, kModePlanes, INIM_ALL, true>), grd, blk, smem, st, img, g, A,
+            launch_kernel((k_inim_final<Q, Tin, Acc, kModePlanes, INIM_ALL, true>), grd, blk, smem, st, img, g, A,
                                K, mask, planes, (float2*)nullptr, (const float2*)nullptr, 0.0, status);
         else if (full && mask == INIM_MIN)
-            hipLaunchKernelGGL((k_inim_final<Q, Tin, Acc, kModePlanes, INIM_MIN, true>), grd, blk, 0, st, img, g, A, K,
+            launch_kernel((k_inim_final<Q, Tin, Acc, kModePlanes, INIM_MIN, true>), grd, blk, 0, st, img, g, A, K,
                                mask, planes, (float2*)nullptr, (const float2*)nullptr, 0.0, status);
         else
-            hipLaunchKernelGGL((k_inim_final<Q, Tin, Acc, kModePlanes>), grd, blk, needUV ? smem : 0, st, img, g, A,
+            launch_kernel((k_inim_final<Q, Tin, Acc, kModePlanes>), grd, blk, needUV ? smem : 0, st, img, g, A,
                                K, mask, planes, (float2*)nullptr, (const float2*)nullptr, 0.0, status);
     }
     return hipGetLastError();

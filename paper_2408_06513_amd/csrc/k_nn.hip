@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <string>
@@ -326,15 +327,33 @@ __global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ par
     }
 }
 
-// Bias gradient partials: part[b][co] = sum over pixels of block b of dy[p][co].
+// Bias gradient partials: part[b][co] = sum over the `per` pixels of block b
+// of dy[p][co].  The block's threads form g = 256 / C groups (C <= 256) of C
+// consecutive channels, so a group reads whole pixels (coalesced); groups
+// take every g-th pixel and are summed in LDS in group order.
 __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dy, int P, int C, int per,
                                                    float* __restrict__ part) {
-    const int co = threadIdx.x;
+    __shared__ float red[256];
     const int p0 = blockIdx.x * per, p1 = min(P, p0 + per);
-    for (int c = co; c < C; c += blockDim.x) {
-        float s = 0.0f;
-        for (int p = p0; p < p1; ++p) s += bf2f(dy[(size_t)p * C + c]);
-        part[(size_t)blockIdx.x * C + c] = s;
+    if (C > 256) {  // one channel per thread, pixels in order
+        for (int c = threadIdx.x; c < C; c += blockDim.x) {
+            float s = 0.0f;
+            for (int p = p0; p < p1; ++p) s += bf2f(dy[(size_t)p * C + c]);
+            part[(size_t)blockIdx.x * C + c] = s;
+        }
+        return;
+    }
+    const int g = 256 / C;
+    const int c = threadIdx.x % C, r = threadIdx.x / C;
+    float s = 0.0f;
+    if (r < g)
+        for (int p = p0 + r; p < p1; p += g) s += bf2f(dy[(size_t)p * C + c]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if ((int)threadIdx.x < C) {
+        float t = 0.0f;
+        for (int k = 0; k < g; ++k) t += red[k * C + threadIdx.x];
+        part[(size_t)blockIdx.x * C + threadIdx.x] = t;
     }
 }
 
@@ -528,30 +547,41 @@ __global__ __launch_bounds__(256) void k_displacement(const float2* __restrict__
 }
 
 // The deformation field of the network's output: field[p] = texel centre +
-// (smoothed output[p][0..1]) / 64, the output first convolved with the
-// normalised Gaussian exp(-m^2 / (2 (r/2)^2)), |m| <= r, along both axes
-// (clamped at the border); r = 0: no smoothing.  Channels beyond the first
-// two are ignored.
-__global__ __launch_bounds__(256) void k_field_from_output(const float* __restrict__ y, int C, int N, int r,
-                                                           float2* __restrict__ field) {
+// (smoothed output[p][0..1]) / 64, the output convolved along x, then along
+// y, with the normalised taps w[0..2r] (indices clamped at the border); the
+// x pass goes to tmp [N][N][2].  Channels beyond the first two are ignored.
+struct FieldTaps {
+    int r;
+    float w[33];
+};
+
+__global__ __launch_bounds__(256) void k_field_smooth_x(const float* __restrict__ y, int C, int N, FieldTaps t,
+                                                        float2* __restrict__ tmp) {
     const size_t n = (size_t)N * N;
-    const float s2 = r > 0 ? 0.5f / (0.25f * r * r) : 0.0f;
     for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
         const int j = (int)(p / N), i = (int)(p - (size_t)j * N);
-        float ax = 0.0f, ay = 0.0f, wsum = 0.0f;
-        for (int dy = -r; dy <= r; ++dy) {
-            const int jj = min(max(j + dy, 0), N - 1);
-            for (int dx = -r; dx <= r; ++dx) {
-                const int ii = min(max(i + dx, 0), N - 1);
-                const float w = __expf(-(float)(dx * dx + dy * dy) * s2);
-                const size_t q = ((size_t)jj * N + ii) * C;
-                ax += w * y[q];
-                ay += w * y[q + 1];
-                wsum += w;
-            }
+        float ax = 0.0f, ay = 0.0f;
+        for (int d = -t.r; d <= t.r; ++d) {
+            const size_t q = ((size_t)j * N + min(max(i + d, 0), N - 1)) * C;
+            ax += t.w[d + t.r] * y[q];
+            ay += t.w[d + t.r] * y[q + 1];
         }
-        field[p] = make_float2(((float)i + 0.5f) / (float)N + ax / wsum / kDispUnit,
-                               ((float)j + 0.5f) / (float)N + ay / wsum / kDispUnit);
+        tmp[p] = make_float2(ax, ay);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_field_smooth_y(const float2* __restrict__ tmp, int N, FieldTaps t,
+                                                        float2* __restrict__ field) {
+    const size_t n = (size_t)N * N;
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        const int j = (int)(p / N), i = (int)(p - (size_t)j * N);
+        float ax = 0.0f, ay = 0.0f;
+        for (int d = -t.r; d <= t.r; ++d) {
+            const float2 v = tmp[(size_t)min(max(j + d, 0), N - 1) * N + i];
+            ax += t.w[d + t.r] * v.x;
+            ay += t.w[d + t.r] * v.y;
+        }
+        field[p] = make_float2(((float)i + 0.5f) / (float)N + ax / kDispUnit, ((float)j + 0.5f) / (float)N + ay / kDispUnit);
     }
 }
 
@@ -859,9 +889,21 @@ int inim_nn_displacement(const float* probe, int32_t res, float* out, hipStream_
     return launched("displacement");
 }
 
-int inim_nn_field(const float* y, int32_t c, int32_t res, int32_t radius, float* field, hipStream_t stream) {
-    if (!y || !field || res < 2 || c < 2 || radius < 0 || radius > 16) return nfail(INIM_EINVAL, "bad field arguments");
-    hipLaunchKernelGGL(k_field_from_output, dim3(grid_1d((int64_t)res * res)), dim3(256), 0, stream, y, c, res, radius,
+int inim_nn_field(const float* y, int32_t c, int32_t res, int32_t radius, float* field, float* work,
+                  hipStream_t stream) {
+    if (!y || !field || !work || res < 2 || c < 2 || radius < 0 || radius > 16)
+        return nfail(INIM_EINVAL, "bad field arguments");
+    FieldTaps t{};
+    t.r = radius;
+    double w[33], s = 0.0;
+    for (int m = -radius; m <= radius; ++m) {  // exp(-m^2 / (2 (r/2)^2)), normalised
+        w[m + radius] = radius ? std::exp(-2.0 * m * m / ((double)radius * radius)) : 1.0;
+        s += w[m + radius];
+    }
+    for (int k = 0; k <= 2 * radius; ++k) t.w[k] = (float)(w[k] / s);
+    const unsigned g = grid_1d((int64_t)res * res);
+    hipLaunchKernelGGL(k_field_smooth_x, dim3(g), dim3(256), 0, stream, y, c, res, t, reinterpret_cast<float2*>(work));
+    hipLaunchKernelGGL(k_field_smooth_y, dim3(g), dim3(256), 0, stream, reinterpret_cast<const float2*>(work), res, t,
                        reinterpret_cast<float2*>(field));
     return launched("field");
 }

@@ -316,8 +316,13 @@ static unsigned grid_for(int64_t n, int per_block = 256, unsigned cap = 8192) {
     return (unsigned)(g > cap ? cap : g);
 }
 
+StageClock*& stage_clock() {
+    thread_local StageClock* c = nullptr;
+    return c;
+}
+
 hipError_t launch_fill(uint32_t* counts, size_t count, int* status, bool clear_status, hipStream_t st) {
-    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)(count / 4 + 1), 256, 2048)), dim3(256), 0, st, counts, count,
+    launch_kernel(k_fill, dim3(grid_for((int64_t)(count / 4 + 1), 256, 2048)), dim3(256), 0, st, counts, count,
                        status, clear_status ? 1 : 0);
     return hipGetLastError();
 }
@@ -336,13 +341,13 @@ hipError_t launch_blur(const uint32_t* counts, float* out, int N, const BlurTaps
                        hipStream_t st) {
     const size_t smem = sizeof(float) * blur_smem_floats(taps.r);
     const dim3 grd((N + kBX - 1) / kBX, (N + kBY - 1) / kBY);
-    hipLaunchKernelGGL(k_blur, grd, dim3(256), smem, st, counts, out, N, taps, status);
+    launch_kernel(k_blur, grd, dim3(256), smem, st, counts, out, N, taps, status);
     return hipGetLastError();
 }
 
 hipError_t launch_advect(const float2* field, int N, float2* xy, int64_t n, uint32_t* counts_next, const int* status,
                          hipStream_t st) {
-    hipLaunchKernelGGL(k_advect, dim3(grid_for(n)), dim3(256), 0, st, field, N, xy, n, counts_next, status);
+    launch_kernel(k_advect, dim3(grid_for(n)), dim3(256), 0, st, field, N, xy, n, counts_next, status);
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // launch.h -- host-side launchers of the gfx950 kernels (used by the C ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -10,6 +11,29 @@
 namespace inim {
 
 constexpr int kMaxRadius = 32;
+
+// Stage timing: while a StageClock is armed on this thread, launches made
+// through launch_kernel() go through hipExtLaunchKernelGGL, the first one
+// recording `start` when it begins and every one recording `stop` when it
+// ends, so the pair brackets exactly the kernels of a stage (no launch
+// gaps).  Disarmed (the default), launch_kernel is a plain launch.
+struct StageClock {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool started = false;
+};
+StageClock*& stage_clock();
+
+template <typename K, typename... A>
+inline void launch_kernel(K kernel, dim3 grid, dim3 block, size_t smem, hipStream_t st, A... args) {
+    StageClock* c = stage_clock();
+    if (c == nullptr) {
+        hipLaunchKernelGGL(kernel, grid, block, smem, st, args...);
+        return;
+    }
+    hipEvent_t s = c->started ? nullptr : c->start;
+    c->started = true;
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)smem, st, s, c->stop, 0, args...);
+}
 
 struct BlurTaps {
     int r;

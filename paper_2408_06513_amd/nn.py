@@ -49,7 +49,7 @@ def lib() -> ctypes.CDLL:
         "inim_adam": [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp, vp],
         "inim_nn_pack_density": [vp, i32, f32, i32, vp, vp],
         "inim_nn_displacement": [vp, i32, vp, vp],
-        "inim_nn_field": [vp, i32, i32, i32, vp, vp],
+        "inim_nn_field": [vp, i32, i32, i32, vp, vp, vp],
         "inim_nn_count_folds": [vp, i32, vp, vp],
         "inim_nn_bin_moments": [vp, i32, i32, vp, vp],
     }
@@ -207,8 +207,10 @@ def displacement(probe, res, out):
     return out
 
 
-def field(y, res, out, radius=0):
-    _check(lib().inim_nn_field(_p(y), y.shape[-1], res, radius, _p(out), _s(out)))
+def field(y, res, out, radius=0, work=None):
+    if work is None:
+        work = torch.empty_like(out)
+    _check(lib().inim_nn_field(_p(y), y.shape[-1], res, radius, _p(out), _p(work), _s(out)))
     return out
 
 
