@@ -127,10 +127,13 @@ __device__ __forceinline__ void store_vec(const Chunks& c, GemmLds& s) {
 // 8 channels of one pixel (a 16-byte load, Cout and Cin multiples of 8, so a
 // chunk of (t, ci) stays in one tap), written transposed into the [row][k]
 // LDS layout.
+// With `ones`, column N of B is 1 at every pixel, so that column of the
+// product is the bias gradient sum_p dy[p][co].
 struct WgradSrc {
     const uint16_t* dy;  // [P][Cout]
     const uint16_t* x;   // [P][Cin]
     int Cout, Cin, N;    // N = taps * Cin
+    bool ones;
     ConvGeom g;
 };
 
@@ -148,6 +151,8 @@ __device__ __forceinline__ void load_wgrad(Chunks& c, const WgradSrc& w, int bm,
             const int t = n / w.Cin, ci = n - t * w.Cin;
             int q;
             if (w.g.shift(p, t, 1, q)) v = *reinterpret_cast<const u16x8*>(w.x + (size_t)q * w.Cin + ci);
+        } else if (w.ones && p < w.g.P && n == w.N) {
+            v[0] = 0x3F80u;  // 1.0 in bfloat16
         }
         c.b[h] = v;
     }
@@ -298,13 +303,15 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(ConvArgs a, int kslice, floa
 }
 
 // Weight gradient, FP32 [Cout][taps][Cin]; K (pixels) split over gridDim.z
-// slices of `kslice` pixels, each slice writing its own partial [slice][...].
-__global__ __launch_bounds__(256) void k_conv_wgrad(ConvArgs a, int kslice) {
+// slices of `kslice` pixels, each slice writing its own partial [slice][...];
+// with bias_part != null, also the bias-gradient partials [slice][Cout]
+// (the column of ones).
+__global__ __launch_bounds__(256) void k_conv_wgrad(ConvArgs a, int kslice, float* bias_part) {
     __shared__ GemmLds s[2];
     const int bm = blockIdx.x * kBM, bn = blockIdx.y * kBN;
     const ConvGeom g{a.H, a.W, a.P, a.ks, a.ks * a.ks, a.ks / 2};
     const int N = g.taps * a.Cin;
-    const WgradSrc src{a.dy, a.x, a.Cout, a.Cin, N, g};
+    const WgradSrc src{a.dy, a.x, a.Cout, a.Cin, N, bias_part != nullptr, g};
     int kbeg, kend;
     k_range(a.P, kslice, kbeg, kend);
     f32x16 acc[2][2] = {};
@@ -312,7 +319,9 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvArgs a, int kslice) {
               [&](const Chunks& c, GemmLds& l) { store_wgrad(c, l); });
     float* out = a.dw + (size_t)blockIdx.z * a.Cout * N;
     for_each_result(acc, bm, bn, [&](int m, int n, float v) {
-        if (m < a.Cout && n < N) out[(size_t)m * N + n] = v;
+        if (m >= a.Cout) return;
+        if (n < N) out[(size_t)m * N + n] = v;
+        else if (n == N && bias_part) bias_part[(size_t)blockIdx.z * a.Cout + m] = v;
     });
 }
 
@@ -324,36 +333,6 @@ __global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ par
         float s = 0.0f;
         for (int q = 0; q < parts; ++q) s += part[(size_t)q * len + i];
         out[i] = s;
-    }
-}
-
-// Bias gradient partials: part[b][co] = sum over the `per` pixels of block b
-// of dy[p][co].  The block's threads form g = 256 / C groups (C <= 256) of C
-// consecutive channels, so a group reads whole pixels (coalesced); groups
-// take every g-th pixel and are summed in LDS in group order.
-__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dy, int P, int C, int per,
-                                                   float* __restrict__ part) {
-    __shared__ float red[256];
-    const int p0 = blockIdx.x * per, p1 = min(P, p0 + per);
-    if (C > 256) {  // one channel per thread, pixels in order
-        for (int c = threadIdx.x; c < C; c += blockDim.x) {
-            float s = 0.0f;
-            for (int p = p0; p < p1; ++p) s += bf2f(dy[(size_t)p * C + c]);
-            part[(size_t)blockIdx.x * C + c] = s;
-        }
-        return;
-    }
-    const int g = 256 / C;
-    const int c = threadIdx.x % C, r = threadIdx.x / C;
-    float s = 0.0f;
-    if (r < g)
-        for (int p = p0 + r; p < p1; p += g) s += bf2f(dy[(size_t)p * C + c]);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if ((int)threadIdx.x < C) {
-        float t = 0.0f;
-        for (int k = 0; k < g; ++k) t += red[k * C + threadIdx.x];
-        part[(size_t)blockIdx.x * C + threadIdx.x] = t;
     }
 }
 
@@ -673,7 +652,7 @@ unsigned grid_1d(int64_t n) {
     return (unsigned)(g > 8192 ? 8192 : g);
 }
 
-constexpr int kTile = 128, kStepK = 32, kMsePartials = 256, kBiasPixels = 2048;
+constexpr int kTile = 128, kStepK = 32, kMsePartials = 256;
 
 int check_conv(int32_t imgs, int32_t h, int32_t w, int32_t cin, int32_t cout, int32_t ks) {
     if (imgs < 1 || h < 1 || w < 1) return nfail(INIM_EINVAL, "empty image batch %d x %d x %d", imgs, h, w);
@@ -699,7 +678,7 @@ int slice_len(int64_t klen, int slices) {
     return (int)((steps + slices - 1) / slices) * kStepK;
 }
 
-int wgrad_slices(int64_t P, int cout, int cin, int ks) { return split_slices(cout, (int64_t)ks * ks * cin, P); }
+int wgrad_slices(int64_t P, int cout, int cin, int ks) { return split_slices(cout, (int64_t)ks * ks * cin + 1, P); }
 int fwd_slices(int64_t P, int cin, int cout, int ks) { return split_slices(P, cout, (int64_t)ks * ks * cin); }
 int dgrad_slices(int64_t P, int cin, int cout, int ks) { return split_slices(P, cin, (int64_t)ks * ks * cout); }
 
@@ -715,8 +694,7 @@ int inim_conv_workspace(int32_t imgs, int32_t h, int32_t w, int32_t cin, int32_t
     if (!bytes) return nfail(INIM_EINVAL, "bytes NULL");
     const int64_t P = (int64_t)imgs * h * w;
     const size_t wlen = (size_t)cout * ks * ks * cin;
-    const size_t bparts = (size_t)((P + kBiasPixels - 1) / kBiasPixels);
-    size_t need = (size_t)wgrad_slices(P, cout, cin, ks) * wlen + bparts * cout;
+    size_t need = (size_t)wgrad_slices(P, cout, cin, ks) * (wlen + cout);
     const int fs = fwd_slices(P, cin, cout, ks), ds = dgrad_slices(P, cin, cout, ks);
     if (fs > 1 && (size_t)fs * P * cout > need) need = (size_t)fs * P * cout;
     if (ds > 1 && (size_t)ds * P * cin > need) need = (size_t)ds * P * cin;
@@ -781,15 +759,13 @@ int inim_conv_backward_weight(const inim_bf16* dy, const inim_bf16* x, int32_t i
     const int kslice = slice_len(a.P, slices);
     const size_t wlen = (size_t)cout * ks * ks * cin;
     a.dw = static_cast<float*>(work);
-    hipLaunchKernelGGL(k_conv_wgrad, dim3((cout + kTile - 1) / kTile, (unsigned)((ks * ks * cin + kTile - 1) / kTile), slices),
-                       dim3(256), 0, stream, a, kslice);
+    float* bp = dbias ? a.dw + (size_t)slices * wlen : nullptr;  // [slices][cout]
+    const int ncols = ks * ks * cin + (dbias ? 1 : 0);               // the bias gradient is the column of ones
+    hipLaunchKernelGGL(k_conv_wgrad, dim3((cout + kTile - 1) / kTile, (unsigned)((ncols + kTile - 1) / kTile), slices),
+                       dim3(256), 0, stream, a, kslice, bp);
     hipLaunchKernelGGL(k_sum_parts, dim3(grid_1d((int64_t)wlen)), dim3(256), 0, stream, a.dw, slices, wlen, dweight);
-    if (dbias) {
-        float* bp = a.dw + (size_t)slices * wlen;
-        const int parts = (a.P + kBiasPixels - 1) / kBiasPixels;
-        hipLaunchKernelGGL(k_bias_grad, dim3(parts), dim3(256), 0, stream, dy, a.P, cout, kBiasPixels, bp);
-        hipLaunchKernelGGL(k_sum_parts, dim3(grid_1d(cout)), dim3(256), 0, stream, bp, parts, (size_t)cout, dbias);
-    }
+    if (dbias)
+        hipLaunchKernelGGL(k_sum_parts, dim3(grid_1d(cout)), dim3(256), 0, stream, bp, slices, (size_t)cout, dbias);
     return launched("conv weight gradient");
 }
 
