@@ -38,12 +38,12 @@ PAPER_ITERS_PER_S = 8 / 12.63e-3  # Table 1: 8 iterations, 1M points, 1024^2, r 
 # --pmc runs of `bench.py --profile-short` (FETCH_SIZE, then WRITE_SIZE; see
 # profiles/pmc_traffic_regularize_1M_1024.md), each scaled by what the same
 # counter reads for a plain 256 MiB device copy in that run (FETCH_SIZE
-# counts half of the bytes read: factor 1.99985; WRITE_SIZE all: factor 1.000).
+# counts half of the bytes read: factor 1.99982; WRITE_SIZE all: factor 1.000).
 # Valid only for the sources they were taken with: SHA-256 over the file that
 # holds the kernel (k_inim.hip) and every header; otherwise traffic is null.
 TRAFFIC = {
     "src_sha256": "7714ac46842eaec9c31a43957366ea772e364451e4b41c6261daf4bc4fe7e039",
-    # k_blur_aggregate: FETCH_SIZE 4045.0 KiB x 1.99985 + WRITE_SIZE 10112.0 KiB x 1.000
+    # k_blur_aggregate: FETCH_SIZE 4045.0 KiB x 1.99982 + WRITE_SIZE 10112.0 KiB x 1.000
     "smooth_aggregate": 18638121,
 }
 
