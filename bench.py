@@ -15,6 +15,10 @@ Also reported:
     kernels), against the method on held-out point sets;
   - the integral images alone on 8192 x 8192 rasters (uint32 Poisson(4) and
     float32 lognormal, all eight planes): Gpixel/s and GB/s;
+  - parameter and quality sweeps: Table 1's grid (0.5-4M points x 1-8
+    iterations), the radius r, the background d0 and the raster size with
+    regularity, overplotting, folds, trustworthiness and orthogonal ordering,
+    and the quality curves over the iterations;
   - the FP64 CPU oracle timed on the same workload (cpu_baseline).
 Progress goes to stderr.
 """
@@ -368,6 +372,21 @@ def bench_surrogate(dev, train_sets: int = 1024, steps: int = 2500, held_out: in
     return rec
 
 
+def bench_sweeps(dev) -> dict:
+    """Parameter and quality sweeps (Table 1's grid of sample counts x
+    iterations; radius, background density and raster size with quality,
+    fold and neighbourhood measures; the quality curves over iterations)."""
+    from paper_2408_06513_amd import sweeps
+    t0 = time.time()
+    log("sweeps: Table 1 grid, r, d0, N, quality curves")
+    sw = sweeps.run_all(dev)
+    sw["summary"] = sweeps.summary(sw)
+    sw["quality_kernels"] = sweeps.kernel_times(dev)
+    sw["seconds"] = round(time.time() - t0, 1)
+    log(f"sweeps: {sw['summary']}")
+    return sw
+
+
 def cpu_baseline(xy0_np, res: int, iters: int, budget_s: float) -> dict:
     import oracle
     log("cpu baseline (oracle)")
@@ -397,7 +416,10 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip training and timing the learned surrogate")
     ap.add_argument("--surrogate-sets", type=int, default=1024, help="training point sets of the surrogate")
     ap.add_argument("--surrogate-steps", type=int, default=2500, help="training steps of the surrogate")
+    ap.add_argument("--no-sweeps", action="store_true", help="skip the parameter and quality sweeps")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--only-sweeps", action="store_true",
+                    help="print only the parameter and quality sweeps (for profiling)")
     ap.add_argument("--only-inim", action="store_true",
                     help="print only the 8192^2 integral-image measurement (for profiling)")
     ap.add_argument("--profile-short", action="store_true",
@@ -421,6 +443,9 @@ def main():
         return
     if args.profile_short:
         profile_short(args, dev)
+        return
+    if args.only_sweeps:
+        print(json.dumps({"sweeps": bench_sweeps(dev)}), flush=True)
         return
     xy0_np, value, ms_per_step, stage_us, roofline, graph_value, probe_value = bench_regularize(args, dev)
     rec = {
@@ -451,6 +476,8 @@ def main():
         rec["splom_45_plots"] = bench_splom(dev)
     if not args.no_surrogate:
         rec["surrogate_256"] = bench_surrogate(dev, args.surrogate_sets, args.surrogate_steps)
+    if not args.no_sweeps:
+        rec["sweeps"] = bench_sweeps(dev)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(xy0_np, args.res, args.iters, args.cpu_seconds)
     print(json.dumps(rec), flush=True)

@@ -20,16 +20,17 @@ def declared_symbols(header: str = "inim.h") -> set[str]:
 
 
 def test_header_and_binding_agree():
-    from paper_2408_06513_amd import nn
+    from paper_2408_06513_amd import nn, quality
     assert declared_symbols() == set(capi.EXPORTS)
     assert declared_symbols("inim_nn.h") == set(nn.NN_EXPORTS)
+    assert declared_symbols("inim_quality.h") == set(quality.QUALITY_EXPORTS)
     headers = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
-    assert headers == ["inim.h", "inim_nn.h"]
+    assert headers == ["inim.h", "inim_nn.h", "inim_quality.h"]
 
 
 def test_library_exports_every_declared_symbol():
     L = capi.lib()
-    for name in declared_symbols() | declared_symbols("inim_nn.h"):
+    for name in declared_symbols() | declared_symbols("inim_nn.h") | declared_symbols("inim_quality.h"):
         assert hasattr(L, name), name
 
 
@@ -94,3 +95,20 @@ def test_argument_errors_return_before_launch():
                                    nul, 0, nul, nul) == capi.EINVAL                        # waves_per_block
     assert L.inim_sync_status(nul, nul) == capi.EWORKSPACE
     assert "NULL" in capi.lib().inim_last_error().decode()
+
+
+@cpu_only
+def test_quality_argument_errors_return_before_launch():
+    from paper_2408_06513_amd import quality
+    L = quality.lib()
+    nul, fake = None, ctypes.c_void_p(0x1000)
+    assert L.inim_quality_bins(nul, 64, 4, fake, nul) == capi.EINVAL                 # counts NULL
+    assert L.inim_quality_bins(fake, 64, 3, fake, nul) == capi.EINVAL                # bins do not tile
+    assert L.inim_quality_bins(fake, 0, 1, fake, nul) == capi.EINVAL
+    assert L.inim_quality_ordering(fake, fake, -1, fake, nul) == capi.EINVAL
+    assert L.inim_quality_ordering(nul, fake, 5, fake, nul) == capi.EINVAL
+    assert L.inim_quality_ordering(nul, nul, 0, fake, nul) == capi.OK                # no pairs: nothing to do
+    assert L.inim_quality_trust(fake, nul, 10, 2, fake, nul) == capi.EINVAL
+    assert L.inim_quality_trust(fake, fake, 10, 0, fake, nul) == capi.EINVAL
+    assert L.inim_quality_trust(fake, fake, 10, 5, fake, nul) == capi.EINVAL          # 2k >= n
+    assert b"2k < n" in L.inim_quality_last_error()
