@@ -11,8 +11,9 @@ Also reported:
     texel lattice moved along as probe points (composite map output);
   - a 45-plot scatterplot matrix (200,000 samples x 10 dims, rasters of
     256/512/1024, 6 iterations) in one batched call against 45 single calls;
-  - the learned surrogate at 256 x 256 (trained here by the project's
-    kernels), against the method on held-out point sets;
+  - the learned surrogate of the 256 x 256 method with its network at
+    64 x 64 (trained here by the project's kernels), against the method on
+    held-out point sets, eager and as graph replays;
   - the integral images alone on 8192 x 8192 rasters (uint32 Poisson(4) and
     float32 lognormal, all eight planes): Gpixel/s and GB/s;
   - parameter and quality sweeps: Table 1's grid (0.5-4M points x 1-8
@@ -297,32 +298,35 @@ def bench_splom(dev, reps: int = 5) -> dict:
             "speedup_vs_sequential": round(t_seq / best, 2)}
 
 
-def bench_surrogate(dev, train_sets: int = 1024, steps: int = 2500, held_out: int = 16) -> dict:
-    """Learned surrogate at 256 x 256, 8 iterations: trained here on the GPU
-    by the project's kernels from point sets of 2-12 Gaussian components
-    (10k-500k points) labelled by the method itself, then compared with the
-    method on held-out point sets (uniformity, folds, gate decisions) and
-    timed per raster (events around the calls)."""
+def bench_surrogate(dev, train_sets: int = 1024, steps: int = 3000, held_out: int = 16, net_res: int = 64) -> dict:
+    """Learned surrogate of the 256 x 256, 8-iteration regularisation with the
+    network on a net_res x net_res raster: trained here on the GPU by the
+    project's kernels from point sets of 2-12 Gaussian components (10k-500k
+    points) labelled by the method itself (its composite map at the coarse
+    texel centres), then compared with the method on held-out point sets
+    (uniformity, folds, gate decisions) and timed per raster with events
+    around the calls: eagerly, as captured graph replays (both the method's
+    and the surrogate's), and batched over the held-out sets."""
     import numpy as np
     import torch
 
-    from paper_2408_06513_amd import capi, datagen, nn
+    from paper_2408_06513_amd import capi, datagen
     from paper_2408_06513_amd import surrogate as S
-    res, iters = 256, 8
-    log(f"surrogate: {train_sets} training sets")
+    res, iters, batch = 256, 8, 16
+    log(f"surrogate: {train_sets} training sets (method {res}^2, network {net_res}^2)")
     t0 = time.perf_counter()
-    X, T = S.dataset(range(train_sets), res, iters, dev)
+    X, T = S.dataset(range(train_sets), res, iters, dev, net_res=net_res)
     t_data = time.perf_counter() - t0
     net = S.UNet(dev, seed=0)
     log(f"surrogate: {steps} training steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    losses = S.train(net, X, T, steps=steps, batch=8, lr=1e-3)
+    losses = S.train(net, X, T, steps=steps, batch=batch, lr=1e-3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del X, T
     seeds = range(100_000, 100_000 + held_out)
-    ev = S.evaluate(net, seeds, res, iters, dev)
+    ev = S.evaluate(net, seeds, res, iters, dev, net_res=net_res)
 
     def ev_time(fn, reps=5):
         a = torch.cuda.Event(enable_timing=True)
@@ -336,18 +340,24 @@ def bench_surrogate(dev, train_sets: int = 1024, steps: int = 2500, held_out: in
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
-    plain_ms, sur_ms = [], []
+    plain_ms, plain_graph_ms, sur_ms, sur_graph_ms, gated_ms = [], [], [], [], []
     for s in seeds:
         xy0 = torch.from_numpy(datagen.surrogate_mixture(s)).to(dev)
         xy = xy0.clone()
         ws = capi.workspace(capi.workspace_size(res, xy.shape[0]), dev)
         plain_ms.append(ev_time(lambda: (xy.copy_(xy0), capi.regularize(xy, res, iters, ws=ws, check=False))))
+        graph = capi.Graph()
+        plain_graph_ms.append(ev_time(lambda: (xy.copy_(xy0), capi.regularize_graph(xy, res, iters, graph, ws))))
+        graph.close()
 
         def sur():
             xy.copy_(xy0)
-            f = S.predict_field(net, xy, res)
-            capi.advect(f, xy)
+            capi.advect(S.predict_field(net, xy, res, net_res=net_res), xy)
         sur_ms.append(ev_time(sur))
+        gated_ms.append(ev_time(lambda: (xy.copy_(xy0), S.regularize(net, xy, res, iters, net_res=net_res))))
+        sg = S.SurrogateGraph(net, xy.shape[0], res, net_res)
+        sur_graph_ms.append(ev_time(lambda: sg(xy0.clone())))
+        del sg
     # the held-out sets together: one batched forward pass
     xs0 = [torch.from_numpy(datagen.surrogate_mixture(s)).to(dev) for s in seeds]
     xs = [x.clone() for x in xs0]
@@ -355,20 +365,36 @@ def bench_surrogate(dev, train_sets: int = 1024, steps: int = 2500, held_out: in
     def many():
         for x, x0 in zip(xs, xs0):
             x.copy_(x0)
-        S.regularize_many(net, xs, res)
+        S.regularize_many(net, xs, res, net_res=net_res)
     t_batch = ev_time(many, 3) / len(xs)
-    t_plain_all = float(np.sum(plain_ms)) / len(xs)
-    rec = {"res": res, "iters": iters, "train_sets": train_sets, "train_steps": steps, "batch": 8,
-           "data_s": round(t_data, 1), "train_s": round(t_train, 1),
-           "loss_first10": round(float(np.mean(losses[:10])), 4), "loss_last10": round(float(np.mean(losses[-10:])), 4),
+    # the method on the same sets in one batched call (its scatterplot-matrix entry point)
+    wsb = capi.workspace(capi.batch_workspace_size(xs, [res] * len(xs)), dev)
+    cfg, _ = capi.batch_autotune(xs, [res] * len(xs), iters, ws=wsb)
+    bgraph = capi.Graph()
+
+    def plain_many():
+        for x, x0 in zip(xs, xs0):
+            x.copy_(x0)
+        capi.regularize_batch(xs, [res] * len(xs), iters, cfg=cfg, ws=wsb, graph=bgraph, check=False)
+    t_plain_batch = ev_time(plain_many, 3) / len(xs)
+    bgraph.close()
+    mean = lambda v: float(np.mean(v))
+    rec = {"res": res, "net_res": net_res, "iters": iters, "train_sets": train_sets, "train_steps": steps,
+           "batch": batch, "data_s": round(t_data, 1), "train_s": round(t_train, 1),
+           "loss_first10": round(mean(losses[:10]), 4), "loss_last10": round(mean(losses[-10:]), 4),
            "held_out": held_out, "explained_variance": round(ev["explained"], 4),
            "bin_std_gain_plain": round(ev["plain_gain"], 4), "bin_std_gain_surrogate": round(ev["surrogate_gain"], 4),
            "folded_triangles": ev["folds"], "gate_fallbacks": ev["fallbacks"],
-           "plain_ms_per_raster": round(float(np.mean(plain_ms)), 4),
-           "surrogate_ms_per_raster": round(float(np.mean(sur_ms)), 4),
-           f"surrogate_ms_per_raster_batch{held_out}": round(t_batch, 4)}
-    rec["speedup_vs_plain"] = round(rec["plain_ms_per_raster"] / rec["surrogate_ms_per_raster"], 3)
-    rec[f"speedup_vs_plain_batch{held_out}"] = round(t_plain_all / t_batch, 3)
+           "plain_ms_per_raster": round(mean(plain_ms), 4), "plain_graph_ms_per_raster": round(mean(plain_graph_ms), 4),
+           "surrogate_ms_per_raster": round(mean(sur_ms), 4),
+           "surrogate_graph_ms_per_raster": round(mean(sur_graph_ms), 4),
+           "surrogate_gated_ms_per_raster": round(mean(gated_ms), 4),
+           f"surrogate_ms_per_raster_batch{held_out}": round(t_batch, 4),
+           f"plain_batched_ms_per_raster_batch{held_out}": round(t_plain_batch, 4)}
+    best_plain = min(rec["plain_ms_per_raster"], rec["plain_graph_ms_per_raster"])
+    rec["speedup_vs_plain"] = round(best_plain / rec["surrogate_graph_ms_per_raster"], 3)
+    rec["speedup_vs_plain_eager"] = round(rec["plain_ms_per_raster"] / rec["surrogate_ms_per_raster"], 3)
+    rec[f"speedup_vs_plain_batch{held_out}"] = round(min(best_plain, t_plain_batch) / t_batch, 3)
     return rec
 
 
@@ -415,7 +441,7 @@ def main():
     ap.add_argument("--no-splom", action="store_true", help="skip the 45-plot scatterplot-matrix measurement")
     ap.add_argument("--no-surrogate", action="store_true", help="skip training and timing the learned surrogate")
     ap.add_argument("--surrogate-sets", type=int, default=1024, help="training point sets of the surrogate")
-    ap.add_argument("--surrogate-steps", type=int, default=2500, help="training steps of the surrogate")
+    ap.add_argument("--surrogate-steps", type=int, default=3000, help="training steps of the surrogate")
     ap.add_argument("--no-sweeps", action="store_true", help="skip the parameter and quality sweeps")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--only-sweeps", action="store_true",

@@ -3,10 +3,15 @@
 A five-level convolutional U-Net (channels 32/64/128/256/256, two 3x3
 convolutions with ReLU per level, 2x2 average pooling, nearest upsampling,
 concatenated skips, a 1x1 output convolution) maps the smoothed density of a
-256 x 256 raster to the displacement that `iters` iterations of the method
-give every texel centre (the composite map of Sec. 4.3 minus the identity,
-in 1/64 of the unit square).  The samples are then moved by one bilinear advection of that
-field.  It is trained on fields that the method itself computes, and the
+point set to the displacement that `iters` iterations of the method on a
+res x res raster give the texel centres of a net_res x net_res lattice (the
+composite map of Sec. 4.3 minus the identity, in 1/64 of the unit square).
+The samples are then moved by one bilinear advection of that field.  With
+net_res < res the network sees a coarser raster than the method (its
+Gaussian radius scaled by net_res / res): the composite map is smooth on the
+scale of the method's Gaussian, a coarse field captures it at a sixteenth
+of the work for res / net_res = 4, and bilinear interpolation of a
+fold-free coarse lattice of convex cells cannot fold between its nodes.  It is trained on fields that the method itself computes, and the
 method remains the judge and the fallback: a prediction whose deformed
 lattice folds, or that does not make the samples more uniform, is replaced by
 the plain regularisation.
@@ -196,27 +201,41 @@ class UNet:
 
 
 # ------------------------------------------------------------------ data
-def example(xy_np: np.ndarray, res: int, iters: int, dev, radius: int = 8):
-    """Input [res, res, 8] bf16 and target [res, res, 2] f32 (the displacement
-    of the texel centres by `iters` iterations, in texels) of one point set."""
+def net_radius(radius: int, res: int, net_res: int) -> int:
+    """The method's Gaussian radius on the network's coarser raster."""
+    return max(1, round(radius * net_res / res))
+
+
+def density_input(xy: torch.Tensor, net_res: int, radius: int, out16: torch.Tensor, counts=None, dens=None):
+    """The network's input channel: the smoothed density on the net_res raster
+    divided by its mean (bf16 [net_res, net_res, 8], other channels 0)."""
+    if counts is None:
+        counts = torch.empty((net_res, net_res), dtype=torch.uint32, device=xy.device)
+    if dens is None:
+        dens = torch.empty((net_res, net_res), dtype=F32, device=xy.device)
+    capi.rasterize(xy, net_res, radius=radius, counts=counts, density=dens)
+    return nn.pack_density(dens, net_res * net_res / xy.shape[0], out16)
+
+
+def example(xy_np: np.ndarray, res: int, iters: int, dev, radius: int = 8, net_res: int | None = None):
+    """Input [net_res, net_res, 8] bf16 and target [net_res, net_res, 2] f32:
+    the displacement by `iters` iterations of the method on a res x res
+    raster, at the texel centres of the net_res lattice, of one point set."""
+    net_res = net_res or res
     xy = torch.from_numpy(xy_np).to(dev)
-    n = xy.shape[0]
-    counts = torch.empty((res, res), dtype=torch.uint32, device=dev)
-    dens = torch.empty((res, res), dtype=F32, device=dev)
-    capi.rasterize(xy, res, radius=radius, counts=counts, density=dens)
-    x16 = torch.empty((res, res, CIN), dtype=BF16, device=dev)
-    nn.pack_density(dens, res * res / n, x16)
-    lat = torch.from_numpy(datagen.lattice_points(res)).to(dev)
+    x16 = torch.empty((net_res, net_res, CIN), dtype=BF16, device=dev)
+    density_input(xy, net_res, net_radius(radius, res, net_res), x16)
+    lat = torch.from_numpy(datagen.lattice_points(net_res)).to(dev)
     capi.regularize_probes(xy.clone(), lat, res, iters, radius=radius)
-    tgt = torch.empty((res, res, 2), dtype=F32, device=dev)
-    nn.displacement(lat, res, tgt)
+    tgt = torch.empty((net_res, net_res, 2), dtype=F32, device=dev)
+    nn.displacement(lat, net_res, tgt)
     return x16, tgt
 
 
-def dataset(seeds, res: int, iters: int, dev, n_hi: int = 500_000):
+def dataset(seeds, res: int, iters: int, dev, n_hi: int = 500_000, net_res: int | None = None):
     xs, ts = [], []
     for s in seeds:
-        x, t = example(datagen.surrogate_mixture(s, n_hi=n_hi), res, iters, dev)
+        x, t = example(datagen.surrogate_mixture(s, n_hi=n_hi), res, iters, dev, net_res=net_res)
         xs.append(x)
         ts.append(t)
     return torch.stack(xs), torch.stack(ts)
@@ -262,44 +281,86 @@ def field_radius(res: int) -> int:
     return 2 if res <= 64 else min(16, res // 16)
 
 
-def predict_field(net: UNet, xy: torch.Tensor, res: int, radius: int = 8) -> torch.Tensor:
-    n = xy.shape[0]
-    dens = torch.empty((res, res), dtype=F32, device=xy.device)
-    counts = torch.empty((res, res), dtype=torch.uint32, device=xy.device)
-    capi.rasterize(xy, res, radius=radius, counts=counts, density=dens)
-    x16 = torch.empty((1, res, res, CIN), dtype=BF16, device=xy.device)
-    nn.pack_density(dens, res * res / n, x16)
+def predict_field(net: UNet, xy: torch.Tensor, res: int, radius: int = 8, net_res: int | None = None) -> torch.Tensor:
+    """The predicted composite map (absolute positions) on the net_res lattice."""
+    net_res = net_res or res
+    x16 = torch.empty((1, net_res, net_res, CIN), dtype=BF16, device=xy.device)
+    density_input(xy, net_res, net_radius(radius, res, net_res), x16[0])
     y = net.forward(x16)
-    field = torch.empty((res, res, 2), dtype=F32, device=xy.device)
-    return nn.field(y[0], res, field, field_radius(res))
+    field = torch.empty((net_res, net_res, 2), dtype=F32, device=xy.device)
+    return nn.field(y[0], net_res, field, field_radius(net_res))
 
 
-def regularize_many(net: UNet, xys, res: int) -> None:
+def regularize_many(net: UNet, xys, res: int, radius: int = 8, net_res: int | None = None) -> None:
     """The surrogate's move of several point sets at once (one batched
     forward pass), in place and without the gate."""
+    net_res = net_res or res
     k = len(xys)
-    x16 = torch.empty((k, res, res, CIN), dtype=BF16, device=net.dev)
-    dens = torch.empty((res, res), dtype=F32, device=net.dev)
-    counts = torch.empty((res, res), dtype=torch.uint32, device=net.dev)
+    x16 = torch.empty((k, net_res, net_res, CIN), dtype=BF16, device=net.dev)
+    dens = torch.empty((net_res, net_res), dtype=F32, device=net.dev)
+    counts = torch.empty((net_res, net_res), dtype=torch.uint32, device=net.dev)
+    r = net_radius(radius, res, net_res)
     for q, xy in enumerate(xys):
-        capi.rasterize(xy, res, counts=counts, density=dens)
-        nn.pack_density(dens, res * res / xy.shape[0], x16[q])
+        density_input(xy, net_res, r, x16[q], counts, dens)
     y = net.forward(x16)
-    field = torch.empty((res, res, 2), dtype=F32, device=net.dev)
+    field = torch.empty((net_res, net_res, 2), dtype=F32, device=net.dev)
     for q, xy in enumerate(xys):
-        nn.field(y[q], res, field, field_radius(res))
+        nn.field(y[q], net_res, field, field_radius(net_res))
         capi.advect(field, xy)
 
 
-def regularize(net: UNet, xy: torch.Tensor, res: int, iters: int, min_gain: float = 0.2):
+class SurrogateGraph:
+    """The surrogate's move of n samples (density on the net_res raster,
+    forward pass, field, advection) captured once as a HIP graph and replayed,
+    for callers that repeat it on sets of the same size.  Every buffer is
+    allocated before the capture; the library's kernels clear their own
+    status words, so nothing in the graph is a memset.  Same results as
+    predict_field + advect, without the gate."""
+
+    def __init__(self, net: UNet, n: int, res: int, net_res: int | None = None, radius: int = 8):
+        self.net, self.res, self.net_res = net, res, net_res or res
+        dev = net.dev
+        r = self.net_res
+        self.radius = net_radius(radius, res, r)
+        self.xy = torch.zeros((n, 2), dtype=F32, device=dev) + 0.5
+        self.x16 = torch.empty((1, r, r, CIN), dtype=BF16, device=dev)
+        self.counts = torch.empty((r, r), dtype=torch.uint32, device=dev)
+        self.dens = torch.empty((r, r), dtype=F32, device=dev)
+        self.field = torch.empty((r, r, 2), dtype=F32, device=dev)
+        self.fwork = torch.empty_like(self.field)
+        self.ws = capi.workspace(256, dev)
+        self._run()  # sizes the network's work buffer outside the capture
+        torch.cuda.synchronize(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._run()
+        torch.cuda.synchronize(dev)
+
+    def _run(self):
+        density_input(self.xy, self.net_res, self.radius, self.x16[0], self.counts, self.dens)
+        y = self.net.forward(self.x16)
+        nn.field(y[0], self.net_res, self.field, field_radius(self.net_res), work=self.fwork)
+        capi.advect(self.field, self.xy, ws=self.ws)
+
+    def __call__(self, xy: torch.Tensor) -> torch.Tensor:
+        """Moves xy (same n) in place; returns it."""
+        self.xy.copy_(xy)
+        self.graph.replay()
+        xy.copy_(self.xy)
+        return xy
+
+
+def regularize(net: UNet, xy: torch.Tensor, res: int, iters: int, min_gain: float = 0.2,
+               net_res: int | None = None):
     """Moves xy (in place) by the surrogate's field when its deformed lattice
     has no fold and it lowers the bin standard deviation by at least
     `min_gain`; otherwise runs the plain method.  Returns 'surrogate' or
     'fallback'."""
+    net_res = net_res or res
     before = bin_std(xy, res)
-    field = predict_field(net, xy, res)
+    field = predict_field(net, xy, res, net_res=net_res)
     folds = torch.zeros(1, dtype=torch.uint32, device=xy.device)
-    nn.count_folds(field, res, folds)
+    nn.count_folds(field, net_res, folds)
     moved = xy.clone()
     capi.advect(field, moved)
     if int(folds.item()) == 0 and bin_std(moved, res) <= (1.0 - min_gain) * before:
@@ -309,7 +370,8 @@ def regularize(net: UNet, xy: torch.Tensor, res: int, iters: int, min_gain: floa
     return "fallback"
 
 
-def evaluate(net: UNet, seeds, res: int, iters: int, dev, n_hi: int = 500_000, min_gain: float = 0.2) -> dict:
+def evaluate(net: UNet, seeds, res: int, iters: int, dev, n_hi: int = 500_000, min_gain: float = 0.2,
+             net_res: int | None = None) -> dict:
     """Held-out comparison on fresh point sets: bin standard deviation (4 x 4
     texel bins) before, after the plain method, after the surrogate's field;
     folds of the surrogate's deformed lattice; how often the gate falls back;
@@ -321,12 +383,12 @@ def evaluate(net: UNet, seeds, res: int, iters: int, dev, n_hi: int = 500_000, m
         before = bin_std(xy, res)
         plain = xy.clone()
         capi.regularize(plain, res, iters)
-        field = predict_field(net, xy, res)
+        field = predict_field(net, xy, res, net_res=net_res)
         folds = torch.zeros(1, dtype=torch.uint32, device=dev)
-        nn.count_folds(field, res, folds)
+        nn.count_folds(field, net_res or res, folds)
         sur = xy.clone()
         capi.advect(field, sur)
-        x16, tgt = example(xy_np, res, iters, dev)
+        x16, tgt = example(xy_np, res, iters, dev, net_res=net_res)
         y = net.forward(x16[None].contiguous())
         loss = torch.zeros(1, dtype=F32, device=dev)
         nn.mse(y, tgt[None].contiguous(), loss)
@@ -334,7 +396,7 @@ def evaluate(net: UNet, seeds, res: int, iters: int, dev, n_hi: int = 500_000, m
         base = torch.zeros(1, dtype=F32, device=dev)
         nn.mse(zero, tgt[None].contiguous(), base)
         gated = xy.clone()
-        which = regularize(net, gated, res, iters, min_gain)
+        which = regularize(net, gated, res, iters, min_gain, net_res=net_res)
         rows.append({"n": int(xy.shape[0]), "before": before, "plain": bin_std(plain, res),
                      "surrogate": bin_std(sur, res), "folds": int(folds.item()), "gate": which,
                      "mse": float(loss.item()), "mse_zero": float(base.item())})

@@ -43,3 +43,38 @@ def test_training_gains_over_untrained(capsys):
     assert trained["folds"] <= 0.01 * triangles
     assert all(r["folds"] == 0 for r in trained["rows"] if r["gate"] == "surrogate")
     assert untrained["fallbacks"] == len(untrained["rows"])
+
+
+def test_coarse_network_for_a_finer_raster_and_its_graph_replay():
+    """The network at 64 x 64 predicting the 256 x 256 method's composite map
+    at the coarse texel centres: most of the method's gain, every prediction
+    the gate lets through fold-free; the captured replay of the move equals
+    the eager one bit for bit on every replay, with other GPU work between."""
+    from paper_2408_06513_amd import capi, datagen
+    from paper_2408_06513_amd import surrogate as S
+    dev = torch.device("cuda:0")
+    res, net_res, iters = 256, 64, 8
+    note("dataset: 160 point sets, method at 256^2, network at 64^2")
+    X, T = S.dataset(range(160), res, iters, dev, n_hi=100_000, net_res=net_res)
+    assert X.shape == (160, net_res, net_res, S.CIN) and T.shape == (160, net_res, net_res, 2)
+    net = S.UNet(dev, seed=1)
+    losses = S.train(net, X, T, steps=600, batch=16, lr=1e-3, log=note)
+    assert np.mean(losses[-10:]) < 0.5 * np.mean(losses[:10])
+    ev = S.evaluate(net, range(2000, 2008), res, iters, dev, n_hi=100_000, net_res=net_res)
+    note(f"explained {ev['explained']:.3f} gain {ev['surrogate_gain']:.3f} (plain {ev['plain_gain']:.3f}) "
+         f"folds {ev['folds']} fallbacks {ev['fallbacks']}")
+    assert ev["explained"] > 0.8
+    assert ev["surrogate_gain"] > 0.7 * ev["plain_gain"]
+    assert all(r["folds"] == 0 for r in ev["rows"] if r["gate"] == "surrogate")
+
+    xy0 = torch.from_numpy(datagen.surrogate_mixture(2100, n_hi=100_000)).to(dev)
+    eager = xy0.clone()
+    capi.advect(S.predict_field(net, eager, res, net_res=net_res), eager)
+    g = S.SurrogateGraph(net, xy0.shape[0], res, net_res)
+    other = torch.from_numpy(datagen.plain_small(0)).to(dev)
+    for rep in range(3):
+        out = g(xy0.clone())
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        capi.regularize(other.clone(), 256, 2)  # unrelated eager work between replays
+        torch.cuda.synchronize()
