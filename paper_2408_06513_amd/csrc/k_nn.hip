@@ -36,19 +36,33 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 
 // ------------------------------------------------------------------ implicit GEMM
-// C[m][n] = sum_k A[m][k] B[k][n] over one 128 x 128 block tile, K in steps of
+// C[m][n] = sum_k A[m][k] B[k][n] over one BM x BN block tile, K in steps of
 // 32 staged through LDS as [row][k] for A and [col][k] for B, so that every
 // lane reads its 8 consecutive k of one row (A) or one column (B) as one
-// 16-byte LDS read.  Four waves, each 64 x 64 = 2 x 2 tiles of the 32 x 32 x 16
-// BF16 MFMA.  MFMA lane layout (gfx950, 32x32x16): lane l holds A[l%32][8(l/32)+j]
-// and B[8(l/32)+j][l%32] for j < 8; result register i of lane l is
-// C[8(i/4) + 4(l/32) + i%4][l%32].
-constexpr int kBM = 128, kBN = 128, kBK = 32, kPad = 8;
+// 16-byte LDS read.  Four waves of 32 x 32 x 16 BF16 MFMA tiles: 2 x 2 waves
+// of 64 x 64 for the square 128 x 128 tile; for narrow outputs (N <= 64,
+// where a 128-wide tile would leave most matrix-core columns idle) 4 x 1
+// waves of 64 x BN over a 256-row tile.  MFMA lane layout (gfx950,
+// 32x32x16): lane l holds A[l%32][8(l/32)+j] and B[8(l/32)+j][l%32] for j < 8;
+// result register i of lane l is C[8(i/4) + 4(l/32) + i%4][l%32].
+constexpr int kBK = 32, kPad = 8;
 
-struct GemmLds {
-    uint16_t a[kBM][kBK + kPad];
-    uint16_t b[kBN][kBK + kPad];
+template <int BM, int BN>
+struct Tile {
+    static constexpr int wavesN = BN >= 128 ? 2 : 1, wavesM = 4 / wavesN;
+    static constexpr int WM = BM / wavesM, WN = BN / wavesN;  // one wave's part
+    static constexpr int TI = WM / 32, TJ = WN / 32;          // its MFMA tiles
+    static constexpr int AC = BM * kBK / 8 / 256;             // A chunks per thread
+    static constexpr int BC = (BN * kBK / 8 + 255) / 256;     // B chunks per thread (at most)
+    static_assert(WM == 64 && WN % 32 == 0 && TJ >= 1, "tile shape");
 };
+
+template <int BM, int BN>
+struct GemmLdsT {
+    uint16_t a[BM][kBK + kPad];
+    uint16_t b[BN][kBK + kPad];
+};
+using GemmLds = GemmLdsT<128, 128>;
 
 // Element source of one operand: 8 consecutive k of row (A) or column (B) `r`.
 // Conv geometry: pixel p = (img, y, x) of an H x W image, taps t = (ky, kx).
@@ -93,32 +107,44 @@ struct WeightLoader {  // B of forward / input gradient: rows of [N][K] contiguo
     }
 };
 
-// One K step of 32 in flight: the four 8-element chunks this thread moves
-// (two of A, two of B), loaded from global memory into registers while the
-// matrix cores work on the previous step, then written to LDS.
-struct Chunks {
-    u16x8 a[2], b[2];
+// One K step of 32 in flight: the 8-element chunks this thread moves, loaded
+// from global memory into registers while the matrix cores work on the
+// previous step, then written to LDS.
+template <int AC, int BC>
+struct ChunksT {
+    u16x8 a[AC], b[BC];
 };
+using Chunks = ChunksT<2, 2>;
 
-template <class LA, class LB>
-__device__ __forceinline__ void load_vec(Chunks& c, const LA& la, const LB& lb, int bm, int bn, int k0) {
-    // 128 rows x 32 k of A and of B: 512 chunks of 8 each, two per thread
+// BM rows x 32 k of A and BN rows x 32 k of B in chunks of 8 consecutive k:
+// chunk e is row e / 4, k offset 8 (e % 4).
+template <int BM, int BN, class LA, class LB>
+__device__ __forceinline__ void load_vec(ChunksT<Tile<BM, BN>::AC, Tile<BM, BN>::BC>& c, const LA& la, const LB& lb,
+                                         int bm, int bn, int k0) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < Tile<BM, BN>::AC; ++h) {
         const int e = threadIdx.x + 256 * h;
-        const int r = e >> 2, kc = (e & 3) * 8;
-        c.a[h] = la.load8(bm + r, k0 + kc);
-        c.b[h] = lb.load8(bn + r, k0 + kc);
+        c.a[h] = la.load8(bm + (e >> 2), k0 + (e & 3) * 8);
+    }
+#pragma unroll
+    for (int h = 0; h < Tile<BM, BN>::BC; ++h) {
+        const int e = threadIdx.x + 256 * h;
+        if (e < BN * 4) c.b[h] = lb.load8(bn + (e >> 2), k0 + (e & 3) * 8);
     }
 }
 
-__device__ __forceinline__ void store_vec(const Chunks& c, GemmLds& s) {
+template <int BM, int BN>
+__device__ __forceinline__ void store_vec(const ChunksT<Tile<BM, BN>::AC, Tile<BM, BN>::BC>& c,
+                                          GemmLdsT<BM, BN>& s) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < Tile<BM, BN>::AC; ++h) {
         const int e = threadIdx.x + 256 * h;
-        const int r = e >> 2, kc = (e & 3) * 8;
-        *reinterpret_cast<u16x8*>(&s.a[r][kc]) = c.a[h];
-        *reinterpret_cast<u16x8*>(&s.b[r][kc]) = c.b[h];
+        *reinterpret_cast<u16x8*>(&s.a[e >> 2][(e & 3) * 8]) = c.a[h];
+    }
+#pragma unroll
+    for (int h = 0; h < Tile<BM, BN>::BC; ++h) {
+        const int e = threadIdx.x + 256 * h;
+        if (e < BN * 4) *reinterpret_cast<u16x8*>(&s.b[e >> 2][(e & 3) * 8]) = c.b[h];
     }
 }
 
@@ -171,33 +197,42 @@ __device__ __forceinline__ void store_wgrad(const Chunks& c, GemmLds& s) {
     }
 }
 
-// The MFMA part of one K step of 32 for this wave's 64 x 64.
-__device__ __forceinline__ void mma_step(const GemmLds& s, f32x16 (&acc)[2][2], int wm, int wn, int lane) {
+// The MFMA part of one K step of 32 for this wave's WM x WN.
+template <int BM, int BN>
+__device__ __forceinline__ void mma_step(const GemmLdsT<BM, BN>& s, f32x16 (&acc)[Tile<BM, BN>::TI][Tile<BM, BN>::TJ],
+                                         int wm, int wn, int lane) {
+    using T = Tile<BM, BN>;
 #pragma unroll
     for (int kk = 0; kk < kBK; kk += 16) {
-        bf16x8 a[2], b[2];
+        bf16x8 a[T::TI], b[T::TJ];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const u16x8 va = *reinterpret_cast<const u16x8*>(&s.a[wm * 64 + i * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
-            const u16x8 vb = *reinterpret_cast<const u16x8*>(&s.b[wn * 64 + i * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+        for (int i = 0; i < T::TI; ++i) {
+            const u16x8 va = *reinterpret_cast<const u16x8*>(&s.a[wm * T::WM + i * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
             a[i] = __builtin_bit_cast(bf16x8, va);
-            b[i] = __builtin_bit_cast(bf16x8, vb);
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < T::TJ; ++j) {
+            const u16x8 vb = *reinterpret_cast<const u16x8*>(&s.b[wn * T::WN + j * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+            b[j] = __builtin_bit_cast(bf16x8, vb);
+        }
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < T::TI; ++i)
+#pragma unroll
+            for (int j = 0; j < T::TJ; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
 }
 
 // The K loop over [kbeg, kend) with two LDS buffers: the global loads of
 // step i+1 are issued before the MFMAs of step i and written to the other
-// buffer after them; one barrier per step.
-template <class Load, class Store>
-__device__ __forceinline__ void gemm_loop(GemmLds (&s)[2], f32x16 (&acc)[2][2], int kbeg, int kend, Load load,
-                                          Store store) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
-    Chunks c;
+// buffer after them; one barrier per step.  s points to the two buffers; C is
+// the chunk type the load and store callbacks move.
+template <int BM, int BN, class C, class Load, class Store>
+__device__ __forceinline__ void gemm_loop(GemmLdsT<BM, BN>* s, f32x16 (&acc)[Tile<BM, BN>::TI][Tile<BM, BN>::TJ],
+                                          int kbeg, int kend, Load load, Store store) {
+    using T = Tile<BM, BN>;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave / T::wavesN, wn = wave % T::wavesN;
+    C c;
     if (kbeg >= kend) return;
     load(c, kbeg);
     store(c, s[0]);
@@ -206,7 +241,7 @@ __device__ __forceinline__ void gemm_loop(GemmLds (&s)[2], f32x16 (&acc)[2][2], 
     for (int k0 = kbeg; k0 < kend; k0 += kBK) {
         const bool more = k0 + kBK < kend;
         if (more) load(c, k0 + kBK);
-        mma_step(s[cur], acc, wm, wn, lane);
+        mma_step<BM, BN>(s[cur], acc, wm, wn, lane);
         if (more) store(c, s[cur ^ 1]);
         __syncthreads();
         cur ^= 1;
@@ -214,17 +249,19 @@ __device__ __forceinline__ void gemm_loop(GemmLds (&s)[2], f32x16 (&acc)[2][2], 
 }
 
 // Epilogue over this wave's results: f(m, n, value).
-template <class F>
-__device__ __forceinline__ void for_each_result(const f32x16 (&acc)[2][2], int bm, int bn, F f) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
+template <int BM, int BN, class F>
+__device__ __forceinline__ void for_each_result(const f32x16 (&acc)[Tile<BM, BN>::TI][Tile<BM, BN>::TJ], int bm,
+                                                int bn, F f) {
+    using T = Tile<BM, BN>;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave / T::wavesN, wn = wave % T::wavesN;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < T::TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < T::TJ; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int m = bm + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int n = bn + wn * 64 + j * 32 + (lane & 31);
+                const int m = bm + wm * T::WM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int n = bn + wn * T::WN + j * 32 + (lane & 31);
                 f(m, n, acc[i][j][r]);
             }
 }
@@ -239,26 +276,29 @@ __device__ __forceinline__ void k_range(int K, int kslice, int& kbeg, int& kend)
 // y = act(b + sum x w) as BF16 (y16) and/or FP32 (y32); with gridDim.z > 1
 // slice z of the K range writes its FP32 partial sums to part[z][p][co] and
 // k_conv_finish completes the layer.
+template <int BM, int BN>
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a, int kslice, float* part) {
-    __shared__ GemmLds s[2];
-    const int bm = blockIdx.x * kBM, bn = blockIdx.y * kBN;
+    using T = Tile<BM, BN>;
+    using C = ChunksT<T::AC, T::BC>;
+    __shared__ GemmLdsT<BM, BN> s[2];
+    const int bm = blockIdx.x * BM, bn = blockIdx.y * BN;
     const ConvGeom g{a.H, a.W, a.P, a.ks, a.ks * a.ks, a.ks / 2};
     const int K = g.taps * a.Cin;
     const RowShiftLoader la{a.x, a.Cin, 1, a.P, K, g};
     const WeightLoader lb{a.w, a.Cout, K};
     int kbeg, kend;
     k_range(K, kslice, kbeg, kend);
-    f32x16 acc[2][2] = {};
-    gemm_loop(s, acc, kbeg, kend, [&](Chunks& c, int k0) { load_vec(c, la, lb, bm, bn, k0); },
-              [&](const Chunks& c, GemmLds& l) { store_vec(c, l); });
+    f32x16 acc[T::TI][T::TJ] = {};
+    gemm_loop<BM, BN, C>(s, acc, kbeg, kend, [&](C& c, int k0) { load_vec<BM, BN>(c, la, lb, bm, bn, k0); },
+                         [&](const C& c, GemmLdsT<BM, BN>& l) { store_vec<BM, BN>(c, l); });
     if (gridDim.z > 1) {
         float* out = part + (size_t)blockIdx.z * a.P * a.Cout;
-        for_each_result(acc, bm, bn, [&](int m, int n, float v) {
+        for_each_result<BM, BN>(acc, bm, bn, [&](int m, int n, float v) {
             if (m < a.P && n < a.Cout) out[(size_t)m * a.Cout + n] = v;
         });
         return;
     }
-    for_each_result(acc, bm, bn, [&](int m, int n, float v) {
+    for_each_result<BM, BN>(acc, bm, bn, [&](int m, int n, float v) {
         if (m >= a.P || n >= a.Cout) return;
         v += a.bias ? a.bias[n] : 0.0f;
         if (a.relu) v = v > 0.0f ? v : 0.0f;
@@ -284,20 +324,23 @@ __global__ __launch_bounds__(256) void k_conv_finish(ConvArgs a, int slices, con
 
 // Input gradient: dx[q][ci] = sum_{t, co} dy[q - off_t][co] wT[ci][t][co],
 // FP32; split slices write part[z] and k_sum_parts adds them.
+template <int BM, int BN>
 __global__ __launch_bounds__(256) void k_conv_dgrad(ConvArgs a, int kslice, float* part) {
-    __shared__ GemmLds s[2];
-    const int bm = blockIdx.x * kBM, bn = blockIdx.y * kBN;
+    using T = Tile<BM, BN>;
+    using C = ChunksT<T::AC, T::BC>;
+    __shared__ GemmLdsT<BM, BN> s[2];
+    const int bm = blockIdx.x * BM, bn = blockIdx.y * BN;
     const ConvGeom g{a.H, a.W, a.P, a.ks, a.ks * a.ks, a.ks / 2};
     const int K = g.taps * a.Cout;
     const RowShiftLoader la{a.dy, a.Cout, -1, a.P, K, g};
     const WeightLoader lb{a.wT, a.Cin, K};
     int kbeg, kend;
     k_range(K, kslice, kbeg, kend);
-    f32x16 acc[2][2] = {};
-    gemm_loop(s, acc, kbeg, kend, [&](Chunks& c, int k0) { load_vec(c, la, lb, bm, bn, k0); },
-              [&](const Chunks& c, GemmLds& l) { store_vec(c, l); });
+    f32x16 acc[T::TI][T::TJ] = {};
+    gemm_loop<BM, BN, C>(s, acc, kbeg, kend, [&](C& c, int k0) { load_vec<BM, BN>(c, la, lb, bm, bn, k0); },
+                         [&](const C& c, GemmLdsT<BM, BN>& l) { store_vec<BM, BN>(c, l); });
     float* out = gridDim.z > 1 ? part + (size_t)blockIdx.z * a.P * a.Cin : a.dx;
-    for_each_result(acc, bm, bn, [&](int m, int n, float v) {
+    for_each_result<BM, BN>(acc, bm, bn, [&](int m, int n, float v) {
         if (m < a.P && n < a.Cin) out[(size_t)m * a.Cin + n] = v;
     });
 }
@@ -308,17 +351,17 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(ConvArgs a, int kslice, floa
 // (the column of ones).
 __global__ __launch_bounds__(256) void k_conv_wgrad(ConvArgs a, int kslice, float* bias_part) {
     __shared__ GemmLds s[2];
-    const int bm = blockIdx.x * kBM, bn = blockIdx.y * kBN;
+    const int bm = blockIdx.x * 128, bn = blockIdx.y * 128;
     const ConvGeom g{a.H, a.W, a.P, a.ks, a.ks * a.ks, a.ks / 2};
     const int N = g.taps * a.Cin;
     const WgradSrc src{a.dy, a.x, a.Cout, a.Cin, N, bias_part != nullptr, g};
     int kbeg, kend;
     k_range(a.P, kslice, kbeg, kend);
     f32x16 acc[2][2] = {};
-    gemm_loop(s, acc, kbeg, kend, [&](Chunks& c, int k0) { load_wgrad(c, src, bm, bn, k0); },
-              [&](const Chunks& c, GemmLds& l) { store_wgrad(c, l); });
+    gemm_loop<128, 128, Chunks>(s, acc, kbeg, kend, [&](Chunks& c, int k0) { load_wgrad(c, src, bm, bn, k0); },
+                                [&](const Chunks& c, GemmLds& l) { store_wgrad(c, l); });
     float* out = a.dw + (size_t)blockIdx.z * a.Cout * N;
-    for_each_result(acc, bm, bn, [&](int m, int n, float v) {
+    for_each_result<128, 128>(acc, bm, bn, [&](int m, int n, float v) {
         if (m >= a.Cout) return;
         if (n < N) out[(size_t)m * N + n] = v;
         else if (n == N && bias_part) bias_part[(size_t)blockIdx.z * a.Cout + m] = v;
@@ -665,8 +708,19 @@ int check_conv(int32_t imgs, int32_t h, int32_t w, int32_t cin, int32_t cout, in
 
 // Slices of a K range of `klen` for an M x N tile grid: enough blocks to
 // fill the chip (512), each slice at least 4 steps of 32.
-int split_slices(int64_t rows, int64_t cols, int64_t klen) {
-    const int64_t tiles = ((rows + kTile - 1) / kTile) * ((cols + kTile - 1) / kTile);
+// Block tile of a forward or input-gradient GEMM with n output columns:
+// 256 x 32 or 256 x 64 when the outputs are that narrow, else 128 x 128.
+struct TileShape {
+    int bm, bn;
+};
+TileShape conv_tile(int64_t n) {
+    if (n <= 32) return {256, 32};
+    if (n <= 64) return {256, 64};
+    return {kTile, kTile};
+}
+
+int split_slices(int64_t rows, int64_t cols, int64_t klen, TileShape t = {kTile, kTile}) {
+    const int64_t tiles = ((rows + t.bm - 1) / t.bm) * ((cols + t.bn - 1) / t.bn);
     int64_t s = (512 + tiles - 1) / tiles;
     const int64_t steps = (klen + kStepK - 1) / kStepK;
     if (s > steps / 4) s = steps / 4;
@@ -679,8 +733,38 @@ int slice_len(int64_t klen, int slices) {
 }
 
 int wgrad_slices(int64_t P, int cout, int cin, int ks) { return split_slices(cout, (int64_t)ks * ks * cin + 1, P); }
-int fwd_slices(int64_t P, int cin, int cout, int ks) { return split_slices(P, cout, (int64_t)ks * ks * cin); }
-int dgrad_slices(int64_t P, int cin, int cout, int ks) { return split_slices(P, cin, (int64_t)ks * ks * cout); }
+int fwd_slices(int64_t P, int cin, int cout, int ks) {
+    return split_slices(P, cout, (int64_t)ks * ks * cin, conv_tile(cout));
+}
+int dgrad_slices(int64_t P, int cin, int cout, int ks) {
+    return split_slices(P, cin, (int64_t)ks * ks * cout, conv_tile(cin));
+}
+
+// Launches k_conv_fwd or k_conv_dgrad with the block tile for n output columns.
+template <template <int, int> class Kern>
+void launch_conv_gemm(int64_t P, int64_t n, int slices, hipStream_t stream, const ConvArgs& a, int kslice,
+                      float* part);
+template <int BM, int BN>
+struct FwdKernel {
+    static void launch(dim3 grd, hipStream_t st, const ConvArgs& a, int kslice, float* part) {
+        hipLaunchKernelGGL((k_conv_fwd<BM, BN>), grd, dim3(256), 0, st, a, kslice, part);
+    }
+};
+template <int BM, int BN>
+struct DgradKernel {
+    static void launch(dim3 grd, hipStream_t st, const ConvArgs& a, int kslice, float* part) {
+        hipLaunchKernelGGL((k_conv_dgrad<BM, BN>), grd, dim3(256), 0, st, a, kslice, part);
+    }
+};
+template <template <int, int> class Kern>
+void launch_conv_gemm(int64_t P, int64_t n, int slices, hipStream_t stream, const ConvArgs& a, int kslice,
+                      float* part) {
+    const TileShape t = conv_tile(n);
+    const dim3 grd((unsigned)((P + t.bm - 1) / t.bm), (unsigned)((n + t.bn - 1) / t.bn), slices);
+    if (t.bn == 32) Kern<256, 32>::launch(grd, stream, a, kslice, part);
+    else if (t.bn == 64) Kern<256, 64>::launch(grd, stream, a, kslice, part);
+    else Kern<128, 128>::launch(grd, stream, a, kslice, part);
+}
 
 }  // namespace
 
@@ -714,9 +798,8 @@ int inim_conv_forward(const inim_bf16* x, int32_t imgs, int32_t h, int32_t w, in
     const int K = ks * ks * cin;
     int slices = fwd_slices(a.P, cin, cout, ks);
     if (!work || work_bytes < (size_t)slices * a.P * cout * sizeof(float)) slices = 1;  // no room: one slice
-    const dim3 grd((a.P + kTile - 1) / kTile, (cout + kTile - 1) / kTile, slices);
-    hipLaunchKernelGGL(k_conv_fwd, grd, dim3(256), 0, stream, a, slices > 1 ? slice_len(K, slices) : K,
-                       static_cast<float*>(work));
+    launch_conv_gemm<FwdKernel>(a.P, cout, slices, stream, a, slices > 1 ? slice_len(K, slices) : K,
+                                static_cast<float*>(work));
     if (slices > 1)
         hipLaunchKernelGGL(k_conv_finish, dim3(grid_1d((int64_t)a.P * cout)), dim3(256), 0, stream, a, slices,
                            static_cast<const float*>(work));
@@ -735,9 +818,8 @@ int inim_conv_backward_data(const inim_bf16* dy, int32_t imgs, int32_t h, int32_
     const int K = ks * ks * cout;
     int slices = dgrad_slices(a.P, cin, cout, ks);
     if (!work || work_bytes < (size_t)slices * a.P * cin * sizeof(float)) slices = 1;
-    const dim3 grd((a.P + kTile - 1) / kTile, (cin + kTile - 1) / kTile, slices);
-    hipLaunchKernelGGL(k_conv_dgrad, grd, dim3(256), 0, stream, a, slices > 1 ? slice_len(K, slices) : K,
-                       static_cast<float*>(work));
+    launch_conv_gemm<DgradKernel>(a.P, cin, slices, stream, a, slices > 1 ? slice_len(K, slices) : K,
+                                  static_cast<float*>(work));
     if (slices > 1)
         hipLaunchKernelGGL(k_sum_parts, dim3(grid_1d((int64_t)a.P * cin)), dim3(256), 0, stream,
                            static_cast<const float*>(work), slices, (size_t)a.P * cin, dx);

@@ -17,7 +17,8 @@ torch = pytest.importorskip("torch")
 D, BF = torch.float64, torch.bfloat16
 
 CONV_SHAPES = [(2, 16, 16, 8, 8, 3), (1, 20, 13, 16, 40, 3), (2, 8, 8, 24, 136, 3), (1, 32, 32, 64, 8, 1),
-               (3, 5, 7, 8, 16, 3), (1, 64, 64, 32, 32, 3), (2, 16, 16, 256, 256, 3)]
+               (3, 5, 7, 8, 16, 3), (1, 64, 64, 32, 32, 3), (2, 16, 16, 256, 256, 3), (2, 32, 32, 32, 64, 3),
+               (1, 16, 16, 96, 48, 3)]
 
 
 def note(msg):
