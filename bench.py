@@ -398,6 +398,42 @@ def bench_surrogate(dev, train_sets: int = 1024, steps: int = 3000, held_out: in
     return rec
 
 
+def hbm_calibration(dev, mib: int = 1024, reps: int = 10) -> dict:
+    """What the device sustains for plain streams (torch's own copy and fill
+    kernels on buffers far larger than the 256 MB last-level cache): the
+    context for the roofline fractions, which are taken against the 8 TB/s
+    peak."""
+    import numpy as np
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    flush = torch.empty(2 * n, dtype=torch.float32, device=dev)
+
+    def timed(fn):
+        out = []
+        for rep in range(reps + 1):
+            flush.fill_(1.0)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            if rep:
+                out.append(a.elapsed_time(b) * 1e-3)
+        return float(np.median(out))
+    t_copy = timed(lambda: dst.copy_(src))
+    t_fill = timed(lambda: dst.fill_(2.0))
+    t_read = timed(lambda: src.sum())
+    nb = n * 4
+    out = {"buffer_MiB": mib, "copy_TBps": round(2 * nb / t_copy / 1e12, 3), "write_TBps": round(nb / t_fill / 1e12, 3),
+           "read_TBps": round(nb / t_read / 1e12, 3)}
+    out["copy_frac_of_peak"] = round(out["copy_TBps"] * 1000 / HBM_PEAK_GBS, 4)
+    del src, dst, flush
+    return out
+
+
 def bench_sweeps(dev) -> dict:
     """Parameter and quality sweeps (Table 1's grid of sample counts x
     iterations; radius, background density and raster size with quality,
@@ -465,7 +501,8 @@ def main():
     capi.lib()
 
     if args.only_inim:
-        print(json.dumps({"inim_8192_all_planes": bench_inim(dev)}), flush=True)
+        print(json.dumps({"inim_8192_all_planes": bench_inim(dev), "hbm_calibration": hbm_calibration(dev)}),
+              flush=True)
         return
     if args.profile_short:
         profile_short(args, dev)
@@ -498,6 +535,7 @@ def main():
     }
     if not args.no_inim:
         rec["inim_8192_all_planes"] = bench_inim(dev)
+        rec["hbm_calibration"] = hbm_calibration(dev)
     if not args.no_splom:
         rec["splom_45_plots"] = bench_splom(dev)
     if not args.no_surrogate:
