@@ -1,5 +1,5 @@
 /*
- * inim_quality.h -- C ABI of the layout quality measures used to judge a
+ * inim_quality.h -- C ABI of the layout quality measures that rate a
  * regularised scatterplot (Sec. 6, numerical tests): the sample counts per
  * 4 x 4-texel bin and the occupied texels behind the regularity measure and
  * overplotting, and the two neighbourhood measures the paper reports against

@@ -11,8 +11,9 @@ net_res < res the network sees a coarser raster than the method (its
 Gaussian radius scaled by net_res / res): the composite map is smooth on the
 scale of the method's Gaussian, a coarse field captures it at a sixteenth
 of the work for res / net_res = 4, and bilinear interpolation of a
-fold-free coarse lattice of convex cells cannot fold between its nodes.  It is trained on fields that the method itself computes, and the
-method remains the judge and the fallback: a prediction whose deformed
+fold-free coarse lattice of convex cells cannot fold between its nodes.
+It is trained on fields that the method itself computes, and the method
+remains the reference and the fallback: a prediction whose deformed
 lattice folds, or that does not make the samples more uniform, is replaced by
 the plain regularisation.
 
