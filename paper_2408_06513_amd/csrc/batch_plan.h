@@ -22,7 +22,6 @@ enum BatchStage : int {
     kBBlurAgg,
     kBScanCol,
     kBScanDiag,
-    kBMarg,
     kBDeform,
     kBAdvect,
     kBUnpermute,
@@ -53,7 +52,6 @@ __host__ __device__ inline unsigned batch_stage_blocks(int s, int N, int64_t n, 
         case kBBlurAgg: return (unsigned)((N / 64) * (N / 16));
         case kBScanCol: return (unsigned)((N + 63) / 64);
         case kBScanDiag: return (unsigned)(((2 * N + 1 + 63) / 64) * 3);
-        case kBMarg: return (unsigned)((6 * N - 1 + 255) / 256);
         case kBDeform: return (unsigned)(((N / 16) * (N / 64) + wpb - 1) / wpb);
     }
     return 0;

@@ -336,7 +336,7 @@ int enqueue_batch(BatchPlan& B, int32_t iters, char* ws, hipStream_t st, bool dr
         if (e == hipSuccess) e = launch_batch_raster(s, T, B.blocks[s], 0, iters, status, st);
     if (e == hipSuccess) e = launch_batch_inim(kBDefect, T, B.blocks[kBDefect], B.a.wpb, B.taps, 0, iters, status, st);
     for (int it = 0; it < iters && e == hipSuccess; ++it) {
-        for (int s : {kBBlurAgg, kBScanCol, kBScanDiag, kBMarg, kBDeform})
+        for (int s : {kBBlurAgg, kBScanCol, kBScanDiag, kBDeform})
             if (e == hipSuccess) e = launch_batch_inim(s, T, B.blocks[s], B.a.wpb, B.taps, it, iters, status, st);
         if (e == hipSuccess) e = launch_batch_raster(kBAdvect, T, B.blocks[kBAdvect], it, iters, status, st);
     }

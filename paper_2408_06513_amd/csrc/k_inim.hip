@@ -747,15 +747,17 @@ __device__ __forceinline__ void deform16_body(const Tin* __restrict__ img, const
         }
     }
 
-    // U and V over the tile's anti-diagonals and diagonals, staged in LDS
+    // U and V over the tile's anti-diagonals and diagonals, evaluated here from
+    // the carries (a few loads each) rather than read from a marginals pass,
+    // and staged in LDS
     constexpr int S = W + H - 1;
     const int u0 = cW + b * H;
     const int v0 = cW - b * H - (H - 1);
     Acc* Uw = reinterpret_cast<Acc*>(smem_raw) + (size_t)wave * 2 * S;
     Acc* Vw = Uw + S;
     for (int k = lane; k < S; k += 64) {
-        Uw[k] = K.U[u0 + k];
-        Vw[k] = K.V[v0 + k + N - 1];
+        Uw[k] = marg_U(g, A, K, u0 + k);
+        Vw[k] = marg_V(g, A, K, v0 + k);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -907,9 +909,12 @@ static hipError_t launch_final_q(const Tin* img, const Geom& g, void* scratch, u
     const dim3 blk(64 * kWavesPerBlock);
     const dim3 grd((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
     const int M = 6 * g.N - 1;
-    launch_kernel((k_inim_marg<Acc>), dim3((M + 255) / 256), dim3(256), 0, st, g, A, K, marg, status);
+    const bool deform16 = field != nullptr && Q == 1 && g.W == 64 && g.H == 16 && g.N >= 64;
+    // the 64 x 16 deformation pass evaluates its own diagonal marginals
+    if (!deform16 || marg != nullptr)
+        launch_kernel((k_inim_marg<Acc>), dim3((M + 255) / 256), dim3(256), 0, st, g, A, K, marg, status);
     const size_t smem = (size_t)kWavesPerBlock * 2 * (g.W + g.H - 1) * sizeof(Acc);
-    if (field != nullptr && Q == 1 && g.W == 64 && g.H == 16 && g.N >= 64) {
+    if (deform16) {
         launch_kernel((k_inim_deform16<Tin, Acc>), grd, blk, smem, st, img, g, A, K, field, t1, d0, status);
     } else if (field != nullptr) {
         launch_kernel((k_inim_final<Q, Tin, Acc, kModeDeform>), grd, blk, smem, st, img, g, A, K, 0u,
@@ -1029,13 +1034,6 @@ __global__ __launch_bounds__(1024) void kb_scan_diag(const BatchTable* __restric
     scan_diag_body<double>(P.g, P.A, P.K, tot, (int)(bid % tx), (int)(bid / tx));
 }
 
-__global__ __launch_bounds__(256) void kb_marg(const BatchTable* __restrict__ T, const int* status) {
-    if (failed(status)) return;
-    int64_t bid, nblk;
-    const BatchPlot& P = batch_locate(T, kBMarg, blockIdx.x, bid, nblk);
-    marg_body<double>(P.g, P.A, P.K, nullptr, (int)bid);
-}
-
 __global__ __launch_bounds__(512) void kb_deform(const BatchTable* __restrict__ T, const int* status) {
     extern __shared__ unsigned char smem_raw[];
     if (failed(status)) return;
@@ -1062,7 +1060,6 @@ hipError_t launch_batch_inim(int stage, const BatchTable* T, unsigned blocks, in
             break;
         case kBScanCol: hipLaunchKernelGGL(kb_scan_col, dim3(blocks), dim3(1024), 0, st, T, status); break;
         case kBScanDiag: hipLaunchKernelGGL(kb_scan_diag, dim3(blocks), dim3(1024), 0, st, T, status); break;
-        case kBMarg: hipLaunchKernelGGL(kb_marg, dim3(blocks), dim3(256), 0, st, T, status); break;
         case kBDeform:
             if (wpb < 1 || wpb > 8) return hipErrorInvalidValue;
             hipLaunchKernelGGL(kb_deform, dim3(blocks), dim3(64 * wpb), (size_t)wpb * 2 * (64 + 16 - 1) * sizeof(double),
