@@ -137,3 +137,26 @@ def test_regularisation_lowers_bin_std_and_overplotting_every_iteration(q, dev):
         note(f"seed {seed}: bin std {np.round(s, 2)} overplotting {np.round(o, 3)}")
         assert all(x > y for x, y in zip(s, s[1:])), s
         assert all(x > y for x, y in zip(o, o[1:])), o
+
+
+def test_neighbourhood_measures_at_the_timed_size_keep_their_invariants(q, dev):
+    """16384 samples, the largest size the benchmark times, in its launch
+    configuration: isometries (identity, the x <-> y reflection) keep every
+    neighbourhood, the identity keeps every pair's order and a mirror in x
+    inverts every x-order while keeping the y-orders."""
+    n = 16384
+    a_np = dg.random_clusters(5, n).astype(np.float32)
+    a = to_dev(a_np, dev)
+    note(f"invariants at n={n}")
+    assert q.trust_penalty(a, a, 7).item() == 0
+    assert q.trust_penalty(a, to_dev(a_np[:, ::-1], dev), 7).item() == 0
+    pairs = n * (n - 1) // 2
+    assert q.ordering_counts(a, a).tolist() == [pairs] * 3
+    mirror = a_np.copy()
+    mirror[:, 0] = 1.0 - mirror[:, 0]
+    # x -> 1 - x reverses every strict x-order (or rounds it to a tie); only
+    # pairs with equal x keep their (zero) sign
+    _, cnt = np.unique(a_np[:, 0], return_counts=True)
+    equal_x = int((cnt * (cnt - 1) // 2).sum())
+    kept = q.ordering_counts(a, to_dev(mirror, dev)).tolist()
+    assert kept == [equal_x, pairs, equal_x]
