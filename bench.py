@@ -40,17 +40,20 @@ HBM_PEAK_GBS = 8000.0
 PAPER_ITERS_PER_S = 8 / 12.63e-3  # Table 1: 8 iterations, 1M points, 1024^2, r = 8, RTX 2060
 
 
-# HBM traffic per launch of the dominant stage's kernel from two rocprofv3
+# HBM traffic per launch of the per-iteration stages' kernels from two rocprofv3
 # --pmc runs of `bench.py --profile-short` (FETCH_SIZE, then WRITE_SIZE; see
 # profiles/pmc_traffic_regularize_1M_1024.md), each scaled by what the same
 # counter reads for a plain 256 MiB device copy in that run (FETCH_SIZE
 # counts half of the bytes read: factor 1.99982; WRITE_SIZE all: factor 1.000).
-# Valid only for the sources they were taken with: SHA-256 over the file that
-# holds the kernel (k_inim.hip) and every header; otherwise traffic is null.
+# Valid only for the sources they were taken with: SHA-256 over the files
+# that hold the kernels (k_inim.hip, k_raster.hip) and every header;
+# otherwise traffic is null.
 TRAFFIC = {
-    "src_sha256": "37fb2748dce9236b6856b38eac0736e6b18536da7d18c5232c6e06dac5c064f0",
-    # k_blur_aggregate: FETCH_SIZE 4037.5 KiB x 1.99982 + WRITE_SIZE 10112.0 KiB x 1.000
-    "smooth_aggregate": 18622744,
+    "src_sha256": "d1fd3b1668f1a7baa28c8b653ccdf8633c10c0e5ee9387f933ad2f560440503e",
+    # k_blur_aggregate: FETCH_SIZE 4075.1 KiB x 1.99982 + WRITE_SIZE 10112.0 KiB x 1.000
+    "smooth_aggregate": 18699742,
+    # k_advect (1M samples): FETCH_SIZE 18645.8 KiB x 1.99982 + WRITE_SIZE 15537.3 KiB x 1.000
+    "advect_splat": 54093357,
 }
 
 
@@ -59,7 +62,8 @@ def kernel_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2408_06513_amd", "csrc")
-    for f in sorted([os.path.join(csrc, "k_inim.hip")] + glob.glob(os.path.join(csrc, "*.h"))):
+    files = [os.path.join(csrc, "k_inim.hip"), os.path.join(csrc, "k_raster.hip")] + glob.glob(os.path.join(csrc, "*.h"))
+    for f in sorted(files):
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())

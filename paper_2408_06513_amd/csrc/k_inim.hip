@@ -183,30 +183,38 @@ __device__ __forceinline__ void blur_aggregate_body(const uint32_t* __restrict__
     const int lane = lane_id(), wave = (int)(threadIdx.x >> 6);
     const int b = by, c = bx;
     const size_t ebase = ((size_t)b * g.T + c) * g.H;
+    const size_t o = (size_t)b * N + ox + lane;
     if (wave == 0) {
-        // column prefixes and the two diagonal sums, row by row; the edge values
-        // of row r are parked in lane r and stored once at the end
-        Acc cp = Acc(0), L = Acc(0), R = Acc(0), eL = Acc(0), eR = Acc(0);
+        // column prefixes and the up-left diagonal sums, row by row; the edge
+        // value of row r is parked in lane r and stored once at the end
+        Acc cp = Acc(0), L = Acc(0), eL = Acc(0);
 #pragma unroll
         for (int r = 0; r < kBY; ++r) {
             cp += (Acc)tile[r][lane];
-            Acc upL = shfl_up1(L), dnR = shfl_down1(R);
+            Acc upL = shfl_up1(L);
             if (lane == 0) upL = Acc(0);
-            if (lane == 63) dnR = Acc(0);
             L = cp + upL;
-            R = cp + dnR;
-            const Acc l63 = bcast(L, 63), r0 = bcast(R, 0);
-            if (lane == r) { eL = l63; eR = r0; }
+            const Acc l63 = bcast(L, 63);
+            if (lane == r) eL = l63;
         }
-        if (lane < kBY) {
-            A.tLedge[ebase + lane] = eL;
-            A.tRedge[ebase + lane] = eR;
-        }
+        if (lane < kBY) A.tLedge[ebase + lane] = eL;
         const Acc incl = wave_inclusive_scan(cp);
-        const size_t o = (size_t)b * N + ox + lane;
         A.colsum[o] = cp;
         A.tcsp[o] = incl;
         A.tLend[o] = L;
+    } else if (wave == 2) {
+        // the same column prefixes and the up-right diagonal sums
+        Acc cp = Acc(0), R = Acc(0), eR = Acc(0);
+#pragma unroll
+        for (int r = 0; r < kBY; ++r) {
+            cp += (Acc)tile[r][lane];
+            Acc dnR = shfl_down1(R);
+            if (lane == 63) dnR = Acc(0);
+            R = cp + dnR;
+            const Acc r0 = bcast(R, 0);
+            if (lane == r) eR = r0;
+        }
+        if (lane < kBY) A.tRedge[ebase + lane] = eR;
         A.tRend[o] = R;
     } else if (wave == 1) {
         // trow(r) = sum over the tile of the band-local column prefix at row r,
