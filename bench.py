@@ -49,11 +49,11 @@ PAPER_ITERS_PER_S = 8 / 12.63e-3  # Table 1: 8 iterations, 1M points, 1024^2, r 
 # that hold the kernels (k_inim.hip, k_raster.hip) and every header;
 # otherwise traffic is null.
 TRAFFIC = {
-    "src_sha256": "d1fd3b1668f1a7baa28c8b653ccdf8633c10c0e5ee9387f933ad2f560440503e",
+    "src_sha256": "e93b296c842525757b58732801ba13160de5d3cc25630e153a04f5e602625913",
     # k_blur_aggregate: FETCH_SIZE 4075.1 KiB x 1.99982 + WRITE_SIZE 10112.0 KiB x 1.000
     "smooth_aggregate": 18699742,
-    # k_advect (1M samples): FETCH_SIZE 18645.8 KiB x 1.99982 + WRITE_SIZE 15537.3 KiB x 1.000
-    "advect_splat": 54093357,
+    # k_advect (1M samples): FETCH_SIZE 18650.5 KiB x 1.99982 + WRITE_SIZE 15537.3 KiB x 1.000
+    "advect_splat": 54102982,
 }
 
 

@@ -732,6 +732,13 @@ __device__ __forceinline__ void deform16_body(const Tin* __restrict__ img, const
         v[r] = src[(size_t)r * N];
         d1[r] = t1p[(size_t)r * N];
     }
+    // carries into the tile's columns (loaded together with the rows)
+    const Acc Ctot = K.ain[(size_t)g.B * N + (N - 1)];
+    const Acc X = K.ain[(size_t)g.B * N + col];
+    Acc cp = K.cpin[(size_t)b * N + col];
+    Acc L = Linb[col], R = Rinb[col];
+    Acc Lleft = (c > 0) ? Linb[cW - 1] : Acc(0);
+    Acc Rright = (cW + W < N) ? Rinb[cW + W] : Acc(0);
 
     // per-row boundary values (lane r holds row r)
     Acc lb = Acc(0), rb = Acc(0), ac = Acc(0), yv = Acc(0);
@@ -770,12 +777,6 @@ __device__ __forceinline__ void deform16_body(const Tin* __restrict__ img, const
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 
-    const Acc Ctot = K.ain[(size_t)g.B * N + (N - 1)];
-    const Acc X = K.ain[(size_t)g.B * N + col];
-    Acc cp = K.cpin[(size_t)b * N + col];
-    Acc L = Linb[col], R = Rinb[col];
-    Acc Lleft = (c > 0) ? Linb[cW - 1] : Acc(0);
-    Acc Rright = (cW + W < N) ? Rinb[cW + W] : Acc(0);
     const MapScale ms = map_scale(to_f64(Ctot), N, d0);
 
 #pragma unroll
