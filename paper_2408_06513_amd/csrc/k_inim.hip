@@ -268,12 +268,23 @@ __device__ __forceinline__ void scan_col_body(const Geom& g, const Agg<Acc>& A, 
     const int c = (bx * 64) / g.W;  // the block's 64 columns lie in one tile
     const size_t N = (size_t)g.N;
     const int b0 = wave * P;
-    for (int b = threadIdx.x; b < g.B; b += blockDim.x) {
+    // left[b]: the totals of the tiles left of c in band b, one (band, tile)
+    // pair per thread (tiles q, q + 16, ... in 16-lane row slot q), summed
+    // over each 16-lane row by row shifts; the loop is uniform over the block,
+    // so every lane takes part in the lane moves
+    for (int base = 0; base < g.B * 16; base += blockDim.x) {
+        const int e = base + (int)threadIdx.x;
+        const int b = e >> 4, q = e & 15;
         Acc t = Acc(0);
-        const Acc* tr = A.trow + (size_t)b * g.T * g.H + (g.H - 1);
-#pragma unroll 8
-        for (int cc = 0; cc < c; ++cc) t += tr[(size_t)cc * g.H];
-        left[b] = t;
+        if (b < g.B) {
+            const Acc* tr = A.trow + (size_t)b * g.T * g.H + (g.H - 1);
+            for (int cc = q; cc < c; cc += 16) t += tr[(size_t)cc * g.H];
+        }
+        t += dpp<kDppRowShr1>(t);
+        t += dpp<kDppRowShr2>(t);
+        t += dpp<kDppRowShr4>(t);
+        t += dpp<kDppRowShr8>(t);
+        if (q == 15 && b < g.B) left[b] = t;
     }
     __syncthreads();
 
