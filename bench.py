@@ -50,11 +50,11 @@ PAPER_ITERS_PER_S = 8 / 12.63e-3  # Table 1: 8 iterations, 1M points, 1024^2, r 
 # that hold the kernels (k_inim.hip, k_raster.hip) and every header;
 # otherwise traffic is null.
 TRAFFIC = {
-    "src_sha256": "dbdfb6afe637398076ff320c658993df27a9e090f01819caac72d03a6cd2737e",
+    "src_sha256": "ff008c5df0401779207c0f47fa725c8c32372190b976148172af69a05e4468cc",
     # k_blur_aggregate: FETCH_SIZE 4077.1 KiB x 1.99982 + WRITE_SIZE 10112.0 KiB x 1.000
     "smooth_aggregate": 18703837,
-    # k_advect (1M samples): FETCH_SIZE 18646.1 KiB x 1.99982 + WRITE_SIZE 15537.7 KiB x 1.000
-    "advect_splat": 54094381,
+    # k_advect (1M samples): FETCH_SIZE 18646.4 KiB x 1.99982 + WRITE_SIZE 15537.0 KiB x 1.000
+    "advect_splat": 54094278,
 }
 
 

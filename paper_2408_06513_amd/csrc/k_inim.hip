@@ -267,7 +267,6 @@ __device__ __forceinline__ void scan_col_body(const Geom& g, const Agg<Acc>& A, 
     const int ii = valid ? i : 0;
     const int c = (bx * 64) / g.W;  // the block's 64 columns lie in one tile
     const size_t N = (size_t)g.N;
-    const int b0 = wave * P;
     // left[b]: the totals of the tiles left of c in band b, one (band, tile)
     // pair per thread (tiles q, q + 16, ... in 16-lane row slot q), summed
     // over each 16-lane row by row shifts; the loop is uniform over the block,
@@ -288,40 +287,103 @@ __device__ __forceinline__ void scan_col_body(const Geom& g, const Agg<Acc>& A, 
     }
     __syncthreads();
 
-    Acc cs[kScanMaxP], da[kScanMaxP];
+    if constexpr (sizeof(Acc) <= 8) {
+        // all P bands of the wave at once: wave w holds bands [w P, w P + P)
+        const int b0 = wave * P;
+        Acc cs[kScanMaxP], da[kScanMaxP];
 #pragma unroll
-    for (int k = 0; k < kScanMaxP; ++k) {
-        cs[k] = Acc(0);
-        da[k] = Acc(0);
-        const int b = b0 + k;
-        if (k < P && b < g.B && valid) {
-            cs[k] = A.colsum[(size_t)b * N + ii];
-            da[k] = A.tcsp[(size_t)b * N + ii] + left[b];
+        for (int k = 0; k < kScanMaxP; ++k) {
+            cs[k] = Acc(0);
+            da[k] = Acc(0);
+            const int b = b0 + k;
+            if (k < P && b < g.B && valid) {
+                cs[k] = A.colsum[(size_t)b * N + ii];
+                da[k] = A.tcsp[(size_t)b * N + ii] + left[b];
+            }
         }
-    }
-    Acc rc = Acc(0), ra = Acc(0);
+        Acc rc = Acc(0), ra = Acc(0);
 #pragma unroll
-    for (int k = 0; k < kScanMaxP; ++k) { rc += cs[k]; ra += da[k]; }
-    tot[(wave * 2 + 0) * 64 + lane] = rc;
-    tot[(wave * 2 + 1) * 64 + lane] = ra;
-    __syncthreads();
+        for (int k = 0; k < kScanMaxP; ++k) { rc += cs[k]; ra += da[k]; }
+        tot[(wave * 2 + 0) * 64 + lane] = rc;
+        tot[(wave * 2 + 1) * 64 + lane] = ra;
+        __syncthreads();
+        Acc oc = Acc(0), oa = Acc(0);
+        for (int w = 0; w < wave; ++w) {
+            oc += tot[(w * 2 + 0) * 64 + lane];
+            oa += tot[(w * 2 + 1) * 64 + lane];
+        }
+        if (!valid) return;
+#pragma unroll
+        for (int k = 0; k < kScanMaxP; ++k) {
+            const int b = b0 + k;
+            if (k < P && b < g.B) {
+                K.cpin[(size_t)b * N + ii] = oc;
+                K.ain[(size_t)b * N + ii] = oa;
+                oc += cs[k];
+                oa += da[k];
+            }
+        }
+        if (wave == nw - 1) {
+            K.cpin[(size_t)g.B * N + ii] = oc;
+            K.ain[(size_t)g.B * N + ii] = oa;
+        }
+        return;
+    }
+    // 128-bit accumulators: the bands in rounds of nw * pc, 8 per wave and
+    // round so that the terms stay in registers; in round q wave w holds the
+    // pc bands from (q nw + w) pc, after the running totals of the earlier
+    // rounds (exact integers: the grouping does not change the sums).
+    constexpr int PC = 8;
+    const int pc = P < PC ? P : PC, rounds = (P + pc - 1) / pc;
+    Acc carry_c = Acc(0), carry_a = Acc(0);  // totals of the earlier rounds
     Acc oc = Acc(0), oa = Acc(0);
-    for (int w = 0; w < wave; ++w) {
-        oc += tot[(w * 2 + 0) * 64 + lane];
-        oa += tot[(w * 2 + 1) * 64 + lane];
-    }
-    if (!valid) return;
+    for (int q = 0; q < rounds; ++q) {
+        const int b0 = (q * nw + wave) * pc;
+        Acc cs[PC], da[PC];
 #pragma unroll
-    for (int k = 0; k < kScanMaxP; ++k) {
-        const int b = b0 + k;
-        if (k < P && b < g.B) {
-            K.cpin[(size_t)b * N + ii] = oc;
-            K.ain[(size_t)b * N + ii] = oa;
-            oc += cs[k];
-            oa += da[k];
+        for (int k = 0; k < PC; ++k) {
+            cs[k] = Acc(0);
+            da[k] = Acc(0);
+            const int b = b0 + k;
+            if (k < pc && b < g.B && valid) {
+                cs[k] = A.colsum[(size_t)b * N + ii];
+                da[k] = A.tcsp[(size_t)b * N + ii] + left[b];
+            }
+        }
+        Acc rc = Acc(0), ra = Acc(0);
+#pragma unroll
+        for (int k = 0; k < PC; ++k) { rc += cs[k]; ra += da[k]; }
+        tot[(wave * 2 + 0) * 64 + lane] = rc;
+        tot[(wave * 2 + 1) * 64 + lane] = ra;
+        __syncthreads();
+        oc = carry_c;
+        oa = carry_a;
+        for (int w = 0; w < wave; ++w) {
+            oc += tot[(w * 2 + 0) * 64 + lane];
+            oa += tot[(w * 2 + 1) * 64 + lane];
+        }
+        if (rounds > 1) {
+            for (int w = 0; w < nw; ++w) {
+                carry_c += tot[(w * 2 + 0) * 64 + lane];
+                carry_a += tot[(w * 2 + 1) * 64 + lane];
+            }
+            __syncthreads();  // tot is rewritten by the next round
+        }
+#pragma unroll
+        for (int k = 0; k < PC; ++k) {
+            const int b = b0 + k;
+            if (k < pc && b < g.B) {
+                if (valid) {
+                    K.cpin[(size_t)b * N + ii] = oc;
+                    K.ain[(size_t)b * N + ii] = oa;
+                }
+                oc += cs[k];
+                oa += da[k];
+            }
         }
     }
-    if (wave == nw - 1) {
+    // the last wave's running sums after the last round are the column totals
+    if (valid && wave == nw - 1) {
         K.cpin[(size_t)g.B * N + ii] = oc;
         K.ain[(size_t)g.B * N + ii] = oa;
     }
@@ -370,23 +432,30 @@ __device__ __forceinline__ void scan_diag_body(const Geom& g, const Agg<Acc>& A,
     }
     const int lane = lane_id();
     const int wave = (int)(threadIdx.x >> 6);
-    const int P = scan_per_wave(g.B);
+    const int nw = scan_waves(g.B), P = scan_per_wave(g.B);
     const int t = bx * 64 + lane;
     const bool left_chain = by == 0;
     const bool tval = t <= 2 * N;
     const int s = left_chain ? t - N : t;
-    const int b0 = wave * P;
     Acc* out = left_chain ? K.Lin : K.Rin;
     if (wave == 0 && tval && t < N) out[t] = Acc(0);
 
-    Acc term[kScanMaxP];
-    int col[kScanMaxP];
+    // 128-bit accumulators: bands in rounds as in the column scan (8 per wave
+    // and round); the others take all P at once (wave w: bands [w P, w P + P))
+    constexpr int PC = sizeof(Acc) > 8 ? 8 : kScanMaxP;
+    const int pc = sizeof(Acc) > 8 && P > PC ? PC : P;
+    const int rounds = sizeof(Acc) > 8 ? (P + pc - 1) / pc : 1;
+    Acc carry = Acc(0);  // the chain's sum over the earlier rounds
+    for (int q = 0; q < rounds; ++q) {
+    const int b0 = (q * nw + wave) * pc;
+    Acc term[PC];
+    int col[PC];
 #pragma unroll
-    for (int k = 0; k < kScanMaxP; ++k) {
+    for (int k = 0; k < PC; ++k) {
         term[k] = Acc(0);
         col[k] = -1;
         const int b = b0 + k;
-        if (!(tval && k < P && b < g.B)) continue;
+        if (!(tval && k < pc && b < g.B)) continue;
         const int i = left_chain ? s + (b + 1) * H : s - (b + 1) * H;
         if (i < 0 || i >= N) continue;
         col[k] = i;
@@ -407,15 +476,20 @@ __device__ __forceinline__ void scan_diag_body(const Geom& g, const Agg<Acc>& A,
     }
     Acc run = Acc(0);
 #pragma unroll
-    for (int k = 0; k < kScanMaxP; ++k) run += term[k];
+    for (int k = 0; k < PC; ++k) run += term[k];
     tot[wave * 64 + lane] = run;
     __syncthreads();
-    Acc off = Acc(0);
+    Acc off = carry;
     for (int w = 0; w < wave; ++w) off += tot[w * 64 + lane];
+    if (rounds > 1) {
+        for (int w = 0; w < nw; ++w) carry += tot[w * 64 + lane];
+        __syncthreads();  // tot is rewritten by the next round
+    }
 #pragma unroll
-    for (int k = 0; k < kScanMaxP; ++k) {
+    for (int k = 0; k < PC; ++k) {
         off += term[k];
         if (col[k] >= 0) out[(size_t)(b0 + k + 1) * N + col[k]] = off;
+    }
     }
 }
 
