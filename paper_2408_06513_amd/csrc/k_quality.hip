@@ -173,6 +173,106 @@ __global__ __launch_bounds__(kThreads) void k_trust(const float2* __restrict__ a
     if (threadIdx.x == 0 && pen) atomicAdd(penalty, pen);
 }
 
+// k <= 16: one pass per space.  Output space: every wave keeps the k nearest
+// of its share of the samples as a sorted list with one entry per lane
+// (lanes k..63 hold entries pushed past the k-th), updated only by the
+// candidates that beat its current k-th entry; the four lists are merged by
+// rank in LDS.  Input space: one pass counts, for each of the k neighbours,
+// the samples before it in the neighbour order; only samples before the last
+// of the k can count.  Same order, ties and sums as k_trust.
+constexpr int kTrustFastK = 16;
+
+__global__ __launch_bounds__(kThreads) void k_trust_fast(const float2* __restrict__ a, const float2* __restrict__ b,
+                                                         int n, int k, u64* __restrict__ penalty) {
+    __shared__ double cand_d[kWaves][kTrustFastK];
+    __shared__ int cand_j[kWaves][kTrustFastK];
+    __shared__ double top_d[kTrustFastK];  // input-space distance of the output neighbours
+    __shared__ int top_j[kTrustFastK];
+    __shared__ int below[kTrustFastK];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    u64 pen = 0;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const float2 ai = a[i], bi = b[i];
+        double Ld = INFINITY, thr_d = INFINITY;
+        int Lj = INT_MAX, thr_j = INT_MAX;  // the lane's list entry; the wave's k-th entry
+        for (int base = wave * kWave; base < n; base += kThreads) {
+            const int j = base + lane;
+            double d = INFINITY;
+            int jj = INT_MAX;
+            if (j < n && j != i) {
+                d = sq_dist(bi, b[j]);
+                jj = j;
+            }
+            u64 m = __ballot(before(d, jj, thr_d, thr_j));
+            while (m) {
+                const int src = __ffsll((long long)m) - 1;
+                m &= m - 1;
+                const double cd = __shfl(d, src, kWave);
+                const int cj = __shfl(jj, src, kWave);
+                if (!before(cd, cj, thr_d, thr_j)) continue;  // the k-th entry moved past it
+                const double ud = __shfl_up(Ld, 1, kWave);
+                const int uj = __shfl_up(Lj, 1, kWave);
+                if (before(cd, cj, Ld, Lj)) {
+                    if (lane == 0 || before(ud, uj, cd, cj)) {
+                        Ld = cd;  // the candidate's place
+                        Lj = cj;
+                    } else {
+                        Ld = ud;  // entries after it move one lane on
+                        Lj = uj;
+                    }
+                }
+                thr_d = __shfl(Ld, k - 1, kWave);
+                thr_j = __shfl(Lj, k - 1, kWave);
+            }
+        }
+        if (lane < k) {
+            cand_d[wave][lane] = Ld;
+            cand_j[wave][lane] = Lj;
+        }
+        if (threadIdx.x < kTrustFastK) below[threadIdx.x] = 0;
+        __syncthreads();
+        // the k nearest of the (distinct) candidates: their rank among them
+        if (threadIdx.x < kWaves * kTrustFastK) {
+            const int w = threadIdx.x / kTrustFastK, t = threadIdx.x % kTrustFastK;
+            if (t < k && cand_j[w][t] < n) {
+                const double d = cand_d[w][t];
+                const int j = cand_j[w][t];
+                int r = 0;
+                for (int w2 = 0; w2 < kWaves; ++w2)
+                    for (int t2 = 0; t2 < k; ++t2)
+                        r += cand_j[w2][t2] < n && before(cand_d[w2][t2], cand_j[w2][t2], d, j);
+                if (r < k) {
+                    top_j[r] = j;
+                    top_d[r] = sq_dist(ai, a[j]);
+                }
+            }
+        }
+        __syncthreads();
+        double last_d = -1.0;
+        int last_j = -1;
+        for (int t = 0; t < k; ++t)
+            if (before(last_d, last_j, top_d[t], top_j[t])) {
+                last_d = top_d[t];
+                last_j = top_j[t];
+            }
+        for (int m = threadIdx.x; m < n; m += kThreads) {
+            if (m == i) continue;
+            const double d = sq_dist(ai, a[m]);
+            if (!before(d, m, last_d, last_j)) continue;
+            for (int t = 0; t < k; ++t)
+                if (before(d, m, top_d[t], top_j[t])) atomicAdd(&below[t], 1);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int t = 0; t < k; ++t) {
+                const int rank = 1 + below[t];
+                if (rank > k) pen += (u64)(rank - k);
+            }
+        __syncthreads();  // the shared lists are rewritten for the next sample
+    }
+    if (threadIdx.x == 0 && pen) atomicAdd(penalty, pen);
+}
+
 // ------------------------------------------------------------------ host
 thread_local std::string g_quality_error;
 
@@ -225,8 +325,12 @@ int inim_quality_trust(const float* a, const float* b, int32_t n, int32_t k, uin
                        hipStream_t stream) {
     if (!a || !b || !penalty) return qfail(INIM_EINVAL, "a, b and penalty must not be NULL");
     if (k < 1 || 2 * (int64_t)k >= n) return qfail(INIM_EINVAL, "need 1 <= k and 2k < n (k = %d, n = %d)", k, n);
-    hipLaunchKernelGGL(k_trust, dim3(capped(n, 1 << 20)), dim3(kThreads), 0, stream, (const float2*)a,
-                       (const float2*)b, n, k, (u64*)penalty);
+    if (k <= kTrustFastK)
+        hipLaunchKernelGGL(k_trust_fast, dim3(capped(n, 1 << 20)), dim3(kThreads), 0, stream, (const float2*)a,
+                           (const float2*)b, n, k, (u64*)penalty);
+    else
+        hipLaunchKernelGGL(k_trust, dim3(capped(n, 1 << 20)), dim3(kThreads), 0, stream, (const float2*)a,
+                           (const float2*)b, n, k, (u64*)penalty);
     return launched("trustworthiness");
 }
 

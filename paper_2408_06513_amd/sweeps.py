@@ -175,9 +175,10 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, vector (non-matrix) FP64
 def kernel_times(dev, sizes=(4096, 16384), k: int = 7, res: int = 1024, reps: int = 10) -> dict:
     """Event times of the quality kernels on samples of a regularised 1M-sample
     layout.  The neighbourhood kernels are bound by FP64 vector arithmetic:
-    the trustworthiness pass evaluates n (n - 1) 2k squared distances of 5
-    FP64 operations each (2 differences, 2 products, 1 sum); orthogonal
-    ordering compares n (n - 1) / 2 pairs."""
+    trustworthiness needs every sample's squared distance to every other in
+    both layouts, 2 n (n - 1) distances of 5 FP64 operations each (2
+    differences, 2 products, 1 sum); orthogonal ordering compares
+    n (n - 1) / 2 pairs."""
     xy0 = _to(datagen.random_clusters(1, 1_000_000), dev)
     xy = xy0.clone()
     capi.regularize(xy, res, 8)
@@ -190,7 +191,7 @@ def kernel_times(dev, sizes=(4096, 16384), k: int = 7, res: int = 1024, reps: in
         a, b = xy0[:n].contiguous(), xy[:n].contiguous()
         t_ord = _median_ms(lambda: quality.ordering_counts(a, b, c3), c3.zero_, reps)
         t_tr = _median_ms(lambda: quality.trust_penalty(a, b, k, c1), c1.zero_, reps)
-        flops = 5.0 * n * (n - 1) * 2 * k
+        flops = 5.0 * n * (n - 1) * 2
         tf = flops / t_tr / 1e9
         out[f"n{n}"] = {"ordering_ms": round(t_ord, 4), "ordering_Gpairs_per_s": round(n * (n - 1) / 2 / t_ord / 1e6, 1),
                         "trust_ms": round(t_tr, 4), "trust_fp64_TFLOPs": round(tf, 2),
