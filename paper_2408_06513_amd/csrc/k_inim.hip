@@ -790,8 +790,11 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
 // values are loaded up front and the row loop is fully unrolled without
 // branches, so the per-texel map of row r overlaps the scans of row r+1.
 // One wave per tile: `tile` is the wave's tile, `wave` its slot in the block's
-// LDS (2 (W + H - 1) accumulators per wave).
-template <typename Tin, typename Acc>
+// LDS (2 (W + H - 1) accumulators per wave).  R0, R1: the wave maps rows
+// [R0, R1) of the tile; rows before R0 are only replayed for the column
+// prefix and the diagonal chains (the same operations in the same order, so
+// splitting a tile over waves gives the same field).
+template <typename Tin, typename Acc, int R0 = 0, int R1 = 16>
 __device__ __forceinline__ void deform16_body(const Tin* __restrict__ img, const Geom& g, const Agg<Acc>& A,
                                               const Carry<Acc>& K, float2* __restrict__ field,
                                               const float2* __restrict__ t1, double d0, unsigned char* smem_raw,
@@ -813,9 +816,9 @@ __device__ __forceinline__ void deform16_body(const Tin* __restrict__ img, const
     const Tin* src = img + (size_t)b * H * N + col;
     const float2* t1p = t1 + (size_t)b * H * N + col;
 #pragma unroll
-    for (int r = 0; r < H; ++r) {
+    for (int r = 0; r < R1; ++r) {
         v[r] = src[(size_t)r * N];
-        d1[r] = t1p[(size_t)r * N];
+        if (r >= R0) d1[r] = t1p[(size_t)r * N];
     }
     // carries into the tile's columns (loaded together with the rows)
     const Acc Ctot = K.ain[(size_t)g.B * N + (N - 1)];
@@ -865,9 +868,19 @@ __device__ __forceinline__ void deform16_body(const Tin* __restrict__ img, const
     const MapScale ms = map_scale(to_f64(Ctot), N, d0);
 
 #pragma unroll
-    for (int r = 0; r < H; ++r) {
+    for (int r = 0; r < R1; ++r) {
         const int j = b * H + r;
         cp += to_acc<Acc, Tin>(v[r]);
+        if (r < R0) {  // replayed row: the chains only
+            Acc upL = shfl_up1(L), dnR = shfl_down1(R);
+            if (lane == 0) upL = Lleft;
+            if (lane == 63) dnR = Rright;
+            L = cp + upL;
+            R = cp + dnR;
+            Lleft = bcast(lb, r);
+            Rright = bcast(rb, r);
+            continue;
+        }
         const Acc incl = wave_inclusive_scan(cp);
         const Acc al = bcast(ac, r) + incl;
         Acc upL = shfl_up1(L), dnR = shfl_down1(R);
@@ -896,6 +909,22 @@ __global__ __launch_bounds__(256) void k_inim_deform16(const Tin* __restrict__ i
     if (failed(status)) return;
     const int wave = (int)(threadIdx.x >> 6);
     deform16_body<Tin, Acc>(img, g, A, K, field, t1, d0, smem_raw, blockIdx.x * kWavesPerBlock + wave, wave);
+}
+
+// Two waves per tile: the even wave maps rows 0-7, the odd one replays them
+// and maps rows 8-15 (twice the waves of k_inim_deform16 for the same field).
+template <typename Tin, typename Acc>
+__global__ __launch_bounds__(256) void k_inim_deform16x2(const Tin* __restrict__ img, Geom g, Agg<Acc> A,
+                                                         Carry<Acc> K, float2* __restrict__ field,
+                                                         const float2* __restrict__ t1, double d0, const int* status) {
+    extern __shared__ unsigned char smem_raw[];
+    if (failed(status)) return;
+    const int wave = (int)(threadIdx.x >> 6);
+    const int tile = (blockIdx.x * kWavesPerBlock + wave) >> 1;
+    if (wave & 1)
+        deform16_body<Tin, Acc, 8, 16>(img, g, A, K, field, t1, d0, smem_raw, tile, wave);
+    else
+        deform16_body<Tin, Acc, 0, 8>(img, g, A, K, field, t1, d0, smem_raw, tile, wave);
 }
 
 // ------------------------------------------------------------------ defect field
@@ -1009,7 +1038,8 @@ static hipError_t launch_final_q(const Tin* img, const Geom& g, void* scratch, u
         launch_kernel((k_inim_marg<Acc>), dim3((M + 255) / 256), dim3(256), 0, st, g, A, K, marg, status);
     const size_t smem = (size_t)kWavesPerBlock * 2 * (g.W + g.H - 1) * sizeof(Acc);
     if (deform16) {
-        launch_kernel((k_inim_deform16<Tin, Acc>), grd, blk, smem, st, img, g, A, K, field, t1, d0, status);
+        const dim3 grd2((2 * tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+        launch_kernel((k_inim_deform16x2<Tin, Acc>), grd2, blk, smem, st, img, g, A, K, field, t1, d0, status);
     } else if (field != nullptr) {
         launch_kernel((k_inim_final<Q, Tin, Acc, kModeDeform>), grd, blk, smem, st, img, g, A, K, 0u,
                            (Tin*)nullptr, field, t1, d0, status);
