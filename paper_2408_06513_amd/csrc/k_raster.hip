@@ -98,17 +98,41 @@ __device__ __forceinline__ float clamp01(double v) { return (float)(v < 0.0 ? 0.
 // the wave are sorted (bitonic network over lane shuffles) and only the first
 // lane of every run of equal keys issues one atomic with the run length.  With
 // samples in texel order most lanes of a wave share a few texels.
+// The key of lane (lane ^ J): DPP quad permutes for J = 1, 2, the swizzle
+// xor mode (within 32 lanes) for J = 4, 8, 16, a permute for J = 32.
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+    if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+    else if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+    else if constexpr (J <= 16) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (J << 10));
+    else return (uint32_t)__shfl_xor((int)v, J, 64);
+}
+
+template <int K, int J>
+__device__ __forceinline__ uint32_t bitonic_step(uint32_t key, int lane) {
+    const uint32_t o = lane_xor<J>(key);
+    const bool keep_min = ((lane & K) == 0) == ((lane & J) == 0);
+    return keep_min ? min(key, o) : max(key, o);
+}
+
+template <int K>
+__device__ __forceinline__ uint32_t bitonic_merge(uint32_t key, int lane) {
+    if constexpr (K >= 64) key = bitonic_step<K, 32>(key, lane);
+    if constexpr (K >= 32) key = bitonic_step<K, 16>(key, lane);
+    if constexpr (K >= 16) key = bitonic_step<K, 8>(key, lane);
+    if constexpr (K >= 8) key = bitonic_step<K, 4>(key, lane);
+    if constexpr (K >= 4) key = bitonic_step<K, 2>(key, lane);
+    return bitonic_step<K, 1>(key, lane);
+}
+
 __device__ __forceinline__ void wave_count(uint32_t* __restrict__ counts, uint32_t key) {
     const int lane = lane_id();
-#pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint32_t o = (uint32_t)__shfl_xor((int)key, j, 64);
-            const bool keep_min = ((lane & k) == 0) == ((lane & j) == 0);
-            key = keep_min ? min(key, o) : max(key, o);
-        }
-    }
+    key = bitonic_merge<2>(key, lane);
+    key = bitonic_merge<4>(key, lane);
+    key = bitonic_merge<8>(key, lane);
+    key = bitonic_merge<16>(key, lane);
+    key = bitonic_merge<32>(key, lane);
+    key = bitonic_merge<64>(key, lane);
     const uint32_t prev = (uint32_t)__shfl_up((int)key, 1, 64);
     const bool head = lane == 0 || prev != key;
     const unsigned long long heads = __ballot(head);
