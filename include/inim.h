@@ -96,8 +96,8 @@ const char* inim_last_error(void);
 /*
  * Workspace for inim_rasterize, inim_advect and inim_regularize at this size:
  * status word, two count rasters, density raster, deformation field, the
- * integral-image carries and a texel-ordered copy of the samples (16 bytes
- * per sample).  `p` may be NULL (defaults).  EINVAL on bad sizes.
+ * integral-image carries, a texel-ordered copy of the samples and the
+ * buffers that sort them (24 bytes per sample).  `p` may be NULL (defaults).  EINVAL on bad sizes.
  */
 int inim_workspace_size(int32_t res, int64_t n, const inim_params* p, size_t* bytes);
 

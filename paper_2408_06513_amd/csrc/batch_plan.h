@@ -70,7 +70,6 @@ struct BatchPlot {
     float2* defect;  // t(p; 1), shared by the plots of one raster size
     bool defect_owner;
     float2* sxy;
-    uint32_t* perm;
     uint32_t* rank;
     uint32_t* partial;
     Agg<double> A;

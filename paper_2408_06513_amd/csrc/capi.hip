@@ -123,7 +123,7 @@ struct ClockScope {
 // The whole call (Sec. 4.3) on the caller's stream.  The samples are first
 // sorted by texel into the workspace (so that the splats of a wave mostly hit
 // the same few texels and the field gathers are local), the iterations run on
-// that copy, and the results are scattered back to the caller's order.
+// that copy, and the results are moved back to the caller's order.
 // Iteration k reads the count raster counts[k % 2]; its advection splats the
 // moved samples into counts[(k+1) % 2], which the smoothing of iteration k has
 // zeroed.
@@ -135,20 +135,21 @@ int enqueue_regularize(float* xy, int64_t n, float* probe, int64_t m, int32_t re
     float* density = reinterpret_cast<float*>(ws + L.density);
     float2* field = reinterpret_cast<float2*>(ws + L.field);
     float2* pts = reinterpret_cast<float2*>(ws + L.sxy);
-    uint32_t* perm = reinterpret_cast<uint32_t*>(ws + L.perm);
+    uint32_t* map = reinterpret_cast<uint32_t*>(ws + L.rank);
     void* scratch = ws + L.scratch;
     const size_t NN = (size_t)res * res;
     const bool fused = L.f32 && blur_aggregate_fits(L.g);
+    float2* defect = reinterpret_cast<float2*>(ws + L.defect);
     hipError_t e;
     if (ev) (void)hipEventRecord(ev->pre[0], st);
-    e = launch_sort_by_texel(reinterpret_cast<const float2*>(xy), n, res, counts[0],
-                             reinterpret_cast<uint32_t*>(ws + L.rank), counts[1],
-                             reinterpret_cast<uint32_t*>(ws + L.partial), pts, perm, status, st);
+    // the density raster is free until the first smoothing: row totals
+    e = launch_sort_by_texel(reinterpret_cast<const float2*>(xy), n, res, counts[0], map, counts[1],
+                             reinterpret_cast<uint32_t*>(ws + L.partial), reinterpret_cast<uint32_t*>(density), pts,
+                             reinterpret_cast<float2*>(ws + L.stage), reinterpret_cast<uint32_t*>(ws + L.idx), defect,
+                             status, st);
     if (e != hipSuccess) return hip_fail(e, "sort by texel");
     if (m > 0 && (e = launch_validate(reinterpret_cast<const float2*>(probe), m, status, st)) != hipSuccess)
         return hip_fail(e, "validate probes");
-    float2* defect = reinterpret_cast<float2*>(ws + L.defect);
-    if ((e = launch_defect_field(res, defect, st)) != hipSuccess) return hip_fail(e, "defect field");
     if (ev) {
         (void)hipEventRecord(ev->pre[1], st);
         if (hipEventSynchronize(ev->pre[1]) != hipSuccess) return fail(INIM_EHIP, "hipEventSynchronize failed");
@@ -206,7 +207,7 @@ int enqueue_regularize(float* xy, int64_t n, float* probe, int64_t m, int32_t re
         }
     }
     if (ev) (void)hipEventRecord(ev->pre[0], st);
-    if ((e = launch_unpermute(pts, perm, n, reinterpret_cast<float2*>(xy), status, st)) != hipSuccess)
+    if ((e = launch_unpermute(pts, map, n, res, reinterpret_cast<float2*>(xy), status, st)) != hipSuccess)
         return hip_fail(e, "unpermute");
     if (ev) {
         (void)hipEventRecord(ev->pre[1], st);

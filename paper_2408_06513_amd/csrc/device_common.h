@@ -316,6 +316,17 @@ __device__ __forceinline__ void map_sum(const Planes8& P, double x, double y, do
     sy = P.a * q1y + P.b * q2y + P.g * q3y + P.d * q4y + P.at + (P.bt + P.dt) * y;
 }
 
+// t(p; 1), the map of the constant raster, at the centre of texel (i, j): the
+// defect that the deformation removes (Sec. 4.2), as floats.
+__device__ __forceinline__ float2 defect_texel(int i, int j, int N) {
+    const double invN = 1.0 / (double)N;
+    const double x = ((double)i + 0.5) * invN, y = ((double)j + 0.5) * invN;
+    double sx, sy;
+    map_sum(ones_planes(i, j, N), x, y, sx, sy);
+    const double s = 1.0 / (2.0 * (double)N * (double)N);
+    return make_float2((float)(sx * s), (float)(sy * s));
+}
+
 // Scale factors of the deformation: 1 / (2 C_d) with C_d = C_r + d0 res^2 the
 // total of d = d_r + d0, and 1 / (2 res^2) for the constant raster.
 // omk = 1 - d0 res^2 / C_d, the weight of the defect once the constant part of

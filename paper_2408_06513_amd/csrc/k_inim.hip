@@ -935,12 +935,7 @@ __device__ __forceinline__ void defect_body(int N, float2* __restrict__ t1, int6
     const size_t NN = (size_t)N * N;
     if (k >= NN) return;
     const int j = (int)(k / N), i = (int)(k - (size_t)j * N);
-    const double invN = 1.0 / (double)N;
-    const double x = ((double)i + 0.5) * invN, y = ((double)j + 0.5) * invN;
-    double sx, sy;
-    map_sum(ones_planes(i, j, N), x, y, sx, sy);
-    const double s = 1.0 / (2.0 * (double)NN);
-    t1[k] = make_float2((float)(sx * s), (float)(sy * s));
+    t1[k] = defect_texel(i, j, N);
 }
 
 __global__ __launch_bounds__(256) void k_defect_field(int N, float2* __restrict__ t1) { defect_body(N, t1, blockIdx.x); }
@@ -1096,7 +1091,6 @@ __global__ __launch_bounds__(64) void kb_init(BatchArgs a, BatchTable* __restric
         P.defect = reinterpret_cast<float2*>(a.ws + batch_plot_offset(owner, a.in, a.radius) + L.defect);
         P.defect_owner = owner == k;
         P.sxy = reinterpret_cast<float2*>(base + L.sxy);
-        P.perm = reinterpret_cast<uint32_t*>(base + L.perm);
         P.rank = reinterpret_cast<uint32_t*>(base + L.rank);
         P.partial = reinterpret_cast<uint32_t*>(base + L.partial);
         carve<double>(L.g, base + L.scratch, P.A, P.K);

@@ -94,6 +94,20 @@ __device__ __forceinline__ void cell_of(float x, int N, int& k0, double& f) {
 
 __device__ __forceinline__ float clamp01(double v) { return (float)(v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v)); }
 
+__device__ __forceinline__ float2 advect_point(const float2* __restrict__ field, int N, float2 q) {
+    int i0, j0;
+    double fx, fy;
+    cell_of(q.x, N, i0, fx);
+    cell_of(q.y, N, j0, fy);
+    const float2* r0 = field + (size_t)j0 * N + i0;
+    const float2* r1 = r0 + N;
+    const float2 a = r0[0], b = r0[1], c = r1[0], d = r1[1];
+    const double w00 = (1.0 - fx) * (1.0 - fy), w10 = fx * (1.0 - fy), w01 = (1.0 - fx) * fy, w11 = fx * fy;
+    const double nx = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
+    const double ny = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
+    return make_float2(clamp01(nx), clamp01(ny));
+}
+
 // Adds 1 at `key` for every lane holding a key below 0xFFFFFFFF: the 64 keys of
 // the wave are sorted (bitonic network over lane shuffles) and only the first
 // lane of every run of equal keys issues one atomic with the run length.  With
@@ -155,18 +169,7 @@ __device__ __forceinline__ void advect_body(const float2* __restrict__ field, in
         const int64_t p = base + lane_id();
         uint32_t key = 0xFFFFFFFFu;
         if (p < n) {
-            const float2 q = xy[p];
-            int i0, j0;
-            double fx, fy;
-            cell_of(q.x, N, i0, fx);
-            cell_of(q.y, N, j0, fy);
-            const float2* r0 = field + (size_t)j0 * N + i0;
-            const float2* r1 = r0 + N;
-            const float2 a = r0[0], b = r0[1], c = r1[0], d = r1[1];
-            const double w00 = (1.0 - fx) * (1.0 - fy), w10 = fx * (1.0 - fy), w01 = (1.0 - fx) * fy, w11 = fx * fy;
-            const double nx = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
-            const double ny = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
-            const float2 o = make_float2(clamp01(nx), clamp01(ny));
+            const float2 o = advect_point(field, N, xy[p]);
             xy[p] = o;
             key = (uint32_t)(texel_of(o.y, N) * N + texel_of(o.x, N));
         }
@@ -299,38 +302,315 @@ __global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* __restrict_
 }
 
 // Moves every sample to slot offset[texel] + rank: texel (row-major) order.
+// The slot replaces the rank, so that the results can be gathered back.
 __device__ __forceinline__ void scatter_sorted_body(const float2* __restrict__ xy, int64_t n, int N,
-                                                    const uint32_t* __restrict__ rank,
-                                                    const uint32_t* __restrict__ offset, float2* __restrict__ sxy,
-                                                    uint32_t* __restrict__ perm, int64_t bid, int64_t nblk) {
+                                                    uint32_t* __restrict__ rank, const uint32_t* __restrict__ offset,
+                                                    float2* __restrict__ sxy, int64_t bid, int64_t nblk) {
     const int64_t stride = (int64_t)nblk * blockDim.x;
     for (int64_t p = (int64_t)bid * blockDim.x + threadIdx.x; p < n; p += stride) {
         const float2 q = xy[p];
         const int i = texel_of(q.x, N), j = texel_of(q.y, N);
         const uint32_t slot = offset[(size_t)j * N + i] + rank[p];
         sxy[slot] = q;
-        perm[slot] = (uint32_t)p;
+        rank[p] = slot;
     }
 }
 
 __global__ __launch_bounds__(256) void k_scatter_sorted(const float2* __restrict__ xy, int64_t n, int N,
-                                                        const uint32_t* __restrict__ rank,
+                                                        uint32_t* __restrict__ rank,
                                                         const uint32_t* __restrict__ offset, float2* __restrict__ sxy,
-                                                        uint32_t* __restrict__ perm, const int* status) {
+                                                        const int* status) {
     if (failed(status)) return;
-    scatter_sorted_body(xy, n, N, rank, offset, sxy, perm, blockIdx.x, gridDim.x);
+    scatter_sorted_body(xy, n, N, rank, offset, sxy, blockIdx.x, gridDim.x);
 }
 
-__device__ __forceinline__ void unpermute_body(const float2* __restrict__ sxy, const uint32_t* __restrict__ perm,
+// Back to the caller's order, from the slot of every sample (xy[p] =
+// sxy[slot[p]]: xy read and written in order, sxy gathered) or from the
+// sample of every slot (xy[perm[q]] = sxy[q]: xy scattered).
+__device__ __forceinline__ void unpermute_body(const float2* __restrict__ sxy, const uint32_t* __restrict__ slot,
                                                int64_t n, float2* __restrict__ xy, int64_t bid, int64_t nblk) {
     const int64_t stride = (int64_t)nblk * blockDim.x;
-    for (int64_t q = (int64_t)bid * blockDim.x + threadIdx.x; q < n; q += stride) xy[perm[q]] = sxy[q];
+    for (int64_t p = (int64_t)bid * blockDim.x + threadIdx.x; p < n; p += stride) xy[p] = sxy[slot[p]];
 }
 
-__global__ __launch_bounds__(256) void k_unpermute(const float2* __restrict__ sxy, const uint32_t* __restrict__ perm,
+__global__ __launch_bounds__(256) void k_unpermute(const float2* __restrict__ sxy, const uint32_t* __restrict__ slot,
                                                    int64_t n, float2* __restrict__ xy, const int* status) {
     if (failed(status)) return;
-    unpermute_body(sxy, perm, n, xy, blockIdx.x, gridDim.x);
+    unpermute_body(sxy, slot, n, xy, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_unpermute_scatter(const float2* __restrict__ sxy,
+                                                           const uint32_t* __restrict__ perm, int64_t n,
+                                                           float2* __restrict__ xy, const int* status) {
+    if (failed(status)) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) xy[perm[q]] = sxy[q];
+}
+
+// Texel order in two levels with no per-sample global atomics (those run at a
+// few tens of billions per second whatever the address pattern, which at 1M
+// samples costs more than every other step of the sort together).
+//  1. Row buckets: kRowTiles blocks, each over one contiguous tile of samples,
+//     count their samples per texel row in LDS (k_row_hist, flagging invalid
+//     samples) and store them tile-major, hist[b * N + j]; k_row_scan turns
+//     every row's counts over the tiles into prefixes (same layout) and row
+//     totals; k_row_bucket scans the row totals into the first slot of every
+//     row (rowstart) and moves every sample to rowstart[j] plus its tile's
+//     prefix in row j plus its place in that run (an LDS counter), together
+//     with its index.
+//  2. One block per row (k_row_sort) counts the row's samples per column in
+//     LDS, writes that row of the count raster, scans the counts and moves
+//     every sample to its slot in texel order, recording its index by slot
+//     (writes that stay within the row's range of slots).
+// The order within a texel is arbitrary: nothing computed from it depends
+// on it.  Rows of up to kRowSortMaxN texels (LDS counters).
+constexpr int kRowTiles = 256, kRowThreads = 1024, kRowSortMaxN = 4096;
+
+__global__ __launch_bounds__(kRowThreads) void k_row_hist(const float2* __restrict__ xy, int64_t n, int N,
+                                                           int64_t tile, uint32_t* __restrict__ hist, int* status) {
+    __shared__ uint32_t bins[kRowSortMaxN];
+    for (int j = threadIdx.x; j < N; j += kRowThreads) bins[j] = 0u;
+    __syncthreads();
+    const int64_t p0 = (int64_t)blockIdx.x * tile, p1 = min(n, p0 + tile);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += kRowThreads) {
+        const float2 q = xy[p];
+        if (!in_unit_square(q)) {
+            flag_domain(status);
+            continue;
+        }
+        atomicAdd(&bins[texel_of(q.y, N)], 1u);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < N; j += kRowThreads) hist[(size_t)blockIdx.x * N + j] = bins[j];
+}
+
+// Moves the samples of one tile, in chunks of kRowChunk, to their row runs:
+// each chunk is first ordered by row in LDS, so that consecutive lanes write
+// consecutive slots of a run.
+constexpr int kRowChunk = 4096;
+
+// prefix[b * N + j] = sum of hist[b' * N + j] over b' < b; rowtot[j] = the sum
+// over all tiles.  A block of 256 threads takes kScanRows rows: their counts
+// over all tiles go through LDS (loads and stores of kScanRows consecutive
+// words per tile), kScanParts threads scan a row, kScanTiles tiles each.
+constexpr int kScanRows = 8, kScanParts = 256 / kScanRows, kScanTiles = kRowTiles / kScanParts;
+
+__global__ __launch_bounds__(256) void k_row_scan(const uint32_t* __restrict__ hist, int N,
+                                                  uint32_t* __restrict__ prefix, uint32_t* __restrict__ rowtot,
+                                                  const int* status) {
+    static_assert(kRowTiles == 256 && kScanParts <= 64, "a row's parts within one wave");
+    __shared__ uint32_t h[kRowTiles][kScanRows + 1];
+    if (failed(status)) return;
+    const int j0 = blockIdx.x * kScanRows, t = threadIdx.x;
+    const int r = t % kScanRows, b0 = t / kScanRows;  // loads: row r, tiles b0 + kScanParts k
+    {
+        uint32_t v[kScanTiles];  // every load in flight before the first store
+#pragma unroll
+        for (int k = 0; k < kScanTiles; ++k) v[k] = hist[(size_t)(b0 + kScanParts * k) * N + j0 + r];
+#pragma unroll
+        for (int k = 0; k < kScanTiles; ++k) h[b0 + kScanParts * k][r] = v[k];
+    }
+    __syncthreads();
+    const int row = t / kScanParts, part = t % kScanParts;  // scan: tiles [kScanTiles part, +kScanTiles)
+    uint32_t c[kScanTiles];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanTiles; ++k) {
+        c[k] = h[part * kScanTiles + k][row];
+        sum += c[k];
+    }
+    uint32_t incl = sum;  // inclusive scan over the row's parts (consecutive lanes)
+#pragma unroll
+    for (int d = 1; d < kScanParts; d <<= 1) {
+        const uint32_t o = (uint32_t)__shfl_up((int)incl, d, kScanParts);
+        if (part >= d) incl += o;
+    }
+    uint32_t run = incl - sum;
+#pragma unroll
+    for (int k = 0; k < kScanTiles; ++k) {
+        h[part * kScanTiles + k][row] = run;
+        run += c[k];
+    }
+    if (part == kScanParts - 1) rowtot[j0 + row] = run;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanTiles; ++k) prefix[(size_t)(b0 + kScanParts * k) * N + j0 + r] = h[b0 + kScanParts * k][r];
+}
+
+// Block 0 also stores rowstart for k_row_sort.
+__global__ __launch_bounds__(kRowThreads) void k_row_bucket(const float2* __restrict__ xy, int64_t n, int N,
+                                                             int64_t tile, const uint32_t* __restrict__ prefix,
+                                                             const uint32_t* __restrict__ rowtot,
+                                                             uint32_t* __restrict__ rowstart,
+                                                             float2* __restrict__ stage, uint32_t* __restrict__ idx,
+                                                             const int* status) {
+    __shared__ uint32_t cnt[kRowSortMaxN];   // per row: count in the chunk, then its first LDS slot
+    __shared__ uint32_t next[kRowSortMaxN];  // per row: the tile's next slot in `stage`
+    __shared__ uint32_t base[kRowSortMaxN];  // per row: stage slot minus LDS slot, for the chunk
+    __shared__ float2 lxy[kRowChunk];
+    __shared__ uint32_t lidx[kRowChunk];
+    __shared__ uint32_t lw[33];
+    constexpr int kPer = kRowChunk / kRowThreads, kRowsPer = kRowSortMaxN / kRowThreads;
+    if (failed(status)) return;  // every sample is in the unit square below
+    const int per = (N + kRowThreads - 1) / kRowThreads, r0 = threadIdx.x * per;
+    {
+        uint32_t v[kRowsPer];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kRowsPer; ++k) {
+            v[k] = (k < per && r0 + k < N) ? rowtot[r0 + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t total;
+        uint32_t run = block_exclusive_scan(sum, lw, total);
+#pragma unroll
+        for (int k = 0; k < kRowsPer; ++k)
+            if (k < per && r0 + k < N) {
+                const int j = r0 + k;
+                next[j] = run + prefix[(size_t)blockIdx.x * N + j];
+                if (blockIdx.x == 0) rowstart[j] = run;
+                run += v[k];
+            }
+    }
+    const int64_t p0 = (int64_t)blockIdx.x * tile, p1 = min(n, p0 + tile);
+    for (int64_t c0 = p0; c0 < p1; c0 += kRowChunk) {
+        const int m = (int)min((int64_t)kRowChunk, p1 - c0);
+        for (int j = threadIdx.x; j < N; j += kRowThreads) cnt[j] = 0u;
+        __syncthreads();
+        float2 q[kPer];
+        uint32_t row[kPer], rk[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int s = threadIdx.x + k * kRowThreads;
+            if (s < m) {
+                q[k] = xy[c0 + s];
+                row[k] = (uint32_t)texel_of(q[k].y, N);
+                rk[k] = atomicAdd(&cnt[row[k]], 1u);
+            }
+        }
+        __syncthreads();
+        // rows [r0, r0 + per) of this thread: first LDS slot, stage offset
+        uint32_t v[kRowsPer];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kRowsPer; ++k) {
+            v[k] = (k < per && r0 + k < N) ? cnt[r0 + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t total;
+        uint32_t run = block_exclusive_scan(sum, lw, total);
+#pragma unroll
+        for (int k = 0; k < kRowsPer; ++k)
+            if (k < per && r0 + k < N) {
+                const int j = r0 + k;
+                cnt[j] = run;
+                base[j] = next[j] - run;
+                next[j] += v[k];
+                run += v[k];
+            }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int s = threadIdx.x + k * kRowThreads;
+            if (s < m) {
+                const uint32_t at = cnt[row[k]] + rk[k];
+                lxy[at] = q[k];
+                lidx[at] = (uint32_t)(c0 + s);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int s = threadIdx.x + k * kRowThreads;
+            if (s < m) {
+                const float2 w = lxy[s];
+                const uint32_t at = base[texel_of(w.y, N)] + (uint32_t)s;
+                stage[at] = w;
+                idx[at] = lidx[s];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One block per row j.  Rows of up to kSortThreads * kSortHeld samples are
+// read once and held in registers between the count and the move; longer
+// rows are read twice.  The block also writes row j of the defect field t1.
+constexpr int kSortThreads = 512, kSortHeld = 8;
+
+__global__ __launch_bounds__(kSortThreads) void k_row_sort(const float2* __restrict__ stage,
+                                                            const uint32_t* __restrict__ idx,
+                                                            const uint32_t* __restrict__ rowstart, int64_t n, int N,
+                                                            uint32_t* __restrict__ counts, float2* __restrict__ sxy,
+                                                            uint32_t* __restrict__ perm, float2* __restrict__ t1,
+                                                            const int* status) {
+    __shared__ uint32_t bins[kRowSortMaxN];
+    __shared__ uint32_t lw[33];
+    constexpr int kColsPer = kRowSortMaxN / kSortThreads;
+    if (failed(status)) return;
+    const int j = blockIdx.x, t = threadIdx.x;
+    const int64_t q0 = rowstart[j];
+    const int64_t q1 = j + 1 < N ? (int64_t)rowstart[j + 1] : n;
+    const bool held = q1 - q0 <= (int64_t)kSortThreads * kSortHeld;
+    for (int i = t; i < N; i += kSortThreads) bins[i] = 0u;
+    __syncthreads();
+    float2 v[kSortHeld];
+    uint32_t col[kSortHeld], from[kSortHeld];
+    if (held) {
+#pragma unroll
+        for (int k = 0; k < kSortHeld; ++k) {
+            const int64_t q = q0 + t + k * kSortThreads;
+            if (q < q1) {
+                v[k] = stage[q];
+                from[k] = idx[q];
+                col[k] = (uint32_t)texel_of(v[k].x, N);
+                atomicAdd(&bins[col[k]], 1u);
+            }
+        }
+    } else {
+        for (int64_t q = q0 + t; q < q1; q += kSortThreads) atomicAdd(&bins[texel_of(stage[q].x, N)], 1u);
+    }
+    __syncthreads();
+    // this row of the count raster, then the exclusive scan of the counts
+    // (thread t holds entries [t * per, t * per + per))
+    const int per = (N + kSortThreads - 1) / kSortThreads;
+    const int i0 = t * per;
+    uint32_t c[kColsPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kColsPer; ++k) {
+        c[k] = (k < per && i0 + k < N) ? bins[i0 + k] : 0u;
+        sum += c[k];
+    }
+    for (int i = t; i < N; i += kSortThreads) counts[(size_t)j * N + i] = bins[i];
+    uint32_t total;
+    uint32_t run = (uint32_t)q0 + block_exclusive_scan(sum, lw, total);
+#pragma unroll
+    for (int k = 0; k < kColsPer; ++k)
+        if (k < per && i0 + k < N) {
+            bins[i0 + k] = run;
+            run += c[k];
+        }
+    __syncthreads();
+    if (held) {
+#pragma unroll
+        for (int k = 0; k < kSortHeld; ++k) {
+            const int64_t q = q0 + t + k * kSortThreads;
+            if (q < q1) {
+                const uint32_t slot = atomicAdd(&bins[col[k]], 1u);
+                sxy[slot] = v[k];
+                perm[slot] = from[k];
+            }
+        }
+    } else {
+        for (int64_t q = q0 + t; q < q1; q += kSortThreads) {
+            const float2 p = stage[q];
+            const uint32_t slot = atomicAdd(&bins[texel_of(p.x, N)], 1u);
+            sxy[slot] = p;
+            perm[slot] = idx[q];
+        }
+    }
+    for (int i = t; i < N; i += kSortThreads) t1[(size_t)j * N + i] = defect_texel(i, j, N);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -379,23 +659,45 @@ hipError_t launch_advect(const float2* field, int N, float2* xy, int64_t n, uint
 
 namespace inim {
 
-hipError_t launch_sort_by_texel(const float2* xy, int64_t n, int N, uint32_t* counts, uint32_t* rank,
-                                uint32_t* offsets, uint32_t* partial, float2* sxy, uint32_t* perm, int* status,
-                                hipStream_t st) {
-    const size_t m = (size_t)N * N;  // a multiple of 4 (N >= 2, a power of two)
-    const int nb = (int)scan_partials(m);
-    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)(m / 4 + 1), 256, 2048)), dim3(256), 0, st, counts, m, status, 1);
-    hipLaunchKernelGGL(k_splat_rank, dim3(grid_for(n)), dim3(256), 0, st, xy, n, N, counts, rank, status);
+static void launch_scan(const uint32_t* a, size_t m, uint32_t* partial, uint32_t* out, const int* status,
+                        hipStream_t st) {
     if (m % kScanBlock == 0) {
-        hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, counts, partial, status);
+        const int nb = (int)scan_partials(m);
+        hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, a, partial, status);
         hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, partial, nb, status);
-        hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, st, counts, partial, offsets, status);
-    } else {  // fewer than 1024 texels (N <= 16): one partial block
-        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, counts, (int)m, offsets, status);
+        hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, st, a, partial, out, status);
+    } else {  // fewer than 1024 words: one block
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, a, (int)m, out, status);
     }
-    hipLaunchKernelGGL(k_scatter_sorted, dim3(grid_for(n)), dim3(256), 0, st, xy, n, N, rank, offsets, sxy, perm,
-                       status);
-    return hipGetLastError();
+}
+
+bool row_sort_fits(int N) { return N >= 256 && N <= kRowSortMaxN; }
+
+hipError_t launch_sort_by_texel(const float2* xy, int64_t n, int N, uint32_t* counts, uint32_t* map,
+                                uint32_t* offsets, uint32_t* partial, uint32_t* rows, float2* sxy, float2* stage,
+                                uint32_t* idx, float2* t1, int* status, hipStream_t st) {
+    if (row_sort_fits(N)) {
+        // N * kRowTiles <= N * N words of tile counts and offsets
+        const int64_t tile = n > 0 ? (n + kRowTiles - 1) / kRowTiles : 1;
+        // tile counts in `counts` (whose rows k_row_sort rewrites), their
+        // prefixes in `offsets`, row totals and row starts in `rows`
+        uint32_t *rowtot = rows, *rowstart = rows + N;
+        hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, counts, (size_t)0, status, 1);
+        hipLaunchKernelGGL(k_row_hist, dim3(kRowTiles), dim3(kRowThreads), 0, st, xy, n, N, tile, counts, status);
+        hipLaunchKernelGGL(k_row_scan, dim3(N / kScanRows), dim3(256), 0, st, counts, N, offsets, rowtot, status);
+        hipLaunchKernelGGL(k_row_bucket, dim3(kRowTiles), dim3(kRowThreads), 0, st, xy, n, N, tile, offsets, rowtot,
+                           rowstart, stage, idx, status);
+        hipLaunchKernelGGL(k_row_sort, dim3(N), dim3(kSortThreads), 0, st, stage, idx, rowstart, n, N, counts, sxy,
+                           map, t1, status);
+        return hipGetLastError();
+    }
+    const size_t m = (size_t)N * N;  // a multiple of 4 (N >= 2, a power of two)
+    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)(m / 4 + 1), 256, 2048)), dim3(256), 0, st, counts, m, status, 1);
+    hipLaunchKernelGGL(k_splat_rank, dim3(grid_for(n)), dim3(256), 0, st, xy, n, N, counts, map, status);
+    launch_scan(counts, m, partial, offsets, status, st);
+    hipLaunchKernelGGL(k_scatter_sorted, dim3(grid_for(n)), dim3(256), 0, st, xy, n, N, map, offsets, sxy, status);
+    const hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : launch_defect_field(N, t1, st);
 }
 
 // ------------------------------------------------------------------ batched (scatterplot matrix)
@@ -442,8 +744,7 @@ __global__ __launch_bounds__(256) void kb_scatter(const BatchTable* __restrict__
     if (failed(status)) return;
     int64_t bid, nblk;
     const BatchPlot& P = batch_locate(T, kBScatter, blockIdx.x, bid, nblk);
-    scatter_sorted_body(reinterpret_cast<const float2*>(P.xy), P.n, P.N, P.rank, P.counts[1], P.sxy, P.perm, bid,
-                        nblk);
+    scatter_sorted_body(reinterpret_cast<const float2*>(P.xy), P.n, P.N, P.rank, P.counts[1], P.sxy, bid, nblk);
 }
 
 __global__ __launch_bounds__(256) void kb_advect(const BatchTable* __restrict__ T, int it, int iters,
@@ -459,7 +760,7 @@ __global__ __launch_bounds__(256) void kb_unpermute(const BatchTable* __restrict
     if (failed(status)) return;
     int64_t bid, nblk;
     const BatchPlot& P = batch_locate(T, kBUnpermute, blockIdx.x, bid, nblk);
-    unpermute_body(P.sxy, P.perm, P.n, reinterpret_cast<float2*>(P.xy), bid, nblk);
+    unpermute_body(P.sxy, P.rank, P.n, reinterpret_cast<float2*>(P.xy), bid, nblk);
 }
 
 hipError_t launch_batch_raster(int stage, const BatchTable* T, unsigned blocks, int it, int iters, int* status,
@@ -481,9 +782,12 @@ hipError_t launch_batch_raster(int stage, const BatchTable* T, unsigned blocks, 
     return hipGetLastError();
 }
 
-hipError_t launch_unpermute(const float2* sxy, const uint32_t* perm, int64_t n, float2* xy, const int* status,
+hipError_t launch_unpermute(const float2* sxy, const uint32_t* map, int64_t n, int N, float2* xy, const int* status,
                             hipStream_t st) {
-    hipLaunchKernelGGL(k_unpermute, dim3(grid_for(n)), dim3(256), 0, st, sxy, perm, n, xy, status);
+    if (row_sort_fits(N))
+        hipLaunchKernelGGL(k_unpermute_scatter, dim3(grid_for(n)), dim3(256), 0, st, sxy, map, n, xy, status);
+    else
+        hipLaunchKernelGGL(k_unpermute, dim3(grid_for(n)), dim3(256), 0, st, sxy, map, n, xy, status);
     return hipGetLastError();
 }
 

@@ -69,16 +69,21 @@ hipError_t launch_blur(const uint32_t* counts, float* out, int N, const BlurTaps
                        hipStream_t st);
 hipError_t launch_validate(const float2* xy, int64_t n, int* status, hipStream_t st);
 
-// Counting sort of the samples by texel (row-major): clears `counts` and the
-// status word, splats with ranks (flagging invalid samples), scans the counts
-// into `offsets` (using `partial`, scan_partials(N*N) words), and writes the
-// samples in texel order to sxy with perm[slot] = original index.  `counts`
-// keeps the texel counts of the input.
-hipError_t launch_sort_by_texel(const float2* xy, int64_t n, int N, uint32_t* counts, uint32_t* rank,
-                                uint32_t* offsets, uint32_t* partial, float2* sxy, uint32_t* perm, int* status,
-                                hipStream_t st);
-// xy[perm[q]] = sxy[q]
-hipError_t launch_unpermute(const float2* sxy, const uint32_t* perm, int64_t n, float2* xy, const int* status,
+// Counting sort of the samples by texel (row-major) into sxy: clears the
+// status word (then set for invalid samples) and writes the texel counts of
+// the input to `counts` and the defect field t(p; 1) to t1 (N x N).  When
+// row_sort_fits(N) (a row-bucketed pass, then one sort per row in LDS), map[q]
+// is the index of the sample in slot q, and `stage` (n samples) and `idx`
+// (n words) are scratch; otherwise (ranks by global atomics) map[p] is the
+// slot of sample p.  `offsets` (N * N words), `partial` (scan_partials(N * N)
+// words) and `rows` (2 N words) are scratch.
+bool row_sort_fits(int N);
+hipError_t launch_sort_by_texel(const float2* xy, int64_t n, int N, uint32_t* counts, uint32_t* map,
+                                uint32_t* offsets, uint32_t* partial, uint32_t* rows, float2* sxy, float2* stage,
+                                uint32_t* idx, float2* t1, int* status, hipStream_t st);
+// The samples of sxy back to the caller's order through the map that
+// launch_sort_by_texel wrote for this N.
+hipError_t launch_unpermute(const float2* sxy, const uint32_t* map, int64_t n, int N, float2* xy, const int* status,
                             hipStream_t st);
 // counts_next != nullptr: also splat the moved samples into it (must be zero).
 hipError_t launch_advect(const float2* field, int N, float2* xy, int64_t n, uint32_t* counts_next, const int* status,

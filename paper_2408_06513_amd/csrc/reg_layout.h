@@ -15,7 +15,11 @@ __host__ __device__ inline size_t scan_partials(size_t m) { return (m + kScanBlo
 
 // Byte offsets of the regions of one plot's regularisation workspace.
 struct RegLayout {
-    size_t status, counts[2], density, field, defect, scratch, sxy, perm, rank, partial, total;
+    // sxy: the samples in texel order, iterated in place; rank: the map
+    // between the caller's order and sxy (per sample its rank in its texel,
+    // then its slot; or per slot its sample); stage / idx: the samples
+    // bucketed by texel row and their indices (row sort only).
+    size_t status, counts[2], density, field, defect, scratch, sxy, stage, idx, rank, partial, total;
     Geom g;
     bool f32;  // integral images of the float density in double (radius > 0), or of the counts
 };
@@ -35,7 +39,8 @@ __host__ __device__ inline RegLayout reg_layout(int32_t res, int64_t n, int radi
     L.defect = o; o += align256(NN * 8);
     L.scratch = o; o += inim_scratch_bytes(L.g, L.f32 ? 8 : 4);
     L.sxy = o; o += align256(nn * 8);
-    L.perm = o; o += align256(nn * 4);
+    L.stage = o; o += align256(nn * 8);
+    L.idx = o; o += align256(nn * 4);
     L.rank = o; o += align256(nn * 4);
     L.partial = o; o += align256(scan_partials(NN) * 4);
     L.total = o;

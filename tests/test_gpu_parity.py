@@ -267,6 +267,30 @@ def test_regularize_edge_sizes(capi, dev, res, n, radius):
     assert np.abs(got - ref).max() <= 1e-5
 
 
+@pytest.mark.parametrize("res,n,iters", [(256, 1, 2), (256, 70_001, 2), (512, 1_100_003, 1), (4096, 20_000, 1)])
+def test_regularize_row_sorted_sizes(capi, dev, res, n, iters):
+    """Rasters of 256^2 to 4096^2, where the samples are put in texel order by
+    row buckets and a per-row sort in LDS: a single sample, a ragged count
+    over the 256 sample tiles, tiles of more than one 4096-sample chunk, the
+    largest raster of that path."""
+    xy = dg.plain_small(8)[:n] if n <= 20_000 else dg.plain_large(2, n=n)
+    note(f"regularize row-sorted res={res} n={n}")
+    got = gpu_regularize(capi, dev, xy, res, iters)
+    assert np.abs(got - oracle.regularize(xy, res, iters)).max() <= 1e-5
+
+
+def test_regularize_crowded_row_and_texel(capi, dev):
+    """150k samples in one texel row and 50k in one texel (512^2): the row and
+    texel buckets far larger than a block."""
+    g = np.random.Generator(np.random.PCG64(8))
+    a = np.stack([g.random(150_000), 0.5 + g.random(150_000) / 512], 1)
+    b = np.stack([0.25 + g.random(50_000) / 1024, 0.75 + g.random(50_000) / 1024], 1)
+    xy = np.concatenate([a, b]).astype(np.float32)[g.permutation(200_000)]
+    note("regularize crowded rows")
+    got = gpu_regularize(capi, dev, xy, 512, 2)
+    assert np.abs(got - oracle.regularize(xy, 512, 2)).max() <= 1e-5
+
+
 def test_regularize_metamorphic_bitwise(capi, dev):
     """Duplicating every sample and permuting the input give bit-identical
     positions on the GPU too (counts are integers; scale invariance)."""
@@ -287,25 +311,26 @@ def test_regularize_lattice_fixed_point(capi, dev):
     assert np.abs(got - xy).max() <= 1e-6
 
 
-def test_regularize_noop_and_domain_error(capi, dev):
+@pytest.mark.parametrize("res", [64, 256])
+def test_regularize_noop_and_domain_error(capi, dev, res):
     empty = torch.empty((0, 2), dtype=torch.float32, device=dev)
-    capi.regularize(empty, 64, 3)
+    capi.regularize(empty, res, 3)
     xy = dg.plain_small(6)[:1000].copy()
     g0 = to_dev(xy, dev)
-    capi.regularize(g0, 64, 0)
+    capi.regularize(g0, res, 0)
     assert np.array_equal(g0.cpu().numpy(), xy)
+    ws = capi.workspace(capi.workspace_size(res, 1000), dev)
     for bad in (np.nan, 1.5, -0.25):
         xb = xy.copy()
         xb[500, 1] = bad
         g = to_dev(xb, dev)
         with pytest.raises(capi.DomainError):
-            capi.regularize(g, 64, 3)
+            capi.regularize(g, res, 3, ws=ws)
         assert np.array_equal(g.cpu().numpy(), xb, equal_nan=True)
     # the workspace recovers: a valid call after a failed one succeeds
-    ws = capi.workspace(capi.workspace_size(64, 1000), dev)
     g = to_dev(xy, dev)
-    capi.regularize(g, 64, 2, ws=ws)
-    assert np.abs(g.cpu().numpy() - oracle.regularize(xy, 64, 2)).max() <= 1e-5
+    capi.regularize(g, res, 2, ws=ws)
+    assert np.abs(g.cpu().numpy() - oracle.regularize(xy, res, 2)).max() <= 1e-5
 
 
 def test_advect_domain_error_leaves_xy(capi, dev):
