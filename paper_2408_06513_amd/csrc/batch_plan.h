@@ -18,6 +18,10 @@ enum BatchStage : int {
     kBScanPartials,
     kBScanDown,
     kBScatter,
+    kBRowHist,
+    kBRowScan,
+    kBRowBucket,
+    kBRowSort,
     kBDefect,
     kBBlurAgg,
     kBScanCol,
@@ -39,16 +43,21 @@ __host__ __device__ inline unsigned grid_blocks(int64_t n, int per_block = 256, 
 // launches; the deformation stage with wpb tiles per block).
 __host__ __device__ inline unsigned batch_stage_blocks(int s, int N, int64_t n, int wpb, bool defect_owner) {
     const size_t NN = (size_t)N * (size_t)N;
+    const bool rows = row_sort_fits(N);  // texel sort by rows (else by global ranks)
     switch (s) {
-        case kBFill: return grid_blocks((int64_t)(NN / 4 + 1), 256, 2048);
+        case kBFill: return rows ? 1u : grid_blocks((int64_t)(NN / 4 + 1), 256, 2048);
         case kBSplatRank:
-        case kBScatter:
+        case kBScatter: return rows ? 0u : grid_blocks(n);
         case kBAdvect:
         case kBUnpermute: return grid_blocks(n);
         case kBScanReduce:
-        case kBScanDown: return (unsigned)scan_partials(NN);
-        case kBScanPartials: return 1;
-        case kBDefect: return defect_owner ? (unsigned)((NN + 255) / 256) : 0u;
+        case kBScanDown: return rows ? 0u : (unsigned)scan_partials(NN);
+        case kBScanPartials: return rows ? 0u : 1u;
+        case kBRowHist:
+        case kBRowBucket: return rows ? (unsigned)kRowTiles : 0u;
+        case kBRowScan: return rows ? (unsigned)(N / kScanRows) : 0u;
+        case kBRowSort: return rows ? (unsigned)(N / row_group(n, N)) : 0u;
+        case kBDefect: return defect_owner && !rows ? (unsigned)((NN + 255) / 256) : 0u;
         case kBBlurAgg: return (unsigned)((N / 64) * (N / 16));
         case kBScanCol: return (unsigned)((N + 63) / 64);
         case kBScanDiag: return (unsigned)(((2 * N + 1 + 63) / 64) * 3);
@@ -70,6 +79,8 @@ struct BatchPlot {
     float2* defect;  // t(p; 1), shared by the plots of one raster size
     bool defect_owner;
     float2* sxy;
+    float2* stage;  // row sort: the row-bucketed samples and their indices
+    uint32_t* idx;
     uint32_t* rank;
     uint32_t* partial;
     Agg<double> A;

@@ -333,7 +333,8 @@ int enqueue_batch(BatchPlan& B, int32_t iters, char* ws, hipStream_t st, bool dr
     int* status = reinterpret_cast<int*>(ws);
     BatchTable* T = reinterpret_cast<BatchTable*>(ws + batch_table_offset());
     hipError_t e = launch_batch_init(B.a, T, st);
-    for (int s : {kBFill, kBSplatRank, kBScanReduce, kBScanPartials, kBScanDown, kBScatter})
+    for (int s : {kBFill, kBSplatRank, kBScanReduce, kBScanPartials, kBScanDown, kBScatter, kBRowHist, kBRowScan,
+                  kBRowBucket, kBRowSort})
         if (e == hipSuccess) e = launch_batch_raster(s, T, B.blocks[s], 0, iters, status, st);
     if (e == hipSuccess) e = launch_batch_inim(kBDefect, T, B.blocks[kBDefect], B.a.wpb, B.taps, 0, iters, status, st);
     for (int it = 0; it < iters && e == hipSuccess; ++it) {

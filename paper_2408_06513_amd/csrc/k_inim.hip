@@ -1067,17 +1067,36 @@ hipError_t launch_inim_final(const Tin* img, const Geom& g, void* scratch, uint3
 }
 
 // ------------------------------------------------------------------ batched (scatterplot matrix)
-// The plot table, built by one block: thread k fills plot k; thread 0 then
-// lays out the blocks of every stage in launch order.
+// Inclusive sum over lanes 0..lane of a wave (64 lanes, one value each).
+template <typename T>
+__device__ __forceinline__ T lane_prefix(T v) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const T o = __shfl_up(v, d, 64);
+        if (lane_id() >= d) v += o;
+    }
+    return v;
+}
+
+// The plot table, built by one wave with one lane per plot (count <= 64):
+// workspace offsets and the first block of every plot in every stage are
+// prefix sums over the lanes.
 __global__ __launch_bounds__(64) void kb_init(BatchArgs a, BatchTable* __restrict__ T) {
+    static_assert(kMaxBatch <= 64, "one lane per plot");
+    __shared__ bool own[kMaxBatch];
     const int k = threadIdx.x;
-    if (k < a.count) {
-        const BatchInput& in = a.in[k];
-        const RegLayout L = reg_layout(in.N, in.n, a.radius);
-        char* base = a.ws + batch_plot_offset(k, a.in, a.radius);
-        int owner = k;  // the first plot of this raster size holds its defect field
-        for (int q = 0; q < k; ++q)
-            if (a.in[q].N == in.N) { owner = q; break; }
+    const bool live = k < a.count;
+    const BatchInput in = live ? a.in[k] : BatchInput{nullptr, 0, 2, 0};
+    const RegLayout L = reg_layout(in.N, in.n, a.radius);
+    const size_t size = live ? L.total : 0;
+    const size_t base_off = kStatusBytes + align256(sizeof(BatchTable)) + lane_prefix(size) - size;
+    int owner = k;  // the first plot of this raster size holds its defect field
+    for (int q = 0; q < k && live; ++q)
+        if (a.in[q].N == in.N) { owner = q; break; }
+    own[k] = owner == k;
+    const size_t owner_off = __shfl(base_off, owner, 64);  // the owner's workspace offset
+    if (live) {
+        char* base = a.ws + base_off;
         BatchPlot P;
         P.xy = reinterpret_cast<float2*>(in.xy);
         P.n = in.n;
@@ -1088,30 +1107,30 @@ __global__ __launch_bounds__(64) void kb_init(BatchArgs a, BatchTable* __restric
         P.counts[1] = reinterpret_cast<uint32_t*>(base + L.counts[1]);
         P.density = reinterpret_cast<float*>(base + L.density);
         P.field = reinterpret_cast<float2*>(base + L.field);
-        P.defect = reinterpret_cast<float2*>(a.ws + batch_plot_offset(owner, a.in, a.radius) + L.defect);
+        P.defect = reinterpret_cast<float2*>(a.ws + owner_off + L.defect);
         P.defect_owner = owner == k;
         P.sxy = reinterpret_cast<float2*>(base + L.sxy);
+        P.stage = reinterpret_cast<float2*>(base + L.stage);
+        P.idx = reinterpret_cast<uint32_t*>(base + L.idx);
         P.rank = reinterpret_cast<uint32_t*>(base + L.rank);
         P.partial = reinterpret_cast<uint32_t*>(base + L.partial);
         carve<double>(L.g, base + L.scratch, P.A, P.K);
         T->plot[k] = P;
+        T->order[k] = a.order[k];
     }
     if (k == 0) {
         T->count = a.count;
         T->wpb = a.wpb;
-        for (int q = 0; q < a.count; ++q) T->order[q] = a.order[q];
-        for (int s = 0; s < kBStages; ++s) {
-            uint32_t run = 0;
-            for (int q = 0; q < a.count; ++q) {
-                T->first[s][q] = run;
-                const int p = a.order[q];
-                bool own = true;
-                for (int r = 0; r < p; ++r)
-                    if (a.in[r].N == a.in[p].N) { own = false; break; }
-                run += batch_stage_blocks(s, a.in[p].N, a.in[p].n, a.wpb, own);
-            }
-            T->first[s][a.count] = run;
-        }
+    }
+    __syncthreads();
+    // stage tables in launch order: lane q holds plot order[q]
+    const int p = live ? a.order[k] : 0;
+    const BatchInput ip = a.in[p];
+    for (int s = 0; s < kBStages; ++s) {
+        const uint32_t b = live ? batch_stage_blocks(s, ip.N, ip.n, a.wpb, own[p]) : 0u;
+        const uint32_t incl = lane_prefix(b);
+        if (live) T->first[s][k] = incl - b;
+        if (k == a.count - 1) T->first[s][a.count] = incl;
     }
 }
 

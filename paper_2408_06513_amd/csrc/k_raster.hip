@@ -339,39 +339,60 @@ __global__ __launch_bounds__(256) void k_unpermute(const float2* __restrict__ sx
     unpermute_body(sxy, slot, n, xy, blockIdx.x, gridDim.x);
 }
 
+__device__ __forceinline__ void unpermute_scatter_body(const float2* __restrict__ sxy,
+                                                       const uint32_t* __restrict__ perm, int64_t n,
+                                                       float2* __restrict__ xy, int64_t bid, int64_t nblk) {
+    const int64_t stride = (int64_t)nblk * blockDim.x;
+    for (int64_t q = (int64_t)bid * blockDim.x + threadIdx.x; q < n; q += stride) xy[perm[q]] = sxy[q];
+}
+
 __global__ __launch_bounds__(256) void k_unpermute_scatter(const float2* __restrict__ sxy,
                                                            const uint32_t* __restrict__ perm, int64_t n,
                                                            float2* __restrict__ xy, const int* status) {
     if (failed(status)) return;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) xy[perm[q]] = sxy[q];
+    unpermute_scatter_body(sxy, perm, n, xy, blockIdx.x, gridDim.x);
 }
 
 // Texel order in two levels with no per-sample global atomics (those run at a
 // few tens of billions per second whatever the address pattern, which at 1M
 // samples costs more than every other step of the sort together).
 //  1. Row buckets: kRowTiles blocks, each over one contiguous tile of samples,
-//     count their samples per texel row in LDS (k_row_hist, flagging invalid
-//     samples) and store them tile-major, hist[b * N + j]; k_row_scan turns
+//     count their samples per texel row in LDS (row_hist, flagging invalid
+//     samples) and store them tile-major, hist[b * N + j]; row_scan turns
 //     every row's counts over the tiles into prefixes (same layout) and row
-//     totals; k_row_bucket scans the row totals into the first slot of every
+//     totals; row_bucket scans the row totals into the first slot of every
 //     row (rowstart) and moves every sample to rowstart[j] plus its tile's
 //     prefix in row j plus its place in that run (an LDS counter), together
 //     with its index.
-//  2. One block per row (k_row_sort) counts the row's samples per column in
-//     LDS, writes that row of the count raster, scans the counts and moves
-//     every sample to its slot in texel order, recording its index by slot
-//     (writes that stay within the row's range of slots).
+//  2. One block per group of row_group(n, N) consecutive rows (row_sort)
+//     counts the group's samples per texel in LDS, writes those rows of the
+//     count raster, scans the counts and moves every sample to its slot in
+//     texel order, recording its index by slot (writes that stay within the
+//     group's range of slots).
 // The order within a texel is arbitrary: nothing computed from it depends
-// on it.  Rows of up to kRowSortMaxN texels (LDS counters).
-constexpr int kRowTiles = 256, kRowThreads = 1024, kRowSortMaxN = 4096;
+// on it.  Rasters with row_sort_fits(N) (LDS counters per row and column).
+// Each body takes its block's index among the blocks of its plot.
+constexpr int kRowThreads = 1024;
+// row_bucket moves the samples of its tile in chunks of kRowChunk, each first
+// ordered by row in LDS, so that consecutive lanes write consecutive slots
+// (56 KB of LDS: two blocks per CU).
+constexpr int kRowChunk = 2048;
+// row_scan: a block of 256 threads takes kScanRows rows; their counts over
+// all tiles go through LDS (loads and stores of kScanRows consecutive words
+// per tile), kScanParts threads scan a row, kScanTiles tiles each.
+constexpr int kScanParts = 256 / kScanRows, kScanTiles = kRowTiles / kScanParts;
+// row_sort: groups of up to kSortThreads * kSortHeld samples are read once
+// and held in registers between the count and the move; larger ones are read
+// twice.
+constexpr int kSortThreads = 512, kSortHeld = 8;
 
-__global__ __launch_bounds__(kRowThreads) void k_row_hist(const float2* __restrict__ xy, int64_t n, int N,
-                                                           int64_t tile, uint32_t* __restrict__ hist, int* status) {
-    __shared__ uint32_t bins[kRowSortMaxN];
+__device__ __forceinline__ int64_t row_tile(int64_t n) { return n > 0 ? (n + kRowTiles - 1) / kRowTiles : 1; }
+
+__device__ __forceinline__ void row_hist_body(const float2* __restrict__ xy, int64_t n, int N,
+                                              uint32_t* __restrict__ hist, int* status, int64_t b, uint32_t* bins) {
     for (int j = threadIdx.x; j < N; j += kRowThreads) bins[j] = 0u;
     __syncthreads();
-    const int64_t p0 = (int64_t)blockIdx.x * tile, p1 = min(n, p0 + tile);
+    const int64_t tile = row_tile(n), p0 = b * tile, p1 = min(n, p0 + tile);
     for (int64_t p = p0 + threadIdx.x; p < p1; p += kRowThreads) {
         const float2 q = xy[p];
         if (!in_unit_square(q)) {
@@ -381,34 +402,32 @@ __global__ __launch_bounds__(kRowThreads) void k_row_hist(const float2* __restri
         atomicAdd(&bins[texel_of(q.y, N)], 1u);
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < N; j += kRowThreads) hist[(size_t)blockIdx.x * N + j] = bins[j];
+    for (int j = threadIdx.x; j < N; j += kRowThreads) hist[(size_t)b * N + j] = bins[j];
 }
 
-// Moves the samples of one tile, in chunks of kRowChunk, to their row runs:
-// each chunk is first ordered by row in LDS, so that consecutive lanes write
-// consecutive slots of a run.
-constexpr int kRowChunk = 4096;
+__global__ __launch_bounds__(kRowThreads) void k_row_hist(const float2* __restrict__ xy, int64_t n, int N,
+                                                           uint32_t* __restrict__ hist, int* status) {
+    __shared__ uint32_t bins[kRowSortMaxN];
+    row_hist_body(xy, n, N, hist, status, blockIdx.x, bins);
+}
 
 // prefix[b * N + j] = sum of hist[b' * N + j] over b' < b; rowtot[j] = the sum
-// over all tiles.  A block of 256 threads takes kScanRows rows: their counts
-// over all tiles go through LDS (loads and stores of kScanRows consecutive
-// words per tile), kScanParts threads scan a row, kScanTiles tiles each.
-constexpr int kScanRows = 8, kScanParts = 256 / kScanRows, kScanTiles = kRowTiles / kScanParts;
+// over all tiles; rows [kScanRows blk, kScanRows blk + kScanRows).
+struct RowScanLds {
+    uint32_t h[kRowTiles][kScanRows + 1];
+};
 
-__global__ __launch_bounds__(256) void k_row_scan(const uint32_t* __restrict__ hist, int N,
-                                                  uint32_t* __restrict__ prefix, uint32_t* __restrict__ rowtot,
-                                                  const int* status) {
+__device__ __forceinline__ void row_scan_body(const uint32_t* __restrict__ hist, int N, uint32_t* __restrict__ prefix,
+                                              uint32_t* __restrict__ rowtot, int64_t blk, RowScanLds& L) {
     static_assert(kRowTiles == 256 && kScanParts <= 64, "a row's parts within one wave");
-    __shared__ uint32_t h[kRowTiles][kScanRows + 1];
-    if (failed(status)) return;
-    const int j0 = blockIdx.x * kScanRows, t = threadIdx.x;
+    const int j0 = (int)blk * kScanRows, t = threadIdx.x;
     const int r = t % kScanRows, b0 = t / kScanRows;  // loads: row r, tiles b0 + kScanParts k
     {
         uint32_t v[kScanTiles];  // every load in flight before the first store
 #pragma unroll
         for (int k = 0; k < kScanTiles; ++k) v[k] = hist[(size_t)(b0 + kScanParts * k) * N + j0 + r];
 #pragma unroll
-        for (int k = 0; k < kScanTiles; ++k) h[b0 + kScanParts * k][r] = v[k];
+        for (int k = 0; k < kScanTiles; ++k) L.h[b0 + kScanParts * k][r] = v[k];
     }
     __syncthreads();
     const int row = t / kScanParts, part = t % kScanParts;  // scan: tiles [kScanTiles part, +kScanTiles)
@@ -416,7 +435,7 @@ __global__ __launch_bounds__(256) void k_row_scan(const uint32_t* __restrict__ h
     uint32_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanTiles; ++k) {
-        c[k] = h[part * kScanTiles + k][row];
+        c[k] = L.h[part * kScanTiles + k][row];
         sum += c[k];
     }
     uint32_t incl = sum;  // inclusive scan over the row's parts (consecutive lanes)
@@ -428,30 +447,41 @@ __global__ __launch_bounds__(256) void k_row_scan(const uint32_t* __restrict__ h
     uint32_t run = incl - sum;
 #pragma unroll
     for (int k = 0; k < kScanTiles; ++k) {
-        h[part * kScanTiles + k][row] = run;
+        L.h[part * kScanTiles + k][row] = run;
         run += c[k];
     }
     if (part == kScanParts - 1) rowtot[j0 + row] = run;
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kScanTiles; ++k) prefix[(size_t)(b0 + kScanParts * k) * N + j0 + r] = h[b0 + kScanParts * k][r];
+    for (int k = 0; k < kScanTiles; ++k)
+        prefix[(size_t)(b0 + kScanParts * k) * N + j0 + r] = L.h[b0 + kScanParts * k][r];
 }
 
-// Block 0 also stores rowstart for k_row_sort.
-__global__ __launch_bounds__(kRowThreads) void k_row_bucket(const float2* __restrict__ xy, int64_t n, int N,
-                                                             int64_t tile, const uint32_t* __restrict__ prefix,
-                                                             const uint32_t* __restrict__ rowtot,
-                                                             uint32_t* __restrict__ rowstart,
-                                                             float2* __restrict__ stage, uint32_t* __restrict__ idx,
-                                                             const int* status) {
-    __shared__ uint32_t cnt[kRowSortMaxN];   // per row: count in the chunk, then its first LDS slot
-    __shared__ uint32_t next[kRowSortMaxN];  // per row: the tile's next slot in `stage`
-    __shared__ uint32_t base[kRowSortMaxN];  // per row: stage slot minus LDS slot, for the chunk
-    __shared__ float2 lxy[kRowChunk];
-    __shared__ uint32_t lidx[kRowChunk];
-    __shared__ uint32_t lw[33];
+__global__ __launch_bounds__(256) void k_row_scan(const uint32_t* __restrict__ hist, int N,
+                                                  uint32_t* __restrict__ prefix, uint32_t* __restrict__ rowtot,
+                                                  const int* status) {
+    __shared__ RowScanLds L;
+    if (failed(status)) return;
+    row_scan_body(hist, N, prefix, rowtot, blockIdx.x, L);
+}
+
+// Tile b's samples to their row runs; the block of tile 0 also stores
+// rowstart for row_sort.  Every sample is in the unit square here (callers
+// run it only when the status word is clear).
+struct RowBucketLds {
+    uint32_t cnt[kRowSortMaxN];   // per row: count in the chunk, its first LDS slot, then stage minus LDS slot
+    uint32_t next[kRowSortMaxN];  // per row: the tile's next slot in `stage`
+    float2 lxy[kRowChunk];
+    uint32_t lidx[kRowChunk];
+    uint32_t lw[33];
+};
+
+__device__ __forceinline__ void row_bucket_body(const float2* __restrict__ xy, int64_t n, int N,
+                                                const uint32_t* __restrict__ prefix,
+                                                const uint32_t* __restrict__ rowtot, uint32_t* __restrict__ rowstart,
+                                                float2* __restrict__ stage, uint32_t* __restrict__ idx, int64_t b,
+                                                RowBucketLds& L) {
     constexpr int kPer = kRowChunk / kRowThreads, kRowsPer = kRowSortMaxN / kRowThreads;
-    if (failed(status)) return;  // every sample is in the unit square below
     const int per = (N + kRowThreads - 1) / kRowThreads, r0 = threadIdx.x * per;
     {
         uint32_t v[kRowsPer];
@@ -462,20 +492,20 @@ __global__ __launch_bounds__(kRowThreads) void k_row_bucket(const float2* __rest
             sum += v[k];
         }
         uint32_t total;
-        uint32_t run = block_exclusive_scan(sum, lw, total);
+        uint32_t run = block_exclusive_scan(sum, L.lw, total);
 #pragma unroll
         for (int k = 0; k < kRowsPer; ++k)
             if (k < per && r0 + k < N) {
                 const int j = r0 + k;
-                next[j] = run + prefix[(size_t)blockIdx.x * N + j];
-                if (blockIdx.x == 0) rowstart[j] = run;
+                L.next[j] = run + prefix[(size_t)b * N + j];
+                if (b == 0) rowstart[j] = run;
                 run += v[k];
             }
     }
-    const int64_t p0 = (int64_t)blockIdx.x * tile, p1 = min(n, p0 + tile);
+    const int64_t tile = row_tile(n), p0 = b * tile, p1 = min(n, p0 + tile);
     for (int64_t c0 = p0; c0 < p1; c0 += kRowChunk) {
         const int m = (int)min((int64_t)kRowChunk, p1 - c0);
-        for (int j = threadIdx.x; j < N; j += kRowThreads) cnt[j] = 0u;
+        for (int j = threadIdx.x; j < N; j += kRowThreads) L.cnt[j] = 0u;
         __syncthreads();
         float2 q[kPer];
         uint32_t row[kPer], rk[kPer];
@@ -485,7 +515,7 @@ __global__ __launch_bounds__(kRowThreads) void k_row_bucket(const float2* __rest
             if (s < m) {
                 q[k] = xy[c0 + s];
                 row[k] = (uint32_t)texel_of(q[k].y, N);
-                rk[k] = atomicAdd(&cnt[row[k]], 1u);
+                rk[k] = atomicAdd(&L.cnt[row[k]], 1u);
             }
         }
         __syncthreads();
@@ -494,18 +524,15 @@ __global__ __launch_bounds__(kRowThreads) void k_row_bucket(const float2* __rest
         uint32_t sum = 0;
 #pragma unroll
         for (int k = 0; k < kRowsPer; ++k) {
-            v[k] = (k < per && r0 + k < N) ? cnt[r0 + k] : 0u;
+            v[k] = (k < per && r0 + k < N) ? L.cnt[r0 + k] : 0u;
             sum += v[k];
         }
         uint32_t total;
-        uint32_t run = block_exclusive_scan(sum, lw, total);
+        uint32_t run = block_exclusive_scan(sum, L.lw, total);
 #pragma unroll
         for (int k = 0; k < kRowsPer; ++k)
             if (k < per && r0 + k < N) {
-                const int j = r0 + k;
-                cnt[j] = run;
-                base[j] = next[j] - run;
-                next[j] += v[k];
+                L.cnt[r0 + k] = run;
                 run += v[k];
             }
         __syncthreads();
@@ -513,46 +540,66 @@ __global__ __launch_bounds__(kRowThreads) void k_row_bucket(const float2* __rest
         for (int k = 0; k < kPer; ++k) {
             const int s = threadIdx.x + k * kRowThreads;
             if (s < m) {
-                const uint32_t at = cnt[row[k]] + rk[k];
-                lxy[at] = q[k];
-                lidx[at] = (uint32_t)(c0 + s);
+                const uint32_t at = L.cnt[row[k]] + rk[k];
+                L.lxy[at] = q[k];
+                L.lidx[at] = (uint32_t)(c0 + s);
             }
         }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kRowsPer; ++k)
+            if (k < per && r0 + k < N) {
+                const int j = r0 + k;
+                L.cnt[j] = L.next[j] - L.cnt[j];
+                L.next[j] += v[k];
+            }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int s = threadIdx.x + k * kRowThreads;
             if (s < m) {
-                const float2 w = lxy[s];
-                const uint32_t at = base[texel_of(w.y, N)] + (uint32_t)s;
+                const float2 w = L.lxy[s];
+                const uint32_t at = L.cnt[texel_of(w.y, N)] + (uint32_t)s;
                 stage[at] = w;
-                idx[at] = lidx[s];
+                idx[at] = L.lidx[s];
             }
         }
         __syncthreads();
     }
 }
 
-// One block per row j.  Rows of up to kSortThreads * kSortHeld samples are
-// read once and held in registers between the count and the move; longer
-// rows are read twice.  The block also writes row j of the defect field t1.
-constexpr int kSortThreads = 512, kSortHeld = 8;
-
-__global__ __launch_bounds__(kSortThreads) void k_row_sort(const float2* __restrict__ stage,
-                                                            const uint32_t* __restrict__ idx,
-                                                            const uint32_t* __restrict__ rowstart, int64_t n, int N,
-                                                            uint32_t* __restrict__ counts, float2* __restrict__ sxy,
-                                                            uint32_t* __restrict__ perm, float2* __restrict__ t1,
-                                                            const int* status) {
-    __shared__ uint32_t bins[kRowSortMaxN];
-    __shared__ uint32_t lw[33];
-    constexpr int kColsPer = kRowSortMaxN / kSortThreads;
+__global__ __launch_bounds__(kRowThreads) void k_row_bucket(const float2* __restrict__ xy, int64_t n, int N,
+                                                             const uint32_t* __restrict__ prefix,
+                                                             const uint32_t* __restrict__ rowtot,
+                                                             uint32_t* __restrict__ rowstart,
+                                                             float2* __restrict__ stage, uint32_t* __restrict__ idx,
+                                                             const int* status) {
+    __shared__ RowBucketLds L;
     if (failed(status)) return;
-    const int j = blockIdx.x, t = threadIdx.x;
-    const int64_t q0 = rowstart[j];
-    const int64_t q1 = j + 1 < N ? (int64_t)rowstart[j + 1] : n;
+    row_bucket_body(xy, n, N, prefix, rowtot, rowstart, stage, idx, blockIdx.x, L);
+}
+
+// Rows [g blk, g blk + g) to texel order, g = row_group(n, N); also those
+// rows of the defect field when t1 is not null.
+struct RowSortLds {
+    uint32_t bins[kRowSortMaxN];
+    uint32_t lw[33];
+};
+
+__device__ __forceinline__ void row_sort_body(const float2* __restrict__ stage, const uint32_t* __restrict__ idx,
+                                              const uint32_t* __restrict__ rowstart, int64_t n, int N,
+                                              uint32_t* __restrict__ counts, float2* __restrict__ sxy,
+                                              uint32_t* __restrict__ perm, float2* __restrict__ t1, int blk,
+                                              RowSortLds& L) {
+    constexpr int kColsPer = kRowSortMaxN / kSortThreads;
+    const int t = threadIdx.x;
+    const int g = row_group(n, N), j0 = blk * g, K = g * N;  // K texels, row-major from (0, j0)
+    const int64_t q0 = rowstart[j0];
+    const int64_t q1 = j0 + g < N ? (int64_t)rowstart[j0 + g] : n;
     const bool held = q1 - q0 <= (int64_t)kSortThreads * kSortHeld;
-    for (int i = t; i < N; i += kSortThreads) bins[i] = 0u;
+    // the texel of a sample of these rows, relative to (0, j0)
+    auto key = [&](float2 p) { return (uint32_t)((texel_of(p.y, N) - j0) * N + texel_of(p.x, N)); };
+    for (int i = t; i < K; i += kSortThreads) L.bins[i] = 0u;
     __syncthreads();
     float2 v[kSortHeld];
     uint32_t col[kSortHeld], from[kSortHeld];
@@ -563,32 +610,32 @@ __global__ __launch_bounds__(kSortThreads) void k_row_sort(const float2* __restr
             if (q < q1) {
                 v[k] = stage[q];
                 from[k] = idx[q];
-                col[k] = (uint32_t)texel_of(v[k].x, N);
-                atomicAdd(&bins[col[k]], 1u);
+                col[k] = key(v[k]);
+                atomicAdd(&L.bins[col[k]], 1u);
             }
         }
     } else {
-        for (int64_t q = q0 + t; q < q1; q += kSortThreads) atomicAdd(&bins[texel_of(stage[q].x, N)], 1u);
+        for (int64_t q = q0 + t; q < q1; q += kSortThreads) atomicAdd(&L.bins[key(stage[q])], 1u);
     }
     __syncthreads();
-    // this row of the count raster, then the exclusive scan of the counts
+    // these rows of the count raster, then the exclusive scan of the counts
     // (thread t holds entries [t * per, t * per + per))
-    const int per = (N + kSortThreads - 1) / kSortThreads;
+    const int per = (K + kSortThreads - 1) / kSortThreads;
     const int i0 = t * per;
     uint32_t c[kColsPer];
     uint32_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kColsPer; ++k) {
-        c[k] = (k < per && i0 + k < N) ? bins[i0 + k] : 0u;
+        c[k] = (k < per && i0 + k < K) ? L.bins[i0 + k] : 0u;
         sum += c[k];
     }
-    for (int i = t; i < N; i += kSortThreads) counts[(size_t)j * N + i] = bins[i];
+    for (int i = t; i < K; i += kSortThreads) counts[(size_t)j0 * N + i] = L.bins[i];
     uint32_t total;
-    uint32_t run = (uint32_t)q0 + block_exclusive_scan(sum, lw, total);
+    uint32_t run = (uint32_t)q0 + block_exclusive_scan(sum, L.lw, total);
 #pragma unroll
     for (int k = 0; k < kColsPer; ++k)
-        if (k < per && i0 + k < N) {
-            bins[i0 + k] = run;
+        if (k < per && i0 + k < K) {
+            L.bins[i0 + k] = run;
             run += c[k];
         }
     __syncthreads();
@@ -597,7 +644,7 @@ __global__ __launch_bounds__(kSortThreads) void k_row_sort(const float2* __restr
         for (int k = 0; k < kSortHeld; ++k) {
             const int64_t q = q0 + t + k * kSortThreads;
             if (q < q1) {
-                const uint32_t slot = atomicAdd(&bins[col[k]], 1u);
+                const uint32_t slot = atomicAdd(&L.bins[col[k]], 1u);
                 sxy[slot] = v[k];
                 perm[slot] = from[k];
             }
@@ -605,12 +652,24 @@ __global__ __launch_bounds__(kSortThreads) void k_row_sort(const float2* __restr
     } else {
         for (int64_t q = q0 + t; q < q1; q += kSortThreads) {
             const float2 p = stage[q];
-            const uint32_t slot = atomicAdd(&bins[texel_of(p.x, N)], 1u);
+            const uint32_t slot = atomicAdd(&L.bins[key(p)], 1u);
             sxy[slot] = p;
             perm[slot] = idx[q];
         }
     }
-    for (int i = t; i < N; i += kSortThreads) t1[(size_t)j * N + i] = defect_texel(i, j, N);
+    if (t1 != nullptr)
+        for (int i = t; i < K; i += kSortThreads) t1[(size_t)j0 * N + i] = defect_texel(i % N, j0 + i / N, N);
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_row_sort(const float2* __restrict__ stage,
+                                                            const uint32_t* __restrict__ idx,
+                                                            const uint32_t* __restrict__ rowstart, int64_t n, int N,
+                                                            uint32_t* __restrict__ counts, float2* __restrict__ sxy,
+                                                            uint32_t* __restrict__ perm, float2* __restrict__ t1,
+                                                            const int* status) {
+    __shared__ RowSortLds L;
+    if (failed(status)) return;
+    row_sort_body(stage, idx, rowstart, n, N, counts, sxy, perm, t1, blockIdx.x, L);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -671,24 +730,21 @@ static void launch_scan(const uint32_t* a, size_t m, uint32_t* partial, uint32_t
     }
 }
 
-bool row_sort_fits(int N) { return N >= 256 && N <= kRowSortMaxN; }
-
 hipError_t launch_sort_by_texel(const float2* xy, int64_t n, int N, uint32_t* counts, uint32_t* map,
                                 uint32_t* offsets, uint32_t* partial, uint32_t* rows, float2* sxy, float2* stage,
                                 uint32_t* idx, float2* t1, int* status, hipStream_t st) {
     if (row_sort_fits(N)) {
         // N * kRowTiles <= N * N words of tile counts and offsets
-        const int64_t tile = n > 0 ? (n + kRowTiles - 1) / kRowTiles : 1;
         // tile counts in `counts` (whose rows k_row_sort rewrites), their
         // prefixes in `offsets`, row totals and row starts in `rows`
         uint32_t *rowtot = rows, *rowstart = rows + N;
         hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, counts, (size_t)0, status, 1);
-        hipLaunchKernelGGL(k_row_hist, dim3(kRowTiles), dim3(kRowThreads), 0, st, xy, n, N, tile, counts, status);
+        hipLaunchKernelGGL(k_row_hist, dim3(kRowTiles), dim3(kRowThreads), 0, st, xy, n, N, counts, status);
         hipLaunchKernelGGL(k_row_scan, dim3(N / kScanRows), dim3(256), 0, st, counts, N, offsets, rowtot, status);
-        hipLaunchKernelGGL(k_row_bucket, dim3(kRowTiles), dim3(kRowThreads), 0, st, xy, n, N, tile, offsets, rowtot,
+        hipLaunchKernelGGL(k_row_bucket, dim3(kRowTiles), dim3(kRowThreads), 0, st, xy, n, N, offsets, rowtot,
                            rowstart, stage, idx, status);
-        hipLaunchKernelGGL(k_row_sort, dim3(N), dim3(kSortThreads), 0, st, stage, idx, rowstart, n, N, counts, sxy,
-                           map, t1, status);
+        hipLaunchKernelGGL(k_row_sort, dim3(N / row_group(n, N)), dim3(kSortThreads), 0, st, stage, idx, rowstart,
+                           n, N, counts, sxy, map, t1, status);
         return hipGetLastError();
     }
     const size_t m = (size_t)N * N;  // a multiple of 4 (N >= 2, a power of two)
@@ -703,10 +759,13 @@ hipError_t launch_sort_by_texel(const float2* xy, int64_t n, int N, uint32_t* co
 // ------------------------------------------------------------------ batched (scatterplot matrix)
 // One launch per stage for all plots of a BatchTable; each block runs the
 // single-plot body for its plot with its block index among that plot's.
+// Block 0 of the launch clears the status word; plots sorted by rows get one
+// block and nothing to fill.
 __global__ __launch_bounds__(256) void kb_fill(const BatchTable* __restrict__ T, int* status) {
     int64_t bid, nblk;
     const BatchPlot& P = batch_locate(T, kBFill, blockIdx.x, bid, nblk);
-    fill_body(P.counts[0], (size_t)P.N * P.N, status, blockIdx.x == 0 ? 1 : 0, bid, nblk);
+    const size_t count = row_sort_fits(P.N) ? 0 : (size_t)P.N * P.N;
+    fill_body(P.counts[0], count, status, blockIdx.x == 0 ? 1 : 0, bid, nblk);
 }
 
 __global__ __launch_bounds__(256) void kb_splat_rank(const BatchTable* __restrict__ T, int* status) {
@@ -747,6 +806,44 @@ __global__ __launch_bounds__(256) void kb_scatter(const BatchTable* __restrict__
     scatter_sorted_body(reinterpret_cast<const float2*>(P.xy), P.n, P.N, P.rank, P.counts[1], P.sxy, bid, nblk);
 }
 
+// The row sort of every plot with row_sort_fits(N): tile counts in counts[0],
+// prefixes in counts[1], row totals and starts in the density raster (free
+// until the first smoothing), as in the single-plot call.
+__global__ __launch_bounds__(kRowThreads) void kb_row_hist(const BatchTable* __restrict__ T, int* status) {
+    __shared__ uint32_t bins[kRowSortMaxN];
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBRowHist, blockIdx.x, bid, nblk);
+    row_hist_body(reinterpret_cast<const float2*>(P.xy), P.n, P.N, P.counts[0], status, bid, bins);
+}
+
+__global__ __launch_bounds__(256) void kb_row_scan(const BatchTable* __restrict__ T, const int* status) {
+    __shared__ RowScanLds L;
+    if (failed(status)) return;
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBRowScan, blockIdx.x, bid, nblk);
+    row_scan_body(P.counts[0], P.N, P.counts[1], reinterpret_cast<uint32_t*>(P.density), bid, L);
+}
+
+__global__ __launch_bounds__(kRowThreads) void kb_row_bucket(const BatchTable* __restrict__ T, const int* status) {
+    __shared__ RowBucketLds L;
+    if (failed(status)) return;
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBRowBucket, blockIdx.x, bid, nblk);
+    uint32_t* rows = reinterpret_cast<uint32_t*>(P.density);
+    row_bucket_body(reinterpret_cast<const float2*>(P.xy), P.n, P.N, P.counts[1], rows, rows + P.N, P.stage, P.idx,
+                    bid, L);
+}
+
+__global__ __launch_bounds__(kSortThreads) void kb_row_sort(const BatchTable* __restrict__ T, const int* status) {
+    __shared__ RowSortLds L;
+    if (failed(status)) return;
+    int64_t bid, nblk;
+    const BatchPlot& P = batch_locate(T, kBRowSort, blockIdx.x, bid, nblk);
+    const uint32_t* rowstart = reinterpret_cast<const uint32_t*>(P.density) + P.N;
+    row_sort_body(P.stage, P.idx, rowstart, P.n, P.N, P.counts[0], P.sxy, P.rank, P.defect_owner ? P.defect : nullptr,
+                  (int)bid, L);
+}
+
 __global__ __launch_bounds__(256) void kb_advect(const BatchTable* __restrict__ T, int it, int iters,
                                                  const int* status) {
     if (failed(status)) return;
@@ -760,7 +857,10 @@ __global__ __launch_bounds__(256) void kb_unpermute(const BatchTable* __restrict
     if (failed(status)) return;
     int64_t bid, nblk;
     const BatchPlot& P = batch_locate(T, kBUnpermute, blockIdx.x, bid, nblk);
-    unpermute_body(P.sxy, P.rank, P.n, reinterpret_cast<float2*>(P.xy), bid, nblk);
+    if (row_sort_fits(P.N))  // rank holds the sample of every slot
+        unpermute_scatter_body(P.sxy, P.rank, P.n, reinterpret_cast<float2*>(P.xy), bid, nblk);
+    else  // rank holds the slot of every sample
+        unpermute_body(P.sxy, P.rank, P.n, reinterpret_cast<float2*>(P.xy), bid, nblk);
 }
 
 hipError_t launch_batch_raster(int stage, const BatchTable* T, unsigned blocks, int it, int iters, int* status,
@@ -775,6 +875,10 @@ hipError_t launch_batch_raster(int stage, const BatchTable* T, unsigned blocks, 
         case kBScanPartials: hipLaunchKernelGGL(kb_scan_partials, dim3(blocks), dim3(1024), 0, st, T, status); break;
         case kBScanDown: hipLaunchKernelGGL(kb_scan_down, dim3(blocks), dim3(kScanThreads), 0, st, T, status); break;
         case kBScatter: hipLaunchKernelGGL(kb_scatter, dim3(blocks), dim3(256), 0, st, T, status); break;
+        case kBRowHist: hipLaunchKernelGGL(kb_row_hist, dim3(blocks), dim3(kRowThreads), 0, st, T, status); break;
+        case kBRowScan: hipLaunchKernelGGL(kb_row_scan, dim3(blocks), dim3(256), 0, st, T, status); break;
+        case kBRowBucket: hipLaunchKernelGGL(kb_row_bucket, dim3(blocks), dim3(kRowThreads), 0, st, T, status); break;
+        case kBRowSort: hipLaunchKernelGGL(kb_row_sort, dim3(blocks), dim3(kSortThreads), 0, st, T, status); break;
         case kBAdvect: hipLaunchKernelGGL(kb_advect, dim3(blocks), dim3(256), 0, st, T, it, iters, status); break;
         case kBUnpermute: hipLaunchKernelGGL(kb_unpermute, dim3(blocks), dim3(256), 0, st, T, status); break;
         default: return hipErrorInvalidValue;

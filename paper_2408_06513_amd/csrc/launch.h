@@ -77,7 +77,6 @@ hipError_t launch_validate(const float2* xy, int64_t n, int* status, hipStream_t
 // (n words) are scratch; otherwise (ranks by global atomics) map[p] is the
 // slot of sample p.  `offsets` (N * N words), `partial` (scan_partials(N * N)
 // words) and `rows` (2 N words) are scratch.
-bool row_sort_fits(int N);
 hipError_t launch_sort_by_texel(const float2* xy, int64_t n, int N, uint32_t* counts, uint32_t* map,
                                 uint32_t* offsets, uint32_t* partial, uint32_t* rows, float2* sxy, float2* stage,
                                 uint32_t* idx, float2* t1, int* status, hipStream_t st);

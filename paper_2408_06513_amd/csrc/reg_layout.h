@@ -10,6 +10,22 @@ namespace inim {
 constexpr size_t kStatusBytes = 256;
 constexpr int kScanThreads = 256, kScanBlock = 4 * kScanThreads;
 
+// The texel sort by rows (rasters with row_sort_fits(N)): kRowTiles sample
+// tiles, per-row and per-column LDS counters of at most kRowSortMaxN entries,
+// kScanRows rows per block of the tile-count scan.
+constexpr int kRowTiles = 256, kRowSortMaxN = 4096, kScanRows = 8;
+__host__ __device__ inline bool row_sort_fits(int N) { return N >= 256 && N <= kRowSortMaxN; }
+// Rows per block of the per-row sort: consecutive rows are one row-major run
+// of texels, so a block takes a group of them, at most 1024 samples on
+// average and at most kRowSortMaxN texels (a power of two that divides N).
+// Larger groups leave dense rows to fewer, longer blocks.
+__host__ __device__ inline int row_group(int64_t n, int N) {
+    const int64_t mean = n / N;
+    int g = 1;
+    while (2 * g * N <= kRowSortMaxN && 2 * g * mean <= 1024) g *= 2;
+    return g;
+}
+
 // Blocks of the per-block partial sums of an exclusive scan over m words.
 __host__ __device__ inline size_t scan_partials(size_t m) { return (m + kScanBlock - 1) / kScanBlock; }
 
