@@ -373,10 +373,11 @@ __global__ __launch_bounds__(256) void k_unpermute_scatter(const float2* __restr
 // on it.  Rasters with row_sort_fits(N) (LDS counters per row and column).
 // Each body takes its block's index among the blocks of its plot.
 constexpr int kRowThreads = 1024;
-// row_bucket moves the samples of its tile in chunks of kRowChunk, each first
-// ordered by row in LDS, so that consecutive lanes write consecutive slots
-// (56 KB of LDS: two blocks per CU).
-constexpr int kRowChunk = 2048;
+// row_bucket moves the samples of its tile in chunks of CHUNK samples, each
+// first ordered by row in LDS, so that consecutive lanes write consecutive
+// slots: chunks of 4096 for tiles of more than 2048 samples (longer runs),
+// else 2048 (56 KB of LDS: two blocks per CU).
+constexpr int kRowChunkSmall = 2048, kRowChunkLarge = 4096;
 // row_scan: a block of 256 threads takes kScanRows rows; their counts over
 // all tiles go through LDS (loads and stores of kScanRows consecutive words
 // per tile), kScanParts threads scan a row, kScanTiles tiles each.
@@ -468,20 +469,22 @@ __global__ __launch_bounds__(256) void k_row_scan(const uint32_t* __restrict__ h
 // Tile b's samples to their row runs; the block of tile 0 also stores
 // rowstart for row_sort.  Every sample is in the unit square here (callers
 // run it only when the status word is clear).
+template <int CHUNK>
 struct RowBucketLds {
     uint32_t cnt[kRowSortMaxN];   // per row: count in the chunk, its first LDS slot, then stage minus LDS slot
     uint32_t next[kRowSortMaxN];  // per row: the tile's next slot in `stage`
-    float2 lxy[kRowChunk];
-    uint32_t lidx[kRowChunk];
+    float2 lxy[CHUNK];
+    uint32_t lidx[CHUNK];
     uint32_t lw[33];
 };
 
+template <int CHUNK>
 __device__ __forceinline__ void row_bucket_body(const float2* __restrict__ xy, int64_t n, int N,
                                                 const uint32_t* __restrict__ prefix,
                                                 const uint32_t* __restrict__ rowtot, uint32_t* __restrict__ rowstart,
                                                 float2* __restrict__ stage, uint32_t* __restrict__ idx, int64_t b,
-                                                RowBucketLds& L) {
-    constexpr int kPer = kRowChunk / kRowThreads, kRowsPer = kRowSortMaxN / kRowThreads;
+                                                RowBucketLds<CHUNK>& L) {
+    constexpr int kPer = CHUNK / kRowThreads, kRowsPer = kRowSortMaxN / kRowThreads;
     const int per = (N + kRowThreads - 1) / kRowThreads, r0 = threadIdx.x * per;
     {
         uint32_t v[kRowsPer];
@@ -503,8 +506,8 @@ __device__ __forceinline__ void row_bucket_body(const float2* __restrict__ xy, i
             }
     }
     const int64_t tile = row_tile(n), p0 = b * tile, p1 = min(n, p0 + tile);
-    for (int64_t c0 = p0; c0 < p1; c0 += kRowChunk) {
-        const int m = (int)min((int64_t)kRowChunk, p1 - c0);
+    for (int64_t c0 = p0; c0 < p1; c0 += CHUNK) {
+        const int m = (int)min((int64_t)CHUNK, p1 - c0);
         for (int j = threadIdx.x; j < N; j += kRowThreads) L.cnt[j] = 0u;
         __syncthreads();
         float2 q[kPer];
@@ -568,15 +571,16 @@ __device__ __forceinline__ void row_bucket_body(const float2* __restrict__ xy, i
     }
 }
 
+template <int CHUNK>
 __global__ __launch_bounds__(kRowThreads) void k_row_bucket(const float2* __restrict__ xy, int64_t n, int N,
                                                              const uint32_t* __restrict__ prefix,
                                                              const uint32_t* __restrict__ rowtot,
                                                              uint32_t* __restrict__ rowstart,
                                                              float2* __restrict__ stage, uint32_t* __restrict__ idx,
                                                              const int* status) {
-    __shared__ RowBucketLds L;
+    __shared__ RowBucketLds<CHUNK> L;
     if (failed(status)) return;
-    row_bucket_body(xy, n, N, prefix, rowtot, rowstart, stage, idx, blockIdx.x, L);
+    row_bucket_body<CHUNK>(xy, n, N, prefix, rowtot, rowstart, stage, idx, blockIdx.x, L);
 }
 
 // Rows [g blk, g blk + g) to texel order, g = row_group(n, N); also those
@@ -741,8 +745,13 @@ hipError_t launch_sort_by_texel(const float2* xy, int64_t n, int N, uint32_t* co
         hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, counts, (size_t)0, status, 1);
         hipLaunchKernelGGL(k_row_hist, dim3(kRowTiles), dim3(kRowThreads), 0, st, xy, n, N, counts, status);
         hipLaunchKernelGGL(k_row_scan, dim3(N / kScanRows), dim3(256), 0, st, counts, N, offsets, rowtot, status);
-        hipLaunchKernelGGL(k_row_bucket, dim3(kRowTiles), dim3(kRowThreads), 0, st, xy, n, N, offsets, rowtot,
-                           rowstart, stage, idx, status);
+        const int64_t tile = n > 0 ? (n + kRowTiles - 1) / kRowTiles : 1;  // as row_tile(n)
+        if (tile > kRowChunkSmall)
+            hipLaunchKernelGGL(k_row_bucket<kRowChunkLarge>, dim3(kRowTiles), dim3(kRowThreads), 0, st, xy, n, N,
+                               offsets, rowtot, rowstart, stage, idx, status);
+        else
+            hipLaunchKernelGGL(k_row_bucket<kRowChunkSmall>, dim3(kRowTiles), dim3(kRowThreads), 0, st, xy, n, N,
+                               offsets, rowtot, rowstart, stage, idx, status);
         hipLaunchKernelGGL(k_row_sort, dim3(N / row_group(n, N)), dim3(kSortThreads), 0, st, stage, idx, rowstart,
                            n, N, counts, sxy, map, t1, status);
         return hipGetLastError();
@@ -825,13 +834,13 @@ __global__ __launch_bounds__(256) void kb_row_scan(const BatchTable* __restrict_
 }
 
 __global__ __launch_bounds__(kRowThreads) void kb_row_bucket(const BatchTable* __restrict__ T, const int* status) {
-    __shared__ RowBucketLds L;
+    __shared__ RowBucketLds<kRowChunkSmall> L;
     if (failed(status)) return;
     int64_t bid, nblk;
     const BatchPlot& P = batch_locate(T, kBRowBucket, blockIdx.x, bid, nblk);
     uint32_t* rows = reinterpret_cast<uint32_t*>(P.density);
-    row_bucket_body(reinterpret_cast<const float2*>(P.xy), P.n, P.N, P.counts[1], rows, rows + P.N, P.stage, P.idx,
-                    bid, L);
+    row_bucket_body<kRowChunkSmall>(reinterpret_cast<const float2*>(P.xy), P.n, P.N, P.counts[1], rows, rows + P.N,
+                                    P.stage, P.idx, bid, L);
 }
 
 __global__ __launch_bounds__(kSortThreads) void kb_row_sort(const BatchTable* __restrict__ T, const int* status) {
