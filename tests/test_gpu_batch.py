@@ -106,6 +106,23 @@ def test_batch_full_splom_equals_sequential(capi, dev):
         assert np.array_equal(x.cpu().numpy(), ref[k]), k
 
 
+def test_batch_grouped_rows_and_both_sorts(capi, dev):
+    """Plots whose per-row sort takes groups of rows (few samples on 2048^2
+    and 512^2), one with dense rows, and 128^2 plots sorted by global ranks,
+    in one batched call: bit-identical to one call per plot."""
+    g = np.random.Generator(np.random.PCG64(11))
+    dense = np.stack([g.random(30_000), 0.5 + g.random(30_000) / 700], 1).astype(np.float32)
+    plots = [(dg.plain_small(1)[:3_000], 2048), (dg.plain_small(2)[:9], 512), (dense, 512),
+             (dg.plain_small(3)[:5_000], 128), (dg.plain_small(4), 2048)]
+    iters = 2
+    ref = sequential(capi, dev, plots, iters)
+    xs = [to_dev(xy, dev) for xy, _ in plots]
+    note("grouped rows, dense rows and both sorts in one batch")
+    capi.regularize_batch(xs, [r for _, r in plots], iters)
+    for k, x in enumerate(xs):
+        assert np.array_equal(x.cpu().numpy(), ref[k]), k
+
+
 def test_batch_autotune_leaves_samples(capi, dev, small_splom):
     res = [r for _, r in small_splom]
     xs = [to_dev(xy, dev) for xy, _ in small_splom]
