@@ -380,6 +380,14 @@ def bench_surrogate(dev, train_sets: int = 1024, steps: int = 3000, held_out: in
             x.copy_(x0)
         S.regularize_many(net, xs, res, net_res=net_res)
     t_batch = ev_time(many, 3) / len(xs)
+    sgm = S.SurrogateManyGraph(net, xs, res, net_res)
+
+    def many_graph():
+        for x, x0 in zip(xs, xs0):
+            x.copy_(x0)
+        sgm()
+    t_batch_graph = ev_time(many_graph, 3) / len(xs)
+    del sgm
     # the method on the same sets in one batched call (its scatterplot-matrix entry point)
     wsb = capi.workspace(capi.batch_workspace_size(xs, [res] * len(xs)), dev)
     cfg, _ = capi.batch_autotune(xs, [res] * len(xs), iters, ws=wsb)
@@ -403,11 +411,12 @@ def bench_surrogate(dev, train_sets: int = 1024, steps: int = 3000, held_out: in
            "surrogate_graph_ms_per_raster": round(mean(sur_graph_ms), 4),
            "surrogate_gated_ms_per_raster": round(mean(gated_ms), 4),
            f"surrogate_ms_per_raster_batch{held_out}": round(t_batch, 4),
+           f"surrogate_graph_ms_per_raster_batch{held_out}": round(t_batch_graph, 4),
            f"plain_batched_ms_per_raster_batch{held_out}": round(t_plain_batch, 4)}
     best_plain = min(rec["plain_ms_per_raster"], rec["plain_graph_ms_per_raster"])
     rec["speedup_vs_plain"] = round(best_plain / rec["surrogate_graph_ms_per_raster"], 3)
     rec["speedup_vs_plain_eager"] = round(rec["plain_ms_per_raster"] / rec["surrogate_ms_per_raster"], 3)
-    rec[f"speedup_vs_plain_batch{held_out}"] = round(min(best_plain, t_plain_batch) / t_batch, 3)
+    rec[f"speedup_vs_plain_batch{held_out}"] = round(min(best_plain, t_plain_batch) / min(t_batch, t_batch_graph), 3)
     return rec
 
 

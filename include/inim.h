@@ -172,6 +172,28 @@ int inim_advect(const float* field, int32_t res, float* xy, int64_t n, void* ws,
                 size_t ws_bytes, hipStream_t stream);
 
 /*
+ * inim_rasterize for `count` sample sets in shared launches (the surrogate's
+ * input for a batch of scatterplots): set q has n[q] samples at xy[q] (host
+ * arrays of device pointers and sizes, 1 <= count <= 64), and its counts and
+ * density are the q-th res x res raster of `counts` (uint32 [count][res][res])
+ * and `density` (float [count][res][res], may be NULL).  Each raster is the
+ * one inim_rasterize gives for that set; a NaN or out-of-range sample in any
+ * set sets the one status word (EDOMAIN).  ws: at least 256 bytes.
+ */
+int inim_rasterize_many(float* const* xy, const int64_t* n, int32_t count, int32_t res, const inim_params* p,
+                        uint32_t* counts, float* density, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * inim_advect for `count` sample sets in shared launches: set q (n[q]
+ * samples at xy[q], host arrays as in inim_rasterize_many) moves through the
+ * q-th field of `field` (float [count][res][res][2]), in place.  If any sample
+ * of any set is NaN or outside [0,1]^2 the status word is set (EDOMAIN) and
+ * no sample is modified.  ws: at least 256 bytes.
+ */
+int inim_advect_many(const float* field, int32_t res, float* const* xy, const int64_t* n, int32_t count, void* ws,
+                     size_t ws_bytes, hipStream_t stream);
+
+/*
  * The whole algorithm (Sec. 4.3): `iters` times splat + smooth, integral
  * images, per-texel deformation and bilinear advection, in place on xy.
  *   xy     device, float [n][2], updated in place.

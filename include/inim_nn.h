@@ -112,6 +112,12 @@ int inim_adam(float* weight, const float* grad, float* m, float* v, int64_t n, f
  * x [res][res][c] = bfloat16(density * scale), the other channels 0. */
 int inim_nn_pack_density(const float* density, int32_t res, float scale, int32_t c, inim_bf16* x, hipStream_t stream);
 
+/* inim_nn_pack_density for a stack of `count` rasters (1..64): density
+ * [count][res][res], x [count][res][res][c], raster q scaled by scale[q]
+ * (host array). */
+int inim_nn_pack_density_many(const float* density, int32_t count, int32_t res, const float* scale, int32_t c,
+                              inim_bf16* x, hipStream_t stream);
+
 /* Training target from probes started at the texel centres and moved by the
  * whole iteration (inim_regularize_probes): out [res][res][2] = (probe -
  * texel centre) * 64, the displacement in units of 1/64 of the unit square
@@ -126,6 +132,12 @@ int inim_nn_displacement(const float* probe, int32_t res, float* out, hipStream_
  * [res][res][2] for the intermediate pass. */
 int inim_nn_field(const float* y, int32_t c, int32_t res, int32_t radius, float* field, float* work,
                   hipStream_t stream);
+
+/* inim_nn_field for a stack of `count` outputs (1..65535): y
+ * [count][res][res][c], field and work [count][res][res][2]; field q is the
+ * one inim_nn_field gives for y[q]. */
+int inim_nn_field_many(const float* y, int32_t count, int32_t c, int32_t res, int32_t radius, float* field, float* work,
+                       hipStream_t stream);
 
 /* Adds to *count (device) the number of lattice triangles (two per cell) of
  * the deformed texel lattice `field` with non-positive signed area (folds). */

@@ -31,6 +31,7 @@ EXPORTS = (
     "inim_deform", "inim_advect", "inim_regularize", "inim_regularize_timed", "inim_sync_status",
     "inim_graph_create", "inim_graph_destroy", "inim_regularize_graph", "inim_regularize_probes",
     "inim_batch_workspace_size", "inim_regularize_batch", "inim_batch_autotune",
+    "inim_rasterize_many", "inim_advect_many",
 )
 
 
@@ -104,6 +105,8 @@ def lib() -> ctypes.CDLL:
     L.inim_inim_f32.argtypes = [vp, i32, u32, vp, vp, vp, sz, vp]
     L.inim_deform.argtypes = [vp, vp, ctypes.c_int, vp, i32, f64, vp, vp]
     L.inim_advect.argtypes = [vp, i32, vp, i64, vp, sz, vp]
+    L.inim_rasterize_many.argtypes = [vp, vp, i32, i32, pp, vp, vp, vp, sz, vp]
+    L.inim_advect_many.argtypes = [vp, i32, vp, vp, i32, vp, sz, vp]
     L.inim_regularize.argtypes = [vp, i64, i32, i32, pp, vp, sz, vp]
     L.inim_regularize_timed.argtypes = [vp, i64, i32, i32, pp, vp, sz, vp, ctypes.POINTER(f64)]
     L.inim_sync_status.argtypes = [vp, vp]
@@ -240,6 +243,44 @@ def advect(field: torch.Tensor, xy: torch.Tensor, ws=None) -> torch.Tensor:
         ws = workspace(256, xy.device)
     _check(lib().inim_advect(_ptr(field), res, _ptr(xy), n, _ptr(ws), ws.numel(), _stream(xy)))
     return xy
+
+
+def _sets(xys):
+    """Host arrays of the device pointers and sizes of several sample sets."""
+    ns = [_xy(t) for t in xys]
+    if len({t.device for t in xys}) > 1:
+        raise ValueError("all sets must be on one device")
+    k = len(xys)
+    return (ctypes.c_void_p * k)(*[t.data_ptr() for t in xys]), (ctypes.c_int64 * k)(*ns), k
+
+
+def rasterize_many(xys, res: int, radius: int = 8, sigma=None, counts=None, density=None, ws=None,
+                   want_density: bool = True):
+    """rasterize for several sample sets in shared launches: counts (uint32
+    [k, res, res]) and densities (float32 [k, res, res]), raster q for xys[q]."""
+    a, n, k = _sets(xys)
+    dev = xys[0].device
+    if counts is None:
+        counts = torch.empty((k, res, res), dtype=torch.uint32, device=dev)
+    if density is None and want_density:
+        density = torch.empty((k, res, res), dtype=torch.float32, device=dev)
+    if ws is None:
+        ws = workspace(256, dev)
+    p = params(radius, sigma)
+    _check(lib().inim_rasterize_many(a, n, k, res, ctypes.byref(p), _ptr(counts), _ptr(density), _ptr(ws),
+                                     ws.numel(), _stream(ws)))
+    return counts, density, ws
+
+
+def advect_many(field: torch.Tensor, xys, ws=None):
+    """advect for several sample sets in shared launches: xys[q] moves (in
+    place) through field[q] ([k, res, res, 2])."""
+    a, n, k = _sets(xys)
+    res = field.shape[1]
+    if ws is None:
+        ws = workspace(256, xys[0].device)
+    _check(lib().inim_advect_many(_ptr(field), res, a, n, k, _ptr(ws), ws.numel(), _stream(ws)))
+    return xys
 
 
 def regularize(xy: torch.Tensor, res: int, iters: int, radius: int = 8, sigma=None, d0=None,

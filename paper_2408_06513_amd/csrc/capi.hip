@@ -475,6 +475,59 @@ int inim_rasterize(const float* xy, int64_t n, int32_t res, const inim_params* p
     return INIM_OK;
 }
 
+// The sets of a *_many call, checked, into a SetTable.
+static int set_table(float* const* xy, const int64_t* n, int32_t count, SetTable& t) {
+    if (count < 1 || count > kMaxSets) return fail(INIM_EINVAL, "count=%d outside [1, %d]", (int)count, kMaxSets);
+    if (xy == nullptr || n == nullptr) return fail(INIM_EINVAL, "xy or n is NULL");
+    t.count = count;
+    for (int q = 0; q < count; ++q) {
+        int s;
+        if ((s = check_xy(xy[q], n[q])) != INIM_OK) return s;
+        t.xy[q] = reinterpret_cast<float2*>(xy[q]);
+        t.n[q] = n[q];
+    }
+    return INIM_OK;
+}
+
+int inim_rasterize_many(float* const* xy, const int64_t* n, int32_t count, int32_t res, const inim_params* p,
+                        uint32_t* counts, float* density, void* ws, size_t ws_bytes, hipStream_t stream) {
+    int s;
+    if ((s = check_res(res)) != INIM_OK) return s;
+    SetTable t;
+    if ((s = set_table(xy, n, count, t)) != INIM_OK) return s;
+    if (counts == nullptr) return fail(INIM_EINVAL, "counts is NULL");
+    Params P;
+    if ((s = resolve_params(p, P)) != INIM_OK) return s;
+    if ((s = check_ws(ws, ws_bytes, kStatusBytes)) != INIM_OK) return s;
+    int* status = reinterpret_cast<int*>(ws);
+    const size_t NN = (size_t)res * res;
+    hipError_t e;
+    if ((e = launch_fill(counts, NN * count, status, true, stream)) != hipSuccess) return hip_fail(e, "fill");
+    if ((e = launch_splat_many(t, res, counts, status, stream)) != hipSuccess) return hip_fail(e, "splat");
+    if (density != nullptr) {
+        const BlurTaps taps = make_taps(P.radius, P.sigma);
+        if ((e = launch_blur_many(counts, density, res, count, taps, status, stream)) != hipSuccess)
+            return hip_fail(e, "blur");
+    }
+    return INIM_OK;
+}
+
+int inim_advect_many(const float* field, int32_t res, float* const* xy, const int64_t* n, int32_t count, void* ws,
+                     size_t ws_bytes, hipStream_t stream) {
+    int s;
+    if ((s = check_res(res)) != INIM_OK) return s;
+    SetTable t;
+    if ((s = set_table(xy, n, count, t)) != INIM_OK) return s;
+    if (field == nullptr) return fail(INIM_EINVAL, "field is NULL");
+    if ((s = check_ws(ws, ws_bytes, kStatusBytes)) != INIM_OK) return s;
+    int* status = reinterpret_cast<int*>(ws);
+    hipError_t e;
+    if ((e = launch_fill(nullptr, 0, status, true, stream)) != hipSuccess) return hip_fail(e, "fill");
+    if ((e = launch_advect_many(t, reinterpret_cast<const float2*>(field), res, status, stream)) != hipSuccess)
+        return hip_fail(e, "advect");
+    return INIM_OK;
+}
+
 static int inim_common(const void* img, int32_t res, uint32_t mask, const void* planes, void* ws, size_t ws_bytes,
                        inim_dtype dt) {
     int s;

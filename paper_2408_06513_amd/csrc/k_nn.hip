@@ -553,6 +553,25 @@ __global__ __launch_bounds__(256) void k_pack_density(const float* __restrict__ 
     }
 }
 
+// The same for a stack of rasters, raster z (blockIdx.y) with scale[z].
+constexpr int kMaxScales = 64;
+struct Scales {
+    float v[kMaxScales];
+};
+
+__global__ __launch_bounds__(256) void k_pack_density_many(const float* __restrict__ d, size_t pixels, Scales sc,
+                                                           int C, uint16_t* __restrict__ x) {
+    const int z = blockIdx.y;
+    const float scale = sc.v[z];
+    d += (size_t)z * pixels;
+    x += (size_t)z * pixels * C;
+    const size_t n = pixels * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t p = i / C;
+        x[i] = (i - p * C) == 0 ? f2bf(d[p] * scale) : (uint16_t)0;
+    }
+}
+
 // Displacements are expressed in units of 1/64 of the unit square, so that
 // targets of every raster size have the same scale.
 constexpr float kDispUnit = 64.0f;
@@ -572,6 +591,8 @@ __global__ __launch_bounds__(256) void k_displacement(const float2* __restrict__
 // (smoothed output[p][0..1]) / 64, the output convolved along x, then along
 // y, with the normalised taps w[0..2r] (indices clamped at the border); the
 // x pass goes to tmp [N][N][2].  Channels beyond the first two are ignored.
+// blockIdx.y selects the output of a stack (y [N][N][C], tmp and field
+// [N][N][2] per output).
 struct FieldTaps {
     int r;
     float w[33];
@@ -580,6 +601,8 @@ struct FieldTaps {
 __global__ __launch_bounds__(256) void k_field_smooth_x(const float* __restrict__ y, int C, int N, FieldTaps t,
                                                         float2* __restrict__ tmp) {
     const size_t n = (size_t)N * N;
+    y += (size_t)blockIdx.y * n * C;
+    tmp += (size_t)blockIdx.y * n;
     for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
         const int j = (int)(p / N), i = (int)(p - (size_t)j * N);
         float ax = 0.0f, ay = 0.0f;
@@ -595,6 +618,8 @@ __global__ __launch_bounds__(256) void k_field_smooth_x(const float* __restrict_
 __global__ __launch_bounds__(256) void k_field_smooth_y(const float2* __restrict__ tmp, int N, FieldTaps t,
                                                         float2* __restrict__ field) {
     const size_t n = (size_t)N * N;
+    tmp += (size_t)blockIdx.y * n;
+    field += (size_t)blockIdx.y * n;
     for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
         const int j = (int)(p / N), i = (int)(p - (size_t)j * N);
         float ax = 0.0f, ay = 0.0f;
@@ -940,6 +965,18 @@ int inim_nn_pack_density(const float* density, int32_t res, float scale, int32_t
     return launched("pack density");
 }
 
+int inim_nn_pack_density_many(const float* density, int32_t count, int32_t res, const float* scale, int32_t c,
+                              inim_bf16* x, hipStream_t stream) {
+    if (!density || !x || !scale || res < 2 || c < 1 || count < 1 || count > kMaxScales)
+        return nfail(INIM_EINVAL, "bad input-packing arguments");
+    Scales sc{};
+    for (int q = 0; q < count; ++q) sc.v[q] = scale[q];
+    const size_t px = (size_t)res * res;
+    hipLaunchKernelGGL(k_pack_density_many, dim3(grid_1d((int64_t)(px * c)), count), dim3(256), 0, stream, density, px,
+                       sc, c, x);
+    return launched("pack density");
+}
+
 int inim_nn_displacement(const float* probe, int32_t res, float* out, hipStream_t stream) {
     if (!probe || !out || res < 2) return nfail(INIM_EINVAL, "bad displacement arguments");
     hipLaunchKernelGGL(k_displacement, dim3(grid_1d((int64_t)res * res)), dim3(256), 0, stream,
@@ -947,10 +984,8 @@ int inim_nn_displacement(const float* probe, int32_t res, float* out, hipStream_
     return launched("displacement");
 }
 
-int inim_nn_field(const float* y, int32_t c, int32_t res, int32_t radius, float* field, float* work,
-                  hipStream_t stream) {
-    if (!y || !field || !work || res < 2 || c < 2 || radius < 0 || radius > 16)
-        return nfail(INIM_EINVAL, "bad field arguments");
+static hipError_t launch_field(const float* y, int c, int res, int radius, int k, float* field, float* work,
+                               hipStream_t stream) {
     FieldTaps t{};
     t.r = radius;
     double w[33], s = 0.0;
@@ -958,11 +993,27 @@ int inim_nn_field(const float* y, int32_t c, int32_t res, int32_t radius, float*
         w[m + radius] = radius ? std::exp(-2.0 * m * m / ((double)radius * radius)) : 1.0;
         s += w[m + radius];
     }
-    for (int k = 0; k <= 2 * radius; ++k) t.w[k] = (float)(w[k] / s);
-    const unsigned g = grid_1d((int64_t)res * res);
-    hipLaunchKernelGGL(k_field_smooth_x, dim3(g), dim3(256), 0, stream, y, c, res, t, reinterpret_cast<float2*>(work));
-    hipLaunchKernelGGL(k_field_smooth_y, dim3(g), dim3(256), 0, stream, reinterpret_cast<const float2*>(work), res, t,
+    for (int q = 0; q <= 2 * radius; ++q) t.w[q] = (float)(w[q] / s);
+    const dim3 g(grid_1d((int64_t)res * res), k);
+    hipLaunchKernelGGL(k_field_smooth_x, g, dim3(256), 0, stream, y, c, res, t, reinterpret_cast<float2*>(work));
+    hipLaunchKernelGGL(k_field_smooth_y, g, dim3(256), 0, stream, reinterpret_cast<const float2*>(work), res, t,
                        reinterpret_cast<float2*>(field));
+    return hipGetLastError();
+}
+
+int inim_nn_field(const float* y, int32_t c, int32_t res, int32_t radius, float* field, float* work,
+                  hipStream_t stream) {
+    if (!y || !field || !work || res < 2 || c < 2 || radius < 0 || radius > 16)
+        return nfail(INIM_EINVAL, "bad field arguments");
+    (void)launch_field(y, c, res, radius, 1, field, work, stream);
+    return launched("field");
+}
+
+int inim_nn_field_many(const float* y, int32_t count, int32_t c, int32_t res, int32_t radius, float* field, float* work,
+                       hipStream_t stream) {
+    if (!y || !field || !work || res < 2 || c < 2 || radius < 0 || radius > 16 || count < 1 || count > 65535)
+        return nfail(INIM_EINVAL, "bad field arguments");
+    (void)launch_field(y, c, res, radius, count, field, work, stream);
     return launched("field");
 }
 

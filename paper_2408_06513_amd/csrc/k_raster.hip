@@ -63,6 +63,42 @@ __global__ __launch_bounds__(256) void k_splat(const float2* __restrict__ xy, in
     }
 }
 
+// Rasters of at most kLdsSplatTexels texels: each block counts its samples
+// in an LDS copy of the raster, then adds its non-zero counts to the raster
+// (where many samples share few texels, per-sample atomics on the same words
+// serialise).  At most kLdsSplatBlocks blocks per sample set.
+constexpr int kLdsSplatTexels = 16384;
+constexpr unsigned kLdsSplatBlocks = 64;
+
+__device__ __forceinline__ void splat_lds_body(const float2* __restrict__ xy, int64_t n, int N,
+                                               uint32_t* __restrict__ counts, int* status, int64_t bid, int64_t nblk,
+                                               uint32_t* bins) {
+    const int NN = N * N;
+    for (int k = threadIdx.x; k < NN; k += blockDim.x) bins[k] = 0u;
+    __syncthreads();
+    const int64_t stride = nblk * blockDim.x;
+    for (int64_t p = bid * blockDim.x + threadIdx.x; p < n; p += stride) {
+        const float2 q = xy[p];
+        if (!in_unit_square(q)) {
+            flag_domain(status);
+            continue;
+        }
+        atomicAdd(&bins[texel_of(q.y, N) * N + texel_of(q.x, N)], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < NN; k += blockDim.x) {
+        const uint32_t c = bins[k];
+        if (c != 0u) __hip_atomic_fetch_add(counts + k, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_splat_lds(const float2* __restrict__ xy, int64_t n, int N,
+                                                   uint32_t* __restrict__ counts, int* status) {
+    extern __shared__ uint32_t bins[];
+    if (failed(status)) return;
+    splat_lds_body(xy, n, N, counts, status, blockIdx.x, gridDim.x, bins);
+}
+
 __global__ __launch_bounds__(256) void k_validate(const float2* __restrict__ xy, int64_t n, int* status) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride)
@@ -70,11 +106,14 @@ __global__ __launch_bounds__(256) void k_validate(const float2* __restrict__ xy,
 }
 
 // ------------------------------------------------------------------ blur
-// One 64 x 16 output tile per 256-thread block (blur_tile.h).
+// One 64 x 16 output tile per 256-thread block (blur_tile.h); blockIdx.z
+// selects the raster of a stack of N x N rasters.
 __global__ __launch_bounds__(256) void k_blur(const uint32_t* __restrict__ counts, float* __restrict__ out, int N,
                                               BlurTaps taps, const int* status) {
     extern __shared__ float lds[];
     if (failed(status)) return;
+    counts += (size_t)blockIdx.z * N * N;
+    out += (size_t)blockIdx.z * N * N;
     const int ox = blockIdx.x * kBX, oy = blockIdx.y * kBY;
     blur_tile(counts, N, taps, ox, oy, lds,
               [&](int row, int cc, float v) { out[(size_t)(oy + row) * N + ox + cc] = v; });
@@ -676,6 +715,49 @@ __global__ __launch_bounds__(kSortThreads) void k_row_sort(const float2* __restr
     row_sort_body(stage, idx, rowstart, n, N, counts, sxy, perm, t1, blockIdx.x, L);
 }
 
+// ------------------------------------------------------------------ several sample sets
+// One launch for the sets of a SetTable: blockIdx.y is the set, blockIdx.x
+// strides over its samples; raster q is the q-th of a stack of N x N rasters.
+__global__ __launch_bounds__(256) void k_splat_many(SetTable t, int N, uint32_t* __restrict__ counts, int* status) {
+    const int q = blockIdx.y;
+    const float2* __restrict__ xy = t.xy[q];
+    uint32_t* c = counts + (size_t)q * N * N;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < t.n[q]; p += stride) {
+        const float2 v = xy[p];
+        if (!in_unit_square(v)) {
+            flag_domain(status);
+            continue;
+        }
+        __hip_atomic_fetch_add(c + (size_t)texel_of(v.y, N) * N + texel_of(v.x, N), 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_splat_many_lds(SetTable t, int N, uint32_t* __restrict__ counts, int* status) {
+    extern __shared__ uint32_t bins[];
+    const int q = blockIdx.y;
+    splat_lds_body(t.xy[q], t.n[q], N, counts + (size_t)q * N * N, status, blockIdx.x, gridDim.x, bins);
+}
+
+__global__ __launch_bounds__(256) void k_validate_many(SetTable t, int* status) {
+    const int q = blockIdx.y;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < t.n[q]; p += stride)
+        if (!in_unit_square(t.xy[q][p])) flag_domain(status);
+}
+
+__global__ __launch_bounds__(256) void k_advect_many(SetTable t, const float2* __restrict__ field, int N,
+                                                     const int* status) {
+    if (failed(status)) return;
+    const int q = blockIdx.y;
+    float2* __restrict__ xy = t.xy[q];
+    const float2* f = field + (size_t)q * N * N;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < t.n[q]; p += stride)
+        xy[p] = advect_point(f, N, xy[p]);
+}
+
 // ------------------------------------------------------------------ launchers
 static unsigned grid_for(int64_t n, int per_block = 256, unsigned cap = 8192) {
     int64_t g = (n + per_block - 1) / per_block;
@@ -695,7 +777,11 @@ hipError_t launch_fill(uint32_t* counts, size_t count, int* status, bool clear_s
 }
 
 hipError_t launch_splat(const float2* xy, int64_t n, int N, uint32_t* counts, int* status, hipStream_t st) {
-    hipLaunchKernelGGL(k_splat, dim3(grid_for(n)), dim3(256), 0, st, xy, n, N, counts, status);
+    if ((int64_t)N * N <= kLdsSplatTexels)
+        hipLaunchKernelGGL(k_splat_lds, dim3(grid_for(n, 256, kLdsSplatBlocks)), dim3(256), sizeof(uint32_t) * N * N,
+                           st, xy, n, N, counts, status);
+    else
+        hipLaunchKernelGGL(k_splat, dim3(grid_for(n)), dim3(256), 0, st, xy, n, N, counts, status);
     return hipGetLastError();
 }
 
@@ -709,6 +795,37 @@ hipError_t launch_blur(const uint32_t* counts, float* out, int N, const BlurTaps
     const size_t smem = sizeof(float) * blur_smem_floats(taps.r);
     const dim3 grd((N + kBX - 1) / kBX, (N + kBY - 1) / kBY);
     launch_kernel(k_blur, grd, dim3(256), smem, st, counts, out, N, taps, status);
+    return hipGetLastError();
+}
+
+static unsigned grid_for_sets(const SetTable& t) {
+    int64_t m = 0;
+    for (int q = 0; q < t.count; ++q) m = t.n[q] > m ? t.n[q] : m;
+    return grid_for(m);
+}
+
+hipError_t launch_blur_many(const uint32_t* counts, float* out, int N, int k, const BlurTaps& taps, const int* status,
+                            hipStream_t st) {
+    const size_t smem = sizeof(float) * blur_smem_floats(taps.r);
+    const dim3 grd((N + kBX - 1) / kBX, (N + kBY - 1) / kBY, k);
+    launch_kernel(k_blur, grd, dim3(256), smem, st, counts, out, N, taps, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_splat_many(const SetTable& t, int N, uint32_t* counts, int* status, hipStream_t st) {
+    if ((int64_t)N * N <= kLdsSplatTexels) {
+        const unsigned g = grid_for_sets(t);
+        hipLaunchKernelGGL(k_splat_many_lds, dim3(g < kLdsSplatBlocks ? g : kLdsSplatBlocks, t.count), dim3(256),
+                           sizeof(uint32_t) * N * N, st, t, N, counts, status);
+    } else {
+        hipLaunchKernelGGL(k_splat_many, dim3(grid_for_sets(t), t.count), dim3(256), 0, st, t, N, counts, status);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_advect_many(const SetTable& t, const float2* field, int N, int* status, hipStream_t st) {
+    hipLaunchKernelGGL(k_validate_many, dim3(grid_for_sets(t), t.count), dim3(256), 0, st, t, status);
+    hipLaunchKernelGGL(k_advect_many, dim3(grid_for_sets(t), t.count), dim3(256), 0, st, t, field, N, status);
     return hipGetLastError();
 }
 

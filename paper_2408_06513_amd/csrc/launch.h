@@ -64,6 +64,20 @@ hipError_t launch_deform_planes(const void* alpha, const void* alpha_t, int dt, 
                                 float2* field, hipStream_t st);
 
 hipError_t launch_fill(uint32_t* counts, size_t count, int* status, bool clear_status, hipStream_t st);
+
+// Several sample sets in one launch (passed by value): set q has n[q] samples
+// at xy[q]; its raster or field is the q-th of a stack of N x N ones.
+constexpr int kMaxSets = 64;
+struct SetTable {
+    int count;
+    float2* xy[kMaxSets];
+    int64_t n[kMaxSets];
+};
+hipError_t launch_splat_many(const SetTable& t, int N, uint32_t* counts, int* status, hipStream_t st);
+hipError_t launch_blur_many(const uint32_t* counts, float* out, int N, int k, const BlurTaps& taps, const int* status,
+                            hipStream_t st);
+// Flags invalid samples of any set, then (if none) moves every set through its field.
+hipError_t launch_advect_many(const SetTable& t, const float2* field, int N, int* status, hipStream_t st);
 hipError_t launch_splat(const float2* xy, int64_t n, int N, uint32_t* counts, int* status, hipStream_t st);
 hipError_t launch_blur(const uint32_t* counts, float* out, int N, const BlurTaps& taps, const int* status,
                        hipStream_t st);

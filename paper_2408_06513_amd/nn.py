@@ -17,7 +17,7 @@ NN_EXPORTS = (
     "inim_conv_backward_weight", "inim_weight_transpose", "inim_f32_to_bf16", "inim_pool2", "inim_pool2_backward",
     "inim_upsample2_into", "inim_copy_channels_into", "inim_upsample2_backward", "inim_take_channels",
     "inim_relu_backward", "inim_mse", "inim_adam", "inim_nn_pack_density", "inim_nn_displacement", "inim_nn_field",
-    "inim_nn_count_folds", "inim_nn_bin_moments",
+    "inim_nn_count_folds", "inim_nn_bin_moments", "inim_nn_pack_density_many", "inim_nn_field_many",
 )
 
 _bound = None
@@ -48,6 +48,8 @@ def lib() -> ctypes.CDLL:
         "inim_mse": [vp, i32, vp, i32, i64, vp, vp, vp, sz, vp],
         "inim_adam": [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp, vp],
         "inim_nn_pack_density": [vp, i32, f32, i32, vp, vp],
+        "inim_nn_pack_density_many": [vp, i32, i32, vp, i32, vp, vp],
+        "inim_nn_field_many": [vp, i32, i32, i32, i32, vp, vp, vp],
         "inim_nn_displacement": [vp, i32, vp, vp],
         "inim_nn_field": [vp, i32, i32, i32, vp, vp, vp],
         "inim_nn_count_folds": [vp, i32, vp, vp],
@@ -202,6 +204,15 @@ def pack_density(density, scale, x):
     return x
 
 
+def pack_density_many(density, scales, x):
+    """density [k, res, res] f32 -> x [k, res, res, c] bf16 (channel 0 of
+    raster q = density[q] * scales[q])."""
+    k = density.shape[0]
+    sc = (ctypes.c_float * k)(*[float(v) for v in scales])
+    _check(lib().inim_nn_pack_density_many(_p(density), k, density.shape[1], sc, x.shape[-1], _p(x), _s(x)))
+    return x
+
+
 def displacement(probe, res, out):
     _check(lib().inim_nn_displacement(_p(probe), res, _p(out), _s(out)))
     return out
@@ -211,6 +222,14 @@ def field(y, res, out, radius=0, work=None):
     if work is None:
         work = torch.empty_like(out)
     _check(lib().inim_nn_field(_p(y), y.shape[-1], res, radius, _p(out), _p(work), _s(out)))
+    return out
+
+
+def field_many(y, res, out, radius=0, work=None):
+    """field for a stack of outputs: y [k, res, res, c] -> out [k, res, res, 2]."""
+    if work is None:
+        work = torch.empty_like(out)
+    _check(lib().inim_nn_field_many(_p(y), y.shape[0], y.shape[-1], res, radius, _p(out), _p(work), _s(out)))
     return out
 
 

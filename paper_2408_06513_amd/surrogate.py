@@ -293,21 +293,22 @@ def predict_field(net: UNet, xy: torch.Tensor, res: int, radius: int = 8, net_re
 
 
 def regularize_many(net: UNet, xys, res: int, radius: int = 8, net_res: int | None = None) -> None:
-    """The surrogate's move of several point sets at once (one batched
-    forward pass), in place and without the gate."""
+    """The surrogate's move of several point sets at once, in place and
+    without the gate: their densities, fields and moves each in shared
+    launches (up to 64 sets a launch) around one batched forward pass."""
     net_res = net_res or res
     k = len(xys)
-    x16 = torch.empty((k, net_res, net_res, CIN), dtype=BF16, device=net.dev)
-    dens = torch.empty((net_res, net_res), dtype=F32, device=net.dev)
-    counts = torch.empty((net_res, net_res), dtype=torch.uint32, device=net.dev)
     r = net_radius(radius, res, net_res)
-    for q, xy in enumerate(xys):
-        density_input(xy, net_res, r, x16[q], counts, dens)
-    y = net.forward(x16)
-    field = torch.empty((net_res, net_res, 2), dtype=F32, device=net.dev)
-    for q, xy in enumerate(xys):
-        nn.field(y[q], net_res, field, field_radius(net_res))
-        capi.advect(field, xy)
+    for q0 in range(0, k, 64):
+        part = xys[q0:q0 + 64]
+        m = len(part)
+        x16 = torch.empty((m, net_res, net_res, CIN), dtype=BF16, device=net.dev)
+        _, dens, ws = capi.rasterize_many(part, net_res, radius=r)
+        nn.pack_density_many(dens, [net_res * net_res / max(1, xy.shape[0]) for xy in part], x16)
+        y = net.forward(x16)
+        field = torch.empty((m, net_res, net_res, 2), dtype=F32, device=net.dev)
+        nn.field_many(y, net_res, field, field_radius(net_res))
+        capi.advect_many(field, part, ws=ws)
 
 
 class SurrogateGraph:
@@ -349,6 +350,35 @@ class SurrogateGraph:
         self.graph.replay()
         xy.copy_(self.xy)
         return xy
+
+
+class SurrogateManyGraph:
+    """regularize_many on a fixed list of point sets (at most 64), captured
+    once as a HIP graph: each replay moves those same tensors in place.  All
+    buffers are allocated before or inside the capture; nothing in the graph
+    is a memset."""
+
+    def __init__(self, net: UNet, xys, res: int, net_res: int | None = None, radius: int = 8):
+        if not 1 <= len(xys) <= 64:
+            raise ValueError("1 to 64 point sets")
+        self.net, self.xys, self.res, self.net_res, self.radius = net, list(xys), res, net_res or res, radius
+        dev = net.dev
+        saved = [x.clone() for x in self.xys]
+        self._run()  # sizes the network's work buffer outside the capture
+        torch.cuda.synchronize(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._run()
+        torch.cuda.synchronize(dev)
+        for x, x0 in zip(self.xys, saved):  # the warm-up run moved them
+            x.copy_(x0)
+
+    def _run(self):
+        regularize_many(self.net, self.xys, self.res, self.radius, self.net_res)
+
+    def __call__(self):
+        self.graph.replay()
+        return self.xys
 
 
 def regularize(net: UNet, xy: torch.Tensor, res: int, iters: int, min_gain: float = 0.2,

@@ -98,6 +98,33 @@ def test_argument_errors_return_before_launch():
 
 
 @cpu_only
+def test_many_set_argument_errors_return_before_launch():
+    from paper_2408_06513_amd import nn
+    L, N = capi.lib(), nn.lib()
+    nul, fake = None, ctypes.c_void_p(0x1000)
+    ptrs = (ctypes.c_void_p * 65)(*([0x1000] * 65))
+    ns = (ctypes.c_int64 * 65)(*([10] * 65))
+    ws = ctypes.c_size_t(256)
+    assert L.inim_rasterize_many(ptrs, ns, 65, 64, nul, fake, nul, fake, 256, nul) == capi.EINVAL   # > 64 sets
+    assert L.inim_rasterize_many(ptrs, ns, 0, 64, nul, fake, nul, fake, 256, nul) == capi.EINVAL    # no set
+    assert L.inim_rasterize_many(nul, ns, 2, 64, nul, fake, nul, fake, 256, nul) == capi.EINVAL     # xy NULL
+    assert L.inim_rasterize_many(ptrs, ns, 2, 100, nul, fake, nul, fake, 256, nul) == capi.EINVAL   # res
+    assert L.inim_rasterize_many(ptrs, ns, 2, 64, nul, nul, nul, fake, 256, nul) == capi.EINVAL     # counts NULL
+    assert L.inim_rasterize_many(ptrs, ns, 2, 64, nul, fake, nul, fake, 8, nul) == capi.EWORKSPACE
+    bad = (ctypes.c_int64 * 2)(10, -1)
+    assert L.inim_rasterize_many(ptrs, bad, 2, 64, nul, fake, nul, fake, 256, nul) == capi.EINVAL   # n < 0
+    assert L.inim_advect_many(fake, 64, ptrs, ns, 65, fake, 256, nul) == capi.EINVAL
+    assert L.inim_advect_many(nul, 64, ptrs, ns, 2, fake, 256, nul) == capi.EINVAL                  # field NULL
+    assert L.inim_advect_many(fake, 64, ptrs, ns, 2, nul, 0, nul) == capi.EWORKSPACE
+    sc = (ctypes.c_float * 65)(*([1.0] * 65))
+    assert N.inim_nn_pack_density_many(fake, 65, 64, sc, 8, fake, nul) == capi.EINVAL
+    assert N.inim_nn_pack_density_many(fake, 2, 64, nul, 8, fake, nul) == capi.EINVAL              # scales NULL
+    assert N.inim_nn_field_many(fake, 0, 8, 64, 2, fake, fake, nul) == capi.EINVAL
+    assert N.inim_nn_field_many(fake, 2, 8, 64, 17, fake, fake, nul) == capi.EINVAL                # radius
+    del ws
+
+
+@cpu_only
 def test_quality_argument_errors_return_before_launch():
     from paper_2408_06513_amd import quality
     L = quality.lib()

@@ -66,6 +66,23 @@ def test_conv_forward_exact(nn, dev, shape):
     assert torch.equal(y16.cpu().double(), O.bf16_round(ref))
 
 
+def test_split_forward_passes_share_one_work_buffer(nn, dev):
+    """Split forward passes of several shapes, repeated on one work buffer:
+    every repeat is exact."""
+    shapes = [(1, 4, 4, 256, 256, 3), (1, 8, 8, 128, 256, 3), (2, 16, 16, 256, 256, 3), (1, 32, 32, 64, 128, 3)]
+    work = torch.empty(max(nn.conv_workspace(*sh) for sh in shapes), dtype=torch.uint8, device=dev)
+    cases = []
+    for k, (n, h, w, cin, cout, ks) in enumerate(shapes):
+        x, wt, b = ints(20 + k, (n, h, w, cin)), ints(30 + k, (cout, ks * ks, cin)), ints(40 + k, (cout,), -20, 20)
+        cases.append((g16(x, dev), g16(wt, dev), g32(b, dev), (n, h, w, cout), O.conv(x, wt, b, relu=True)))
+    for rep in range(3):
+        for k, (x, wt, b, oshape, ref) in enumerate(cases):
+            note(f"split forward {shapes[k]} repeat {rep}")
+            y32 = torch.empty(oshape, dtype=torch.float32, device=dev)
+            nn.conv_forward(x, wt, b, relu=True, y32=y32, work=work)
+            assert torch.equal(y32.cpu().double(), ref), (rep, k)
+
+
 @pytest.mark.parametrize("shape", CONV_SHAPES)
 def test_conv_backward_exact(nn, dev, shape):
     n, h, w, cin, cout, ks = shape
