@@ -85,6 +85,11 @@ int inim_upsample2_into(const inim_bf16* x, int32_t imgs, int32_t h, int32_t w, 
 /* y[p][c0 + c'] = x[p][c'] for c' < c (the second half of a concatenation). */
 int inim_copy_channels_into(const inim_bf16* x, int64_t pixels, int32_t c, inim_bf16* y, int32_t ct, int32_t c0,
                             hipStream_t stream);
+/* The decoder's concatenation in one pass: y (imgs x 2h x 2w, ca + cb
+ * channels) = [inim_upsample2_into(a) | b], a imgs x h x w x ca, b
+ * imgs x 2h x 2w x cb; the same values as the two calls above. */
+int inim_concat_up2(const inim_bf16* a, int32_t imgs, int32_t h, int32_t w, int32_t ca, const inim_bf16* b,
+                    int32_t cb, inim_bf16* y, hipStream_t stream);
 /* Gradient of inim_upsample2_into for c0 = 0: da (h x w, ca channels) = sum of
  * the 2 x 2 block of dy (2h x 2w, ct channels), channels [0, ca). */
 int inim_upsample2_backward(const float* dy, int32_t imgs, int32_t h, int32_t w, int32_t ct, int32_t ca, float* da,

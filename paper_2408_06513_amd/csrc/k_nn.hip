@@ -458,6 +458,28 @@ __global__ __launch_bounds__(256) void k_copy_into(const uint16_t* __restrict__ 
     }
 }
 
+// The concatenation [up(a) | b] in one pass over its elements: channels
+// [0, Ca) from the 2 x 2 upsampled a (imgs x h x w x Ca), [Ca, Ca + Cb) from b
+// (imgs x 2h x 2w x Cb).
+__global__ __launch_bounds__(256) void k_concat_up2(const uint16_t* __restrict__ a, int imgs, int h, int w, int Ca,
+                                                    const uint16_t* __restrict__ b, int Cb, uint16_t* __restrict__ y) {
+    const int Ct = Ca + Cb;
+    const size_t n = (size_t)imgs * 4 * h * w * Ct;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % Ct);
+        const size_t p = i / Ct;  // output pixel
+        if (c >= Ca) {
+            y[i] = b[p * Cb + (c - Ca)];
+        } else {
+            const int xx = (int)(p % (2 * w));
+            const size_t r = p / (2 * w);
+            const int yy = (int)(r % (2 * h));
+            const size_t img = r / (2 * h);
+            y[i] = a[((img * h + yy / 2) * w + xx / 2) * Ca + c];
+        }
+    }
+}
+
 // Gradients through a concatenation [up(a) | b]: da[img][y][x][c] = sum of
 // the 2 x 2 block of dy[...][c] (channels [0, Ca)); db (channels [Ca, Ca+Cb))
 // is added to db_acc (FP32) when accumulate != 0, else stored.
@@ -916,6 +938,14 @@ int inim_upsample2_into(const inim_bf16* x, int32_t imgs, int32_t h, int32_t w, 
     hipLaunchKernelGGL(k_up2_into, dim3(grid_1d((int64_t)imgs * 4 * h * w * c)), dim3(256), 0, stream, x, imgs, h, w, c, y,
                        ct, c0);
     return launched("upsample");
+}
+
+int inim_concat_up2(const inim_bf16* a, int32_t imgs, int32_t h, int32_t w, int32_t ca, const inim_bf16* b,
+                    int32_t cb, inim_bf16* y, hipStream_t stream) {
+    if (!a || !b || !y || imgs < 1 || h < 1 || w < 1 || ca < 1 || cb < 1) return nfail(INIM_EINVAL, "bad concat arguments");
+    hipLaunchKernelGGL(k_concat_up2, dim3(grid_1d((int64_t)imgs * 4 * h * w * (ca + cb))), dim3(256), 0, stream, a, imgs,
+                       h, w, ca, b, cb, y);
+    return launched("concat");
 }
 
 int inim_copy_channels_into(const inim_bf16* x, int64_t pixels, int32_t c, inim_bf16* y, int32_t ct, int32_t c0,

@@ -18,6 +18,7 @@ NN_EXPORTS = (
     "inim_upsample2_into", "inim_copy_channels_into", "inim_upsample2_backward", "inim_take_channels",
     "inim_relu_backward", "inim_mse", "inim_adam", "inim_nn_pack_density", "inim_nn_displacement", "inim_nn_field",
     "inim_nn_count_folds", "inim_nn_bin_moments", "inim_nn_pack_density_many", "inim_nn_field_many",
+    "inim_concat_up2",
 )
 
 _bound = None
@@ -42,6 +43,7 @@ def lib() -> ctypes.CDLL:
         "inim_pool2_backward": [vp, i32, i32, i32, i32, vp, i32, vp],
         "inim_upsample2_into": [vp, i32, i32, i32, i32, vp, i32, i32, vp],
         "inim_copy_channels_into": [vp, i64, i32, vp, i32, i32, vp],
+        "inim_concat_up2": [vp, i32, i32, i32, i32, vp, i32, vp, vp],
         "inim_upsample2_backward": [vp, i32, i32, i32, i32, i32, vp, vp],
         "inim_take_channels": [vp, i64, i32, i32, i32, vp, i32, vp],
         "inim_relu_backward": [vp, vp, i64, vp, vp],
@@ -161,6 +163,14 @@ def pool2_backward(dy, dx, accumulate=False):
 def upsample2_into(x, y, c0=0):
     imgs, h, w, c = x.shape
     _check(lib().inim_upsample2_into(_p(x), imgs, h, w, c, _p(y), y.shape[3], c0, _s(x)))
+    return y
+
+
+def concat_up2(a, b, y):
+    """y [imgs, 2h, 2w, ca + cb] = [upsample2(a) | b] in one launch."""
+    imgs, h, w, ca = a.shape
+    assert b.shape == (imgs, 2 * h, 2 * w, b.shape[3]) and y.shape == (imgs, 2 * h, 2 * w, ca + b.shape[3])
+    _check(lib().inim_concat_up2(_p(a), imgs, h, w, ca, _p(b), b.shape[3], _p(y), _s(y)))
     return y
 
 

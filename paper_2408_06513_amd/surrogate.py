@@ -133,8 +133,7 @@ class UNet:
             n, hh, ww, cs = skip.shape
             cu = h.shape[3]
             cat = torch.empty((n, hh, ww, cu + cs), dtype=BF16, device=self.dev)
-            nn.upsample2_into(h, cat, 0)
-            nn.copy_channels_into(skip, cat, cu)
+            nn.concat_up2(h, skip, cat)
             self.inp[f"d{lvl}"] = cat
             a = self._conv(f"d{lvl}a", cat)
             b = self._conv(f"d{lvl}b", a)

@@ -66,6 +66,18 @@ def test_conv_forward_exact(nn, dev, shape):
     assert torch.equal(y16.cpu().double(), O.bf16_round(ref))
 
 
+@pytest.mark.parametrize("imgs,h,w,ca,cb", [(1, 4, 4, 256, 256), (2, 8, 5, 64, 32), (3, 1, 1, 8, 16)])
+def test_concat_up2_equals_upsample_and_copy(nn, dev, imgs, h, w, ca, cb):
+    a = g16(normal(50, (imgs, h, w, ca)), dev)
+    b = g16(normal(51, (imgs, 2 * h, 2 * w, cb)), dev)
+    y = torch.empty((imgs, 2 * h, 2 * w, ca + cb), dtype=BF, device=dev)
+    nn.concat_up2(a, b, y)
+    ref = torch.empty_like(y)
+    nn.upsample2_into(a, ref, 0)
+    nn.copy_channels_into(b, ref, ca)
+    assert torch.equal(y, ref)
+
+
 def test_split_forward_passes_share_one_work_buffer(nn, dev):
     """Split forward passes of several shapes, repeated on one work buffer:
     every repeat is exact."""
