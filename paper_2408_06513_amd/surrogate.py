@@ -316,14 +316,19 @@ class SurrogateGraph:
     for callers that repeat it on sets of the same size.  Every buffer is
     allocated before the capture; the library's kernels clear their own
     status words, so nothing in the graph is a memset.  Same results as
-    predict_field + advect, without the gate."""
+    predict_field + advect, without the gate.  With `xy` given, the graph
+    moves that tensor itself (call it without an argument); otherwise it moves
+    a private copy of the argument of each call."""
 
-    def __init__(self, net: UNet, n: int, res: int, net_res: int | None = None, radius: int = 8):
+    def __init__(self, net: UNet, n: int, res: int, net_res: int | None = None, radius: int = 8,
+                 xy: torch.Tensor | None = None):
         self.net, self.res, self.net_res = net, res, net_res or res
         dev = net.dev
         r = self.net_res
         self.radius = net_radius(radius, res, r)
-        self.xy = torch.zeros((n, 2), dtype=F32, device=dev) + 0.5
+        self.own = xy is None
+        saved = None if self.own else xy.clone()
+        self.xy = torch.zeros((n, 2), dtype=F32, device=dev) + 0.5 if self.own else xy
         self.x16 = torch.empty((1, r, r, CIN), dtype=BF16, device=dev)
         self.counts = torch.empty((r, r), dtype=torch.uint32, device=dev)
         self.dens = torch.empty((r, r), dtype=F32, device=dev)
@@ -336,6 +341,8 @@ class SurrogateGraph:
         with torch.cuda.graph(self.graph):
             self._run()
         torch.cuda.synchronize(dev)
+        if saved is not None:  # the warm-up run moved the caller's samples
+            self.xy.copy_(saved)
 
     def _run(self):
         density_input(self.xy, self.net_res, self.radius, self.x16[0], self.counts, self.dens)
@@ -343,8 +350,13 @@ class SurrogateGraph:
         nn.field(y[0], self.net_res, self.field, field_radius(self.net_res), work=self.fwork)
         capi.advect(self.field, self.xy, ws=self.ws)
 
-    def __call__(self, xy: torch.Tensor) -> torch.Tensor:
-        """Moves xy (same n) in place; returns it."""
+    def __call__(self, xy: torch.Tensor | None = None) -> torch.Tensor:
+        """Moves xy (same n) in place, or the tensor given at construction; returns it."""
+        if xy is None or not self.own:
+            if xy is not None and xy is not self.xy:
+                raise ValueError("this graph moves the tensor it was built on")
+            self.graph.replay()
+            return self.xy
         self.xy.copy_(xy)
         self.graph.replay()
         xy.copy_(self.xy)

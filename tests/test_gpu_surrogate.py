@@ -78,3 +78,12 @@ def test_coarse_network_for_a_finer_raster_and_its_graph_replay():
         assert torch.equal(out, eager), rep
         capi.regularize(other.clone(), 256, 2)  # unrelated eager work between replays
         torch.cuda.synchronize()
+    # built on the caller's tensor: each replay moves that tensor itself
+    mine = xy0.clone()
+    g2 = S.SurrogateGraph(net, xy0.shape[0], res, net_res, xy=mine)
+    assert torch.equal(mine, xy0)
+    for rep in range(2):
+        mine.copy_(xy0)
+        g2()
+        torch.cuda.synchronize()
+        assert torch.equal(mine, eager), rep
