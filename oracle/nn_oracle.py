@@ -130,3 +130,98 @@ def unet_loss_grads(p: dict, x, target, levels: int = 5, bf16: bool = False):
     loss = mse(y, target) / n
     g = torch.autograd.grad(loss, list(ps.values()))
     return loss.detach(), dict(zip(ps.keys(), [t.detach() for t in g])), y.detach()
+
+
+def _conv_dx(gz, w, xshape):
+    """Gradient of conv(x, w) with respect to x for the output gradient gz (NHWC)."""
+    cout, taps, cin = w.shape
+    ks = int(round(taps ** 0.5))
+    wk = w.reshape(cout, ks, ks, cin).permute(0, 3, 1, 2)
+    n, h, wd, _ = xshape
+    return _nhwc(torch.nn.grad.conv2d_input((n, cin, h, wd), wk, _nchw(gz), padding=ks // 2))
+
+
+def _conv_dw(x, gz, ks):
+    """Gradient of conv(x, w) with respect to w [cout, ks*ks, cin]."""
+    cin, cout = x.shape[-1], gz.shape[-1]
+    g = torch.nn.grad.conv2d_weight(_nchw(x), (cout, cin, ks, ks), _nchw(gz), padding=ks // 2)
+    return g.permute(0, 2, 3, 1).reshape(cout, ks * ks, cin)
+
+
+def _pool2_adjoint(g):
+    """Adjoint of 2x2 average pooling: every input pixel gets a quarter."""
+    return torch.repeat_interleave(torch.repeat_interleave(g, 2, 1), 2, 2) / 4
+
+
+def _up2_adjoint(g):
+    """Adjoint of nearest 2x upsampling: the sum over each 2x2 block."""
+    n, h, w, c = g.shape
+    return g.reshape(n, h // 2, 2, w // 2, 2, c).sum(dim=(2, 4))
+
+
+def unet_grads_stored(p: dict, x, target, levels: int = 5, store=bf16_round):
+    """Loss, parameter gradients and output of the U-Net, with the backward
+    pass written out layer by layer (chain rule through each convolution,
+    ReLU, pooling, upsampling and concatenation) and `store` applied to every
+    tensor where the HIP path keeps it in bfloat16: the weights, the input,
+    every activation after bias and ReLU, every pooled activation, the
+    gradient of the squared error, and every gradient after its ReLU mask.
+    All other quantities (sums, the network output, gradients with respect to
+    convolution inputs, and the skip and pooling gradients, which are added
+    before the mask of the level they reach) stay in the tensors' own dtype.
+    With store = identity this is the exact gradient, the same as
+    unet_loss_grads."""
+    s = store
+    W = {k: (s(v) if k.endswith(".w") else v) for k, v in p.items()}
+
+    def fwd(name, t, relu=True):
+        return conv(t, W[name + ".w"], W[name + ".b"], relu)
+
+    acts, skips = {}, []
+    h = s(x)
+    for lvl in range(levels):
+        if lvl:
+            h = s(pool2(h))
+        a = s(fwd(f"e{lvl}a", h))
+        b = s(fwd(f"e{lvl}b", a))
+        acts[f"e{lvl}"] = (h, a, b)
+        skips.append(b)
+        h = b
+    for lvl in range(levels - 2, -1, -1):
+        cat = torch.cat([up2(h), skips[lvl]], dim=-1)
+        a = s(fwd(f"d{lvl}a", cat))
+        b = s(fwd(f"d{lvl}b", a))
+        acts[f"d{lvl}"] = (cat, a, b)
+        h = b
+    y = fwd("head", h, relu=False)
+    ct, n = target.shape[-1], target.numel()
+    loss = mse(y, target) / n
+    gy = torch.zeros_like(y)
+    gy[..., :ct] = 2 * (y[..., :ct] - target) / n
+    gy = s(gy)
+
+    grads = {}
+
+    def back(name, gz, inp):
+        """Parameter gradients of one convolution; returns the gradient of its input."""
+        w = W[name + ".w"]
+        grads[name + ".w"] = _conv_dw(inp, gz, int(round(w.shape[1] ** 0.5)))
+        grads[name + ".b"] = gz.sum(dim=(0, 1, 2))
+        return _conv_dx(gz, w, inp.shape)
+
+    g = back("head", gy, h)
+    skip_g = {}
+    for lvl in range(levels - 1):  # decoder, the level next to the head first
+        cat, a, b = acts[f"d{lvl}"]
+        g = back(f"d{lvl}b", s(g * (b > 0)), a)
+        gcat = back(f"d{lvl}a", s(g * (a > 0)), cat)
+        cu = cat.shape[-1] - skips[lvl].shape[-1]
+        skip_g[lvl] = gcat[..., cu:]
+        g = _up2_adjoint(gcat[..., :cu])
+    for lvl in range(levels - 1, -1, -1):  # encoder, the deepest level first
+        inp, a, b = acts[f"e{lvl}"]
+        g = back(f"e{lvl}b", s(g * (b > 0)), a)
+        gx = back(f"e{lvl}a", s(g * (a > 0)), inp)
+        if lvl:
+            g = _pool2_adjoint(gx) + skip_g[lvl - 1]
+    return loss.detach(), grads, y.detach()

@@ -156,23 +156,37 @@ class UNet:
         g16 = torch.empty(g32.shape, dtype=BF16, device=self.dev)
         return nn.relu_backward(g32, act16, g16)
 
-    def backward(self, gy16: torch.Tensor):
-        """gy16: gradient of the loss w.r.t. the forward output, bf16 [n, H, W, 8]."""
+    def backward(self, gy16: torch.Tensor, record: dict | None = None):
+        """gy16: gradient of the loss w.r.t. the forward output, bf16 [n, H, W, 8].
+        With `record`, every convolution's name maps to what its backward
+        consumed and produced: "g" the FP32 gradient of its ReLU output (absent
+        for the head), "gz" the masked BF16 gradient of its pre-activation, and
+        "dx" the FP32 gradient of its input (absent for the first convolution)."""
         L = self.levels
+
+        def keep(name, **t):
+            if record is not None:
+                record.setdefault(name, {}).update(t)
+
         c = self.convs["head"]
         self._wgrad(c, gy16, self.inp["head"])
         g = self._dgrad(c, gy16)  # d loss / d (output of the last decoder level)
+        keep("head", gz=gy16, dx=g)
         skip_grad = {}
         for lvl in range(L - 1):  # decoder levels, top (0) first
             a, b, cat = self.mid[f"d{lvl}"], self.out[f"d{lvl}"], self.inp[f"d{lvl}"]
             gz = self._relu_back(g, b)
+            keep(f"d{lvl}b", g=g, gz=gz)
             cb = self.convs[f"d{lvl}b"]
             self._wgrad(cb, gz, a)
             g = self._dgrad(cb, gz)
+            keep(f"d{lvl}b", dx=g)
             gz = self._relu_back(g, a)
+            keep(f"d{lvl}a", g=g, gz=gz)
             ca = self.convs[f"d{lvl}a"]
             self._wgrad(ca, gz, cat)
             gcat = self._dgrad(ca, gz)
+            keep(f"d{lvl}a", dx=gcat)
             n, hh, ww, ct = gcat.shape
             cs = self.out[f"e{lvl}"].shape[3]
             cu = ct - cs
@@ -183,15 +197,19 @@ class UNet:
         for lvl in range(L - 1, -1, -1):  # encoder, bottom first
             a, b, x = self.mid[f"e{lvl}"], self.out[f"e{lvl}"], self.inp[f"e{lvl}"]
             gz = self._relu_back(g, b)
+            keep(f"e{lvl}b", g=g, gz=gz)
             cb = self.convs[f"e{lvl}b"]
             self._wgrad(cb, gz, a)
             g = self._dgrad(cb, gz)
+            keep(f"e{lvl}b", dx=g)
             gz = self._relu_back(g, a)
+            keep(f"e{lvl}a", g=g, gz=gz)
             ca = self.convs[f"e{lvl}a"]
             self._wgrad(ca, gz, x)
             if lvl == 0:
                 break
             gx = self._dgrad(ca, gz)  # gradient of the pooled input
+            keep(f"e{lvl}a", dx=gx)
             g = nn.pool2_backward(gx, skip_grad[lvl - 1], accumulate=True)
 
     def step(self, lr: float):

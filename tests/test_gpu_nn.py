@@ -205,3 +205,147 @@ def test_unet_forward_and_gradients_match_oracle(dev):
             cos = float((a @ b) / (a.norm() * b.norm() + 1e-300))
             assert cos >= 0.995, (key, cos)
             assert abs(float(a.norm() / b.norm()) - 1.0) <= 0.03, (key, float(a.norm() / b.norm()))
+
+
+# ------------------------------------------------------------------ 5-level network, element by element
+U = 2.0 ** -24  # unit roundoff of FP32
+
+
+def gamma(k: int) -> float:
+    """Worst-case relative bound of a sum of k FP32 roundings (any order)."""
+    return k * U / (1.0 - k * U)
+
+
+def check_close(name, got, ref, bound):
+    """Element-wise |got - ref| <= bound, reporting the worst ratio."""
+    err = (got - ref).abs()
+    ratio = float((err / bound.clamp(min=1e-300)).max())
+    note(f"{name}: max|err| {float(err.max()):.3e}, worst err/bound {ratio:.3f}")
+    assert (err <= bound).all(), (name, ratio)
+
+
+def test_unet5_lockstep_elementwise(dev):
+    """The 5-level 32-256 network (the surrogate's configuration) at 32 x 32,
+    two images, compared element by element with the FP64 oracle, one layer at
+    a time: each layer's output is recomputed by the oracle from the inputs the
+    layer received, so no rounding difference of an earlier layer is carried
+    along.  (Run end to end, FP32 and FP64 accumulation under the same BF16
+    storage already differ by up to half the scale of the deepest layer's
+    weight gradient on the CPU: ReLU masks and BF16 roundings flip and the
+    flips compound, so no element-wise tolerance would mean anything there.)
+
+    Bounds, from the arithmetic: a product of two BF16 values is exact in
+    FP32, a sum of K of them carries at most gamma(K) = K u / (1 - K u) of the
+    sum of their magnitudes (u = 2^-24, any order, split sums included), taken
+    twice for margin; a value stored in BF16 (round to nearest even) is
+    within 2^-8 of its magnitude of what was rounded; the ReLU-masked cast is
+    the same rounding on both sides and must match bit for bit."""
+    from paper_2408_06513_amd import nn as m
+    from paper_2408_06513_amd import surrogate as S
+
+    net = S.UNet(dev, seed=3)  # channels 32, 64, 128, 256, 256
+    assert net.levels == 5
+    n, hw = 2, 32
+    x = normal(21, (n, hw, hw, 8))
+    t = normal(22, (n, hw, hw, 2))
+    y = net.forward(g16(x, dev))
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    gy = torch.empty(y.shape, dtype=BF, device=dev)
+    m.mse(y, g32(t, dev), loss, gy)
+    rec = {}
+    net.backward(gy, record=rec)
+    torch.cuda.synchronize()
+    unet_lockstep_checks(net, y, gy, t, rec)
+
+
+def unet_lockstep_checks(net, y, gy, t, rec):
+    """The element-wise checks of test_unet5_lockstep_elementwise on a network
+    after one forward and backward pass (tensors on any device)."""
+    n, hw = y.shape[0], y.shape[1]
+    h64 = lambda a: a.detach().cpu().double()  # noqa: E731
+    bf = O.bf16_round
+    W = {k: h64(c.w16) for k, c in net.convs.items()}
+    for k, c in net.convs.items():
+        assert torch.equal(W[k], bf(h64(c.w))), k  # the BF16 weight copies
+    pixels = n * hw * hw
+
+    def conv_inputs(name):
+        if name == "head":
+            return h64(net.inp["head"])
+        lvl = name[:2]
+        return h64(net.inp[lvl]) if name.endswith("a") else h64(net.mid[lvl])
+
+    def conv_output(name):
+        lvl = name[:2]
+        return h64(net.mid[lvl]) if name.endswith("a") else h64(net.out[lvl])
+
+    # forward, every convolution: output = bf16(relu(conv(input) + bias))
+    for name, c in net.convs.items():
+        xin = conv_inputs(name)
+        k = c.cin * c.ks * c.ks + 1
+        ref = O.conv(xin, W[name], h64(c.b))
+        mag = O.conv(xin.abs(), W[name].abs(), h64(c.b).abs())
+        acc = 2 * gamma(k) * mag
+        if name == "head":
+            check_close("forward head", h64(y), ref, acc)
+            continue
+        ref = torch.relu(ref)
+        check_close(f"forward {name}", conv_output(name), ref, 2.0 ** -8 * (ref + acc) + acc)
+
+    # forward glue: pooling (BF16 mean of four BF16 values) and concatenation
+    for lvl in range(1, 5):
+        ref = O.pool2(h64(net.out[f"e{lvl - 1}"]))
+        check_close(f"pool into e{lvl}", h64(net.inp[f"e{lvl}"]), ref, 2.0 ** -8 * ref.abs() + 1e-30)
+    for lvl in range(4):
+        below = h64(net.out[f"d{lvl + 1}"] if lvl < 3 else net.out["e4"])
+        ref = torch.cat([O.up2(below), h64(net.out[f"e{lvl}"])], dim=-1)
+        assert torch.equal(h64(net.inp[f"d{lvl}"]), ref), lvl
+
+    # the squared-error gradient: bf16(2 (y - t) / (pixels * 2)) on the first two channels
+    ref = torch.zeros_like(h64(y))
+    ref[..., :2] = 2 * (h64(y)[..., :2] - t.float().double()) / t.numel()
+    check_close("mse gradient", h64(gy), ref, 2.0 ** -8 * ref.abs() + 1e-30)
+
+    # backward, every convolution
+    for name, c in net.convs.items():
+        r = rec[name]
+        xin, gz = conv_inputs(name), h64(r["gz"])
+        if "g" in r:  # the ReLU mask and BF16 cast, the same rounding on both sides
+            mask = conv_output(name) > 0
+            assert torch.equal(gz, bf(h64(r["g"]) * mask)), name
+        kw = pixels
+        ref = O._conv_dw(xin, gz, c.ks)
+        check_close(f"weight gradient {name}", h64(c.gw), ref, 2 * gamma(kw) * O._conv_dw(xin.abs(), gz.abs(), c.ks))
+        check_close(f"bias gradient {name}", h64(c.gb), gz.sum(dim=(0, 1, 2)),
+                    2 * gamma(kw) * gz.abs().sum(dim=(0, 1, 2)) + 1e-30)
+        if "dx" in r:
+            ref = O._conv_dx(gz, W[name], xin.shape)
+            bound = 2 * gamma(c.cout * c.ks * c.ks) * O._conv_dx(gz.abs(), W[name].abs(), xin.shape)
+            check_close(f"data gradient {name}", h64(r["dx"]), ref, bound + 1e-30)
+
+    # backward glue: the upsampling adjoint feeds the level below, the pooling
+    # adjoint plus the skip gradient feed each encoder level but the deepest
+    for lvl in range(4):
+        gcat = h64(rec[f"d{lvl}a"]["dx"])
+        cu = gcat.shape[-1] - net.out[f"e{lvl}"].shape[3]
+        ref = O._up2_adjoint(gcat[..., :cu])
+        below = f"d{lvl + 1}b" if lvl < 3 else "e4b"
+        check_close(f"upsampling adjoint into {below}", h64(rec[below]["g"]), ref,
+                    2 * gamma(4) * O._up2_adjoint(gcat[..., :cu].abs()) + 1e-30)
+        ref = O._pool2_adjoint(h64(rec[f"e{lvl + 1}a"]["dx"])) + gcat[..., cu:]
+        mag = O._pool2_adjoint(h64(rec[f"e{lvl + 1}a"]["dx"]).abs()) + gcat[..., cu:].abs()
+        check_close(f"pooling adjoint + skip into e{lvl}b", h64(rec[f"e{lvl}b"]["g"]), ref, 2 * gamma(1) * mag + 1e-30)
+
+
+def test_adam_two_step_closed_form(nn, dev):
+    """The GPU's Adam on gradients (1, 0): the second move is
+    -lr (b1 / (1 + b1)) / (sqrt(b2 / (1 + b2)) + eps), which tells b1 from b2."""
+    lr, b1, b2, eps = 0.01, 0.9, 0.999, 1e-8
+    w = torch.zeros(256, device=dev)
+    mo, v = torch.zeros_like(w), torch.zeros_like(w)
+    nn.adam(w, torch.ones_like(w), mo, v, 1, lr=lr, b1=b1, b2=b2, eps=eps)
+    w1 = w.clone()
+    nn.adam(w, torch.zeros_like(w), mo, v, 2, lr=lr, b1=b1, b2=b2, eps=eps)
+    step2 = -lr * (b1 / (1 + b1)) / (np.sqrt(b2 / (1 + b2)) + eps)
+    assert torch.allclose(w1.cpu().double(), torch.full((256,), -lr / (1 + eps), dtype=D), rtol=1e-6, atol=0)
+    assert torch.allclose((w - w1).cpu().double(), torch.full((256,), step2, dtype=D), rtol=1e-5, atol=0)
