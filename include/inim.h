@@ -304,6 +304,30 @@ int inim_batch_autotune(float* const* xy, const int64_t* n, const int32_t* res, 
                         inim_batch_config* best, double* best_ms);
 
 /*
+ * inim_regularize without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  It runs the same kernels, on a static
+ * scratch array of 64 MiB that the library holds on each GPU it runs on until
+ * the process ends; nothing is allocated or freed.  The call fits when
+ * inim_workspace_size(res, n, p) is at most 64 MiB: 1M samples at 1024^2
+ * (55.5 MiB) or 2.4M samples at 512^2, for example; larger calls return
+ * EWORKSPACE before anything is enqueued.
+ *   xy, n, res, iters, p  as for inim_regularize; the results are identical.
+ *   status  device, int; may be NULL.  When given, the call's status word is
+ *           kept there (it is cleared when the call starts) and
+ *           inim_sync_status(status, stream) reports EDOMAIN for NaN or
+ *           out-of-range samples; with NULL such a call leaves xy unchanged
+ *           and the error is not reported.
+ * The current device must be the device of `stream` (EINVAL otherwise).  The
+ * scratch is looked up once per device.  All calls on one GPU share its
+ * scratch, which keeps the last call's contents: two calls that overlap in
+ * time on one GPU (other streams, other host threads) race and give wrong
+ * results.
+ */
+int inim_regularize_noalloc(float* xy, int64_t n, int32_t res, int32_t iters, const inim_params* p, int* status,
+                            hipStream_t stream);
+
+/*
  * Waits for `stream`, returns the status word of the last call that used ws
  * (INIM_OK or INIM_EDOMAIN) and clears it.  EHIP if the synchronisation fails.
  */

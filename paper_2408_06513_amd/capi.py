@@ -31,7 +31,7 @@ EXPORTS = (
     "inim_deform", "inim_advect", "inim_regularize", "inim_regularize_timed", "inim_sync_status",
     "inim_graph_create", "inim_graph_destroy", "inim_regularize_graph", "inim_regularize_probes",
     "inim_batch_workspace_size", "inim_regularize_batch", "inim_batch_autotune",
-    "inim_rasterize_many", "inim_advect_many",
+    "inim_rasterize_many", "inim_advect_many", "inim_regularize_noalloc",
 )
 
 
@@ -114,6 +114,7 @@ def lib() -> ctypes.CDLL:
     L.inim_graph_destroy.argtypes = [vp]
     L.inim_regularize_graph.argtypes = [vp, i64, i32, i32, pp, vp, sz, vp, vp]
     L.inim_regularize_probes.argtypes = [vp, i64, vp, i64, i32, i32, pp, vp, sz, vp]
+    L.inim_regularize_noalloc.argtypes = [vp, i64, i32, i32, pp, vp, vp]
     bp = ctypes.POINTER(BatchConfig)
     L.inim_batch_workspace_size.argtypes = [vp, vp, vp, i32, pp, ctypes.POINTER(sz)]
     L.inim_regularize_batch.argtypes = [vp, vp, vp, i32, i32, pp, bp, vp, sz, vp, vp]
@@ -295,6 +296,23 @@ def regularize(xy: torch.Tensor, res: int, iters: int, radius: int = 8, sigma=No
                                  _stream(xy)))
     if check:
         _check(sync_status(ws))
+    return xy
+
+
+def regularize_noalloc(xy: torch.Tensor, res: int, iters: int, radius: int = 8, sigma=None, d0=None,
+                       status: torch.Tensor | None = None, check: bool = False) -> torch.Tensor:
+    """regularize on the library's static per-GPU scratch (no workspace; the
+    call allocates nothing).  status: an int32 device tensor of at least one
+    element for the call's status word, or None; check=True needs it."""
+    n = _xy(xy)
+    if status is not None and not (status.is_cuda and status.dtype == torch.int32 and status.numel() >= 1):
+        raise ValueError("status must be an int32 device tensor")
+    if check and status is None:
+        raise ValueError("check=True needs a status tensor")
+    p = params(radius, sigma, d0)
+    _check(lib().inim_regularize_noalloc(_ptr(xy), n, res, iters, ctypes.byref(p), _ptr(status), _stream(xy)))
+    if check:
+        _check(sync_status(status))
     return xy
 
 

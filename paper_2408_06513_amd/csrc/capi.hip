@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -127,10 +128,11 @@ struct ClockScope {
 // Iteration k reads the count raster counts[k % 2]; its advection splats the
 // moved samples into counts[(k+1) % 2], which the smoothing of iteration k has
 // zeroed.
+// `status` is the call's status word: the workspace's own (ws + L.status) or
+// one the caller keeps apart from the workspace.
 int enqueue_regularize(float* xy, int64_t n, float* probe, int64_t m, int32_t res, int32_t iters, double d0,
-                       const BlurTaps& taps, const RegLayout& L, char* ws, hipStream_t st, StageEvents* ev,
-                       double* stage_ms) {
-    int* status = reinterpret_cast<int*>(ws + L.status);
+                       const BlurTaps& taps, const RegLayout& L, char* ws, int* status, hipStream_t st,
+                       StageEvents* ev, double* stage_ms) {
     uint32_t* counts[2] = {reinterpret_cast<uint32_t*>(ws + L.counts[0]), reinterpret_cast<uint32_t*>(ws + L.counts[1])};
     float* density = reinterpret_cast<float*>(ws + L.density);
     float2* field = reinterpret_cast<float2*>(ws + L.field);
@@ -239,7 +241,8 @@ int regularize_impl(float* xy, int64_t n, float* probe, int64_t m, int32_t res, 
     const double d0 = P.d0 < 0.0 ? (double)n / ((double)res * (double)res) : P.d0;
     const BlurTaps taps = make_taps(P.radius, P.sigma);
     if (stage_ms == nullptr)
-        return enqueue_regularize(xy, n, probe, m, res, iters, d0, taps, L, (char*)ws, stream, nullptr, nullptr);
+        return enqueue_regularize(xy, n, probe, m, res, iters, d0, taps, L, (char*)ws,
+                                  reinterpret_cast<int*>((char*)ws + L.status), stream, nullptr, nullptr);
 
     StageEvents ev;
     hipEvent_t t0, t1;
@@ -248,7 +251,8 @@ int regularize_impl(float* xy, int64_t n, float* probe, int64_t m, int32_t res, 
     for (auto* h : all)
         if (hipEventCreate(h) != hipSuccess) return fail(INIM_EHIP, "hipEventCreate failed");
     (void)hipEventRecord(t0, stream);
-    s = enqueue_regularize(xy, n, probe, m, res, iters, d0, taps, L, (char*)ws, stream, &ev, stage_ms);
+    s = enqueue_regularize(xy, n, probe, m, res, iters, d0, taps, L, (char*)ws,
+                           reinterpret_cast<int*>((char*)ws + L.status), stream, &ev, stage_ms);
     (void)hipEventRecord(t1, stream);
     if (s == INIM_OK && hipEventSynchronize(t1) == hipSuccess) {
         float ms = 0.0f;
@@ -406,6 +410,48 @@ int graph_launch(inim_graph_cache* G, const std::vector<char>& key, hipStream_t 
     }
     hipError_t e = hipGraphLaunch(G->exec, stream);
     return e == hipSuccess ? INIM_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ static scratch
+// The workspace of inim_regularize_noalloc: a fixed array in device memory,
+// one copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it looks up each device's address once, with that device current,
+// and uses that address.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices];
+
+// The device address of `scratch` on the current device, which must be the
+// device of `stream` (the null stream: the current device).
+int static_scratch(hipStream_t stream, char** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (stream != nullptr) {
+        int sdev = -1;
+        if ((e = hipStreamGetDevice(stream, &sdev)) != hipSuccess) return hip_fail(e, "hipStreamGetDevice");
+        if (sdev != dev) return fail(INIM_EINVAL, "stream is on device %d, the current device is %d", sdev, dev);
+    }
+    if (dev < 0 || dev >= kMaxDevices) return fail(INIM_EINVAL, "device %d is beyond the first %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* ptr = nullptr;
+        if ((e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != hipSuccess)
+            return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (ptr == nullptr || ((uintptr_t)ptr & 255u) != 0)
+            return fail(INIM_EHIP, "static scratch at %p is not 256-byte aligned", ptr);
+        g_scratch_ptr[dev] = static_cast<char*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return INIM_OK;
 }
 
 }  // namespace
@@ -647,7 +693,8 @@ int inim_regularize_graph(float* xy, int64_t n, int32_t res, int32_t iters, cons
     const double d0 = P.d0 < 0.0 ? (double)n / ((double)res * (double)res) : P.d0;
     const BlurTaps taps = make_taps(P.radius, P.sigma);
     return graph_launch(G, k.bytes, stream, [&](hipStream_t cs) {
-        return enqueue_regularize(xy, n, nullptr, 0, res, iters, d0, taps, L, (char*)ws, cs, nullptr, nullptr);
+        return enqueue_regularize(xy, n, nullptr, 0, res, iters, d0, taps, L, (char*)ws,
+                                  reinterpret_cast<int*>((char*)ws + L.status), cs, nullptr, nullptr);
     });
 }
 
@@ -723,6 +770,30 @@ int inim_batch_autotune(float* const* xy, const int64_t* n, const int32_t* res, 
     (void)hipEventDestroy(t1);
     if (s == INIM_OK && best_ms) *best_ms = bestv;
     return s;
+}
+
+int inim_regularize_noalloc(float* xy, int64_t n, int32_t res, int32_t iters, const inim_params* p, int* status,
+                            hipStream_t stream) {
+    int s;
+    if ((s = check_res(res)) != INIM_OK) return s;
+    if ((s = check_xy(xy, n)) != INIM_OK) return s;
+    if (iters < 0) return fail(INIM_EINVAL, "iters=%d is negative", (int)iters);
+    Params P;
+    if ((s = resolve_params(p, P)) != INIM_OK) return s;
+    const RegLayout L = reg_layout(res, n, P.radius);
+    if (L.total > kStaticScratchBytes)
+        return fail(INIM_EWORKSPACE, "res=%d with n=%lld needs %zu bytes of scratch; the static scratch holds %zu",
+                    (int)res, (long long)n, L.total, kStaticScratchBytes);
+    char* ws = nullptr;
+    if ((s = static_scratch(stream, &ws)) != INIM_OK) return s;
+    int* st = status ? status : reinterpret_cast<int*>(ws + L.status);
+    if (n == 0 || iters == 0) {
+        hipError_t e = launch_fill(nullptr, 0, st, true, stream);
+        return e == hipSuccess ? INIM_OK : hip_fail(e, "fill");
+    }
+    const double d0 = P.d0 < 0.0 ? (double)n / ((double)res * (double)res) : P.d0;
+    const BlurTaps taps = make_taps(P.radius, P.sigma);
+    return enqueue_regularize(xy, n, nullptr, 0, res, iters, d0, taps, L, ws, st, stream, nullptr, nullptr);
 }
 
 int inim_sync_status(void* ws, hipStream_t stream) {

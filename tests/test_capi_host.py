@@ -95,6 +95,16 @@ def test_argument_errors_return_before_launch():
                                    nul, 0, nul, nul) == capi.EINVAL                        # waves_per_block
     assert L.inim_sync_status(nul, nul) == capi.EWORKSPACE
     assert "NULL" in capi.lib().inim_last_error().decode()
+    # the no-allocation variant: the same checks, then its size limit, all before any HIP call
+    assert L.inim_regularize_noalloc(nul, 10, 64, 2, ctypes.byref(p), nul, nul) == capi.EINVAL        # xy NULL
+    assert L.inim_regularize_noalloc(fake, 10, 100, 2, ctypes.byref(p), nul, nul) == capi.EINVAL      # res
+    assert L.inim_regularize_noalloc(fake, 10, 64, -1, ctypes.byref(p), nul, nul) == capi.EINVAL      # iters
+    assert L.inim_regularize_noalloc(fake, 2**32, 64, 2, ctypes.byref(p), nul, nul) == capi.ERANGE
+    assert capi.workspace_size(2048, 10) > 64 << 20
+    assert L.inim_regularize_noalloc(fake, 10, 2048, 2, ctypes.byref(p), nul, nul) == capi.EWORKSPACE
+    assert "static scratch" in capi.lib().inim_last_error().decode()
+    assert capi.workspace_size(1024, 3_000_000) > 64 << 20
+    assert L.inim_regularize_noalloc(fake, 3_000_000, 1024, 2, ctypes.byref(p), nul, nul) == capi.EWORKSPACE
 
 
 @cpu_only
