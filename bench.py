@@ -82,13 +82,24 @@ def log(msg: str):
 
 
 def stage_bytes(n: int, res: int) -> dict:
-    """Algorithmic bytes of one launch of each per-iteration stage (what the method must move)."""
+    """Algorithmic bytes of one launch of each per-iteration stage (what the
+    method must move).  The carry scans between the aggregate and the final
+    pass move only scratch partial sums: no algorithmic bytes."""
     px = res * res
     return {
         "smooth_aggregate": 4 * px + 4 * px + 4 * px,  # read counts, write density, clear next counts
+        "inim_scans": 0,                               # band carries (scratch only)
         "inim_deform": 4 * px + 8 * px,                # read the density, write the 2-channel field
         "advect_splat": 16 * n + 8 * px + 4 * px,      # read + write xy, read the field, next counts
     }
+
+
+# The kernel the roofline field reports: the longest per-iteration kernel of
+# the headline workload in the committed rocprofv3 kernel trace
+# (profiles/regularize_1M_1024_kernels.md: k_advect).  Fixed rather than
+# picked per run from event timings, where the stages lie within a few
+# percent of each other and the pick would flip between runs.
+ROOFLINE_STAGE = "advect_splat"
 
 
 def bench_regularize(args, dev):
@@ -178,13 +189,40 @@ def bench_regularize(args, dev):
     stage_us["sort_unsort_per_call"] = 1e3 * acc["sort_unsort"] / reps
     stage_us["total_per_iter"] = 1e3 * acc["total"] / (reps * iters)
     sb = stage_bytes(n, res)
-    dom = max(sb, key=lambda k: stage_us[k])
-    t_dom = stage_us[dom] * 1e-6
-    achieved = sb[dom] / t_dom / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    per_stage = {}
+    for k, b in sb.items():
+        t = stage_us[k] * 1e-6
+        per_stage[k] = {"us": round(stage_us[k], 3), "bytes_per_launch": b,
+                        "achieved_GBps": round(b / t / 1e9, 2), "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4),
+                        "traffic": measured_traffic(k)}
+    dom = ROOFLINE_STAGE
+    achieved = per_stage[dom]["achieved_GBps"]
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom), "kernel": dom,
-                "bytes_per_launch": sb[dom], "launch_us": round(stage_us[dom], 3)}
-    return xy0_np, value, ms_per_step, stage_us, roofline, graph_value, probe_value
+                "bytes_per_launch": sb[dom], "launch_us": round(stage_us[dom], 3), "stages": per_stage}
+
+    # the small configuration (20,000 points, 256^2, 4 iterations) as a
+    # graph replay, for the oracle's time on it
+    c1 = datagen.plain_small(0)
+    c1_0 = torch.from_numpy(c1).to(dev)
+    c1_xy = torch.empty_like(c1_0)
+    c1_ws = capi.workspace(capi.workspace_size(256, c1.shape[0], radius), dev)
+    c1_graph = capi.Graph()
+    c1_times = []
+    for rep in range(21):
+        c1_xy.copy_(c1_0)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        capi.regularize_graph(c1_xy, 256, 4, c1_graph, c1_ws)
+        b.record()
+        torch.cuda.synchronize()
+        if rep:
+            c1_times.append(a.elapsed_time(b))
+    assert capi.sync_status(c1_ws) == capi.OK
+    c1_graph.close()
+    small = {"n": int(c1.shape[0]), "res": 256, "iters": 4, "ms_per_call": round(float(np.median(c1_times)), 4)}
+    return xy0_np, value, ms_per_step, stage_us, roofline, graph_value, probe_value, small
 
 
 def bench_inim(dev, res: int = 8192, reps: int = 20) -> dict:
@@ -471,19 +509,88 @@ def bench_sweeps(dev) -> dict:
     return sw
 
 
-def cpu_baseline(xy0_np, res: int, iters: int, budget_s: float) -> dict:
+def host_cpu() -> dict:
+    """The host the oracle runs on: logical CPUs, the CPUs this process may
+    use, and the model name."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model,
+            "node": os.uname().nodename}
+
+
+def oracle_threads_all() -> int:
+    """All the threads this process should use: OMP_NUM_THREADS when set
+    (the CPU share of the machine), else every CPU of its affinity mask."""
+    aff = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(aff, int(env))) if env.isdigit() else aff
+
+
+def cpu_baseline(xy0_np, res: int, iters: int, budget_s: float, gpu_ms: dict) -> dict:
+    """The FP64 oracle timed on the host: the headline workload (bounded to
+    about budget_s of work per thread count), the small configuration, and the
+    8192^2 integral images, each on one thread and on all threads."""
+    import numpy as np
+
     import oracle
-    log("cpu baseline (oracle)")
-    done, t = 0, 0.0
-    while t < budget_s:
-        t0 = time.perf_counter()
-        oracle.regularize(xy0_np, res, iters)
-        t += time.perf_counter() - t0
-        done += iters
-    return {"value": round(done / t, 4), "unit": "iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"full workload ({xy0_np.shape[0]} points, {res}^2, r=8), {done} iterations "
-                      f"({done // iters} regularisations of {iters}), single thread, FP64",
-            "host": os.uname().nodename}
+    from paper_2408_06513_amd import datagen
+    host = host_cpu()
+    T = oracle_threads_all()
+    log(f"cpu baseline (oracle), 1 and {T} threads, host {host}")
+
+    def regularize_rate(k, budget):
+        oracle.set_threads(k)
+        done, t = 0, 0.0
+        while t < budget:
+            t0 = time.perf_counter()
+            oracle.regularize(xy0_np, res, iters)
+            t += time.perf_counter() - t0
+            done += iters
+        return done / t, done
+
+    def once(k, fn, reps=1):
+        oracle.set_threads(k)
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    r1, n1 = regularize_rate(1, budget_s)
+    rT, nT = regularize_rate(T, max(2.0, budget_s / 2))
+    c1 = datagen.plain_small(0).astype(np.float64)
+    c1_1 = once(1, lambda: oracle.regularize(c1, 256, 4), 3)
+    c1_T = once(T, lambda: oracle.regularize(c1, 256, 4), 3)
+    img = datagen.poisson_raster(0, 8192).astype(np.float64)
+    c3 = {}
+    for tag, mask in (("all", oracle.MASK_ALL), ("min", oracle.MASK_MIN)):
+        t1 = once(1, lambda: oracle.planes(img, mask))
+        tT = once(T, lambda: oracle.planes(img, mask))
+        g = gpu_ms.get(f"inim_u32_{tag}")
+        c3[tag] = {"s_1_thread": round(t1, 3), f"s_{T}_threads": round(tT, 3),
+                   "gpu_ms": g, "gpu_speedup_vs_all_threads": round(tT * 1e3 / g, 1) if g else None}
+    del img
+    oracle.set_threads(1)
+    g2 = gpu_ms.get("regularize_call")
+    g1 = gpu_ms.get("small_call")
+    return {"value": round(rT, 4), "unit": "iterations/s", "cores": T, "kind": "oracle",
+            "sample": f"full workload ({xy0_np.shape[0]} points, {res}^2, r=8): {nT} iterations "
+                      f"({nT // iters} regularisations of {iters}) on {T} threads; FP64",
+            "single_thread": {"value": round(r1, 4), "unit": "iterations/s",
+                              "sample": f"{n1} iterations ({n1 // iters} regularisations of {iters}), 1 thread"},
+            "gpu_speedup_vs_all_threads": round(iters / (g2 * 1e-3) / rT, 1) if g2 else None,
+            "small_config": {"n": int(c1.shape[0]), "res": 256, "iters": 4, "s_1_thread": round(c1_1, 4),
+                             f"s_{T}_threads": round(c1_T, 4), "gpu_ms": g1,
+                             "gpu_speedup_vs_all_threads": round(c1_T * 1e3 / g1, 1) if g1 else None},
+            "inim_8192_u32": c3, "host": host}
 
 
 def main():
@@ -532,7 +639,7 @@ def main():
     if args.only_sweeps:
         print(json.dumps({"sweeps": bench_sweeps(dev)}), flush=True)
         return
-    xy0_np, value, ms_per_step, stage_us, roofline, graph_value, probe_value = bench_regularize(args, dev)
+    xy0_np, value, ms_per_step, stage_us, roofline, graph_value, probe_value, small = bench_regularize(args, dev)
     rec = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -554,6 +661,7 @@ def main():
         "stages_us_per_iter": {k: round(v, 3) for k, v in stage_us.items()},
         "graph_replay_iters_per_s": round(graph_value, 2),
         "with_lattice_probes_iters_per_s": round(probe_value, 2),
+        "small_config": small,
     }
     if not args.no_inim:
         rec["inim_8192"] = bench_inim(dev)
@@ -569,7 +677,11 @@ def main():
     if not args.no_sweeps:
         rec["sweeps"] = bench_sweeps(dev)
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(xy0_np, args.res, args.iters, args.cpu_seconds)
+        gpu_ms = {"regularize_call": ms_per_step, "small_call": small["ms_per_call"]}
+        for tag in ("all", "min"):
+            if "inim_8192" in rec:
+                gpu_ms[f"inim_u32_{tag}"] = rec["inim_8192"][f"u32_{tag}"]["ms"]
+        rec["cpu_baseline"] = cpu_baseline(xy0_np, args.res, args.iters, args.cpu_seconds, gpu_ms)
     print(json.dumps(rec), flush=True)
 
 

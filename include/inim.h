@@ -77,7 +77,9 @@ typedef enum { INIM_U32 = 0, INIM_F32 = 1 } inim_dtype;
  *   sigma   Gaussian standard deviation in texels; <= 0 selects radius / 2.
  *   d0      background density added to every texel; < 0 selects the paper's
  *           choice n / res^2 (average samples per texel).
- * Defaults (inim_default_params): radius 8, sigma 4 (radius / 2), d0 = -1.
+ * Defaults (inim_default_params): radius 8, sigma 0 (unset: radius / 2 of the
+ * radius in force when the call runs, so a caller who only raises the radius
+ * gets the matching sigma), d0 = -1.
  */
 typedef struct {
     int32_t radius;

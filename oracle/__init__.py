@@ -28,7 +28,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (strict IEEE double, no FMA contraction)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                                "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -55,8 +55,17 @@ def lib():
         L.oracle_advect.argtypes = [dp, i32, dp, i64]
         L.oracle_regularize.argtypes = [dp, i64, i32, i32, i32, f64, f64]
         L.oracle_regularize_probes.argtypes = [dp, i64, dp, i64, i32, i32, i32, f64, f64]
+        L.oracle_set_threads.argtypes = [i32]
+        L.oracle_set_threads.restype = i32
+        L.oracle_set_threads(1)
         _lib = L
     return _lib
+
+
+def set_threads(k: int) -> int:
+    """Threads of the oracle's parallel loops (results do not depend on it);
+    returns the number in force.  The default is one."""
+    return int(lib().oracle_set_threads(int(k)))
 
 
 class OracleError(RuntimeError):

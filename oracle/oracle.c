@@ -37,13 +37,38 @@
  *                    inside [0,1] (else status 2, positions untouched); n = 0 is a
  *                    no-op.
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared oracle.c -o liboracle.so -lm
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared oracle.c -o liboracle.so -lm
  * All arithmetic is IEEE double, round to nearest, no contraction.
+ *
+ * Threads (OpenMP, optional): only loops whose iterations are independent run
+ * in parallel -- the rows of each blur pass, the eight planes (each swept by
+ * one thread, as written), the texels of the map, the samples of the advection
+ * and row bands of the splat (each thread counts the samples of its own rows).
+ * Every value is computed by the same operations in the same order whatever
+ * the thread count, so results are bit-identical for any thread count.
+ * oracle_set_threads(k) picks k threads (k <= 0: one); without -fopenmp the
+ * file builds as a single-threaded program.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static int oracle_threads = 1;
+
+/* Number of OpenMP threads of the parallel loops (1 without OpenMP). */
+int oracle_set_threads(int k) {
+#ifdef _OPENMP
+    oracle_threads = k > 0 ? k : 1;
+#else
+    (void)k;
+    oracle_threads = 1;
+#endif
+    return oracle_threads;
+}
 
 #define ORACLE_OK 0
 #define ORACLE_EINVAL 1
@@ -86,10 +111,22 @@ int oracle_counts(const double* xy, int64_t n, int N, double* counts) {
     if (!valid_res(N) || n < 0) return ORACLE_EINVAL;
     if (oracle_check_points(xy, n)) return ORACLE_EDOMAIN;
     memset(counts, 0, sizeof(double) * (size_t)N * (size_t)N);
-    for (int64_t p = 0; p < n; ++p) {
-        int i = pixel_of(xy[2 * p], N);
-        int j = pixel_of(xy[2 * p + 1], N);
-        counts[(size_t)j * N + i] += 1.0;
+    /* thread t counts the samples whose row lies in its band [j0, j1): every
+     * texel is written by one thread, and counts are exact integers */
+#pragma omp parallel num_threads(oracle_threads)
+    {
+        int nt = 1, t = 0;
+#ifdef _OPENMP
+        nt = omp_get_num_threads();
+        t = omp_get_thread_num();
+#endif
+        int j0 = (int)((int64_t)N * t / nt), j1 = (int)((int64_t)N * (t + 1) / nt);
+        for (int64_t p = 0; p < n; ++p) {
+            int j = pixel_of(xy[2 * p + 1], N);
+            if (j < j0 || j >= j1) continue;
+            int i = pixel_of(xy[2 * p], N);
+            counts[(size_t)j * N + i] += 1.0;
+        }
     }
     return ORACLE_OK;
 }
@@ -124,6 +161,7 @@ int oracle_blur(const double* c, int N, int r, double sigma, double* out) {
     }
     for (int m = 0; m <= 2 * r; ++m) g[m] /= sum;
     /* along x (within each row) */
+#pragma omp parallel for num_threads(oracle_threads) schedule(static)
     for (int j = 0; j < N; ++j)
         for (int i = 0; i < N; ++i) {
             double a = 0.0;
@@ -131,6 +169,7 @@ int oracle_blur(const double* c, int N, int r, double sigma, double* out) {
             tmp[(size_t)j * N + i] = a;
         }
     /* along y (within each column) */
+#pragma omp parallel for num_threads(oracle_threads) schedule(static)
     for (int j = 0; j < N; ++j)
         for (int i = 0; i < N; ++i) {
             double a = 0.0;
@@ -263,9 +302,14 @@ static void marginals(const double* d, int N, double* marg) {
 int oracle_planes(const double* d, int N, unsigned mask, double* planes, double* marg) {
     if (!valid_res(N) || (mask & ~0xFFu)) return ORACLE_EINVAL;
     size_t NN = (size_t)N * (size_t)N;
+    double* out[8] = {0};
     double* o = planes;
     for (int b = 0; b < 8; ++b)
-        if (mask & (1u << b)) { one_plane(d, N, b, o); o += NN; }
+        if (mask & (1u << b)) { out[b] = o; o += NN; }
+    /* the planes are independent: one thread sweeps each */
+#pragma omp parallel for num_threads(oracle_threads) schedule(dynamic, 1)
+    for (int b = 0; b < 8; ++b)
+        if (out[b]) one_plane(d, N, b, out[b]);
     if (marg) marginals(d, N, marg);
     return ORACLE_OK;
 }
@@ -285,6 +329,7 @@ static double texel_pos(int k, int N) { return ((double)k + 0.5) / (double)N; }
 /* t: N*N*2 (x,y interleaved); planes8: the 8 planes of d in bit order; C = sum d */
 static void molchanov_linsen_map(const double* P, int N, double C, double* t) {
     size_t NN = (size_t)N * (size_t)N;
+#pragma omp parallel for num_threads(oracle_threads) schedule(static)
     for (int j = 0; j < N; ++j)
         for (int i = 0; i < N; ++i) {
             size_t k = (size_t)j * N + i;
@@ -338,6 +383,7 @@ static int deform_with_defect(const double* dr, int N, double d0, const double* 
     for (size_t k = 0; k < NN; ++k) d[k] = dr[k] + d0; /* eq. (d0) */
     int st = oracle_map(d, N, t);
     if (st == ORACLE_OK)
+#pragma omp parallel for num_threads(oracle_threads) schedule(static)
         for (int j = 0; j < N; ++j)
             for (int i = 0; i < N; ++i) {
                 size_t k = (size_t)j * N + i;
@@ -378,6 +424,7 @@ static double clamp01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
 int oracle_advect(const double* field, int N, double* xy, int64_t n) {
     if (!valid_res(N) || n < 0) return ORACLE_EINVAL;
     if (oracle_check_points(xy, n)) return ORACLE_EDOMAIN;
+#pragma omp parallel for num_threads(oracle_threads) schedule(static)
     for (int64_t p = 0; p < n; ++p) {
         int i0, j0;
         double fx, fy;

@@ -180,8 +180,11 @@ def _xy(xy: torch.Tensor):
 
 
 def rasterize(xy: torch.Tensor, res: int, radius: int = 8, sigma=None, counts=None, density=None,
-              ws=None, want_density: bool = True):
-    """Counts (uint32 [res, res]) and smoothed density (float32 [res, res])."""
+              ws=None, want_density: bool = True, check: bool = True):
+    """Counts (uint32 [res, res]) and smoothed density (float32 [res, res]).
+    With check=True the call synchronises and raises DomainError when a
+    sample is NaN or outside the unit square (the rasters are then left
+    incomplete); pass False under graph capture and call sync_status(ws)."""
     n = _xy(xy)
     dev = xy.device
     if counts is None:
@@ -193,6 +196,8 @@ def rasterize(xy: torch.Tensor, res: int, radius: int = 8, sigma=None, counts=No
     p = params(radius, sigma)
     _check(lib().inim_rasterize(_ptr(xy), n, res, ctypes.byref(p), _ptr(counts), _ptr(density),
                                 _ptr(ws), ws.numel(), _stream(xy)))
+    if check:
+        _check(sync_status(ws))
     return counts, density, ws
 
 
@@ -236,13 +241,18 @@ def deform(alpha: torch.Tensor, alpha_t: torch.Tensor, marg: torch.Tensor, d0: f
     return field
 
 
-def advect(field: torch.Tensor, xy: torch.Tensor, ws=None) -> torch.Tensor:
-    """Bilinear advection of xy (in place) through field [res, res, 2]."""
+def advect(field: torch.Tensor, xy: torch.Tensor, ws=None, check: bool = True) -> torch.Tensor:
+    """Bilinear advection of xy (in place) through field [res, res, 2].  With
+    check=True the call synchronises and raises DomainError when a sample is
+    NaN or outside the unit square (xy is then left unmoved); pass False
+    under graph capture and call sync_status(ws)."""
     n = _xy(xy)
     res = field.shape[0]
     if ws is None:
         ws = workspace(256, xy.device)
     _check(lib().inim_advect(_ptr(field), res, _ptr(xy), n, _ptr(ws), ws.numel(), _stream(xy)))
+    if check:
+        _check(sync_status(ws))
     return xy
 
 
@@ -256,9 +266,11 @@ def _sets(xys):
 
 
 def rasterize_many(xys, res: int, radius: int = 8, sigma=None, counts=None, density=None, ws=None,
-                   want_density: bool = True):
+                   want_density: bool = True, check: bool = True):
     """rasterize for several sample sets in shared launches: counts (uint32
-    [k, res, res]) and densities (float32 [k, res, res]), raster q for xys[q]."""
+    [k, res, res]) and densities (float32 [k, res, res]), raster q for xys[q].
+    One NaN or out-of-range sample in any set stops every set; check=True
+    synchronises and raises DomainError then."""
     a, n, k = _sets(xys)
     dev = xys[0].device
     if counts is None:
@@ -270,17 +282,23 @@ def rasterize_many(xys, res: int, radius: int = 8, sigma=None, counts=None, dens
     p = params(radius, sigma)
     _check(lib().inim_rasterize_many(a, n, k, res, ctypes.byref(p), _ptr(counts), _ptr(density), _ptr(ws),
                                      ws.numel(), _stream(ws)))
+    if check:
+        _check(sync_status(ws))
     return counts, density, ws
 
 
-def advect_many(field: torch.Tensor, xys, ws=None):
+def advect_many(field: torch.Tensor, xys, ws=None, check: bool = True):
     """advect for several sample sets in shared launches: xys[q] moves (in
-    place) through field[q] ([k, res, res, 2])."""
+    place) through field[q] ([k, res, res, 2]).  One NaN or out-of-range
+    sample in any set leaves every set unmoved; check=True synchronises and
+    raises DomainError then."""
     a, n, k = _sets(xys)
     res = field.shape[1]
     if ws is None:
         ws = workspace(256, xys[0].device)
     _check(lib().inim_advect_many(_ptr(field), res, a, n, k, _ptr(ws), ws.numel(), _stream(ws)))
+    if check:
+        _check(sync_status(ws))
     return xys
 
 

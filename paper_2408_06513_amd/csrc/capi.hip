@@ -461,7 +461,7 @@ extern "C" {
 void inim_default_params(inim_params* p) {
     if (!p) return;
     p->radius = 8;
-    p->sigma = 4.0f;
+    p->sigma = 0.0f;  // unset: radius / 2 at resolve time
     p->d0 = -1.0;
 }
 

@@ -224,14 +224,16 @@ def net_radius(radius: int, res: int, net_res: int) -> int:
     return max(1, round(radius * net_res / res))
 
 
-def density_input(xy: torch.Tensor, net_res: int, radius: int, out16: torch.Tensor, counts=None, dens=None):
+def density_input(xy: torch.Tensor, net_res: int, radius: int, out16: torch.Tensor, counts=None, dens=None,
+                  ws=None, check: bool = True):
     """The network's input channel: the smoothed density on the net_res raster
-    divided by its mean (bf16 [net_res, net_res, 8], other channels 0)."""
+    divided by its mean (bf16 [net_res, net_res, 8], other channels 0).
+    check: as for capi.rasterize (False under graph capture)."""
     if counts is None:
         counts = torch.empty((net_res, net_res), dtype=torch.uint32, device=xy.device)
     if dens is None:
         dens = torch.empty((net_res, net_res), dtype=F32, device=xy.device)
-    capi.rasterize(xy, net_res, radius=radius, counts=counts, density=dens)
+    capi.rasterize(xy, net_res, radius=radius, counts=counts, density=dens, ws=ws, check=check)
     return nn.pack_density(dens, net_res * net_res / xy.shape[0], out16)
 
 
@@ -309,23 +311,39 @@ def predict_field(net: UNet, xy: torch.Tensor, res: int, radius: int = 8, net_re
     return nn.field(y[0], net_res, field, field_radius(net_res))
 
 
-def regularize_many(net: UNet, xys, res: int, radius: int = 8, net_res: int | None = None) -> None:
+def regularize_many(net: UNet, xys, res: int, radius: int = 8, net_res: int | None = None,
+                    check: bool = True) -> list:
     """The surrogate's move of several point sets at once, in place and
     without the gate: their densities, fields and moves each in shared
-    launches (up to 64 sets a launch) around one batched forward pass."""
+    launches (up to 64 sets a launch) around one batched forward pass.
+    A NaN or out-of-range sample in a group of 64 sets leaves that group
+    unmoved; check=True synchronises and raises DomainError then (pass
+    False under graph capture and check the returned status workspaces)."""
     net_res = net_res or res
     k = len(xys)
     r = net_radius(radius, res, net_res)
+    wss = []
     for q0 in range(0, k, 64):
         part = xys[q0:q0 + 64]
         m = len(part)
         x16 = torch.empty((m, net_res, net_res, CIN), dtype=BF16, device=net.dev)
-        _, dens, ws = capi.rasterize_many(part, net_res, radius=r)
+        _, dens, ws = capi.rasterize_many(part, net_res, radius=r, check=False)
         nn.pack_density_many(dens, [net_res * net_res / max(1, xy.shape[0]) for xy in part], x16)
         y = net.forward(x16)
         field = torch.empty((m, net_res, net_res, 2), dtype=F32, device=net.dev)
         nn.field_many(y, net_res, field, field_radius(net_res))
-        capi.advect_many(field, part, ws=ws)
+        capi.advect_many(field, part, ws=ws, check=False)
+        wss.append(ws)
+    if check:
+        check_status(wss)
+    return wss
+
+
+def check_status(wss) -> None:
+    """Synchronises and raises DomainError if a call that used one of these
+    status workspaces met a NaN or out-of-range sample."""
+    for ws in wss:
+        capi._check(capi.sync_status(ws))
 
 
 class SurrogateGraph:
@@ -363,20 +381,28 @@ class SurrogateGraph:
             self.xy.copy_(saved)
 
     def _run(self):
-        density_input(self.xy, self.net_res, self.radius, self.x16[0], self.counts, self.dens)
+        density_input(self.xy, self.net_res, self.radius, self.x16[0], self.counts, self.dens, ws=self.ws,
+                      check=False)
         y = self.net.forward(self.x16)
         nn.field(y[0], self.net_res, self.field, field_radius(self.net_res), work=self.fwork)
-        capi.advect(self.field, self.xy, ws=self.ws)
+        capi.advect(self.field, self.xy, ws=self.ws, check=False)
 
-    def __call__(self, xy: torch.Tensor | None = None) -> torch.Tensor:
-        """Moves xy (same n) in place, or the tensor given at construction; returns it."""
+    def __call__(self, xy: torch.Tensor | None = None, check: bool = False) -> torch.Tensor:
+        """Moves xy (same n) in place, or the tensor given at construction;
+        returns it.  check=True synchronises after the replay and raises
+        DomainError if a sample was NaN or outside the unit square (the
+        samples are then unmoved)."""
         if xy is None or not self.own:
             if xy is not None and xy is not self.xy:
                 raise ValueError("this graph moves the tensor it was built on")
             self.graph.replay()
+            if check:
+                check_status([self.ws])
             return self.xy
         self.xy.copy_(xy)
         self.graph.replay()
+        if check:
+            check_status([self.ws])
         xy.copy_(self.xy)
         return xy
 
@@ -397,16 +423,20 @@ class SurrogateManyGraph:
         torch.cuda.synchronize(dev)
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            self._run()
+            self.wss = self._run()
         torch.cuda.synchronize(dev)
         for x, x0 in zip(self.xys, saved):  # the warm-up run moved them
             x.copy_(x0)
 
     def _run(self):
-        regularize_many(self.net, self.xys, self.res, self.radius, self.net_res)
+        return regularize_many(self.net, self.xys, self.res, self.radius, self.net_res, check=False)
 
-    def __call__(self):
+    def __call__(self, check: bool = False):
+        """One replay; check=True synchronises and raises DomainError if a
+        sample was NaN or outside the unit square (the sets are then unmoved)."""
         self.graph.replay()
+        if check:
+            check_status(self.wss)
         return self.xys
 
 

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 def test_defaults_and_strerror():
     p = capi.Params()
     capi.lib().inim_default_params(ctypes.byref(p))
-    assert (p.radius, p.sigma, p.d0) == (8, 4.0, -1.0)
+    assert (p.radius, p.sigma, p.d0) == (8, 0.0, -1.0)  # sigma unset: radius / 2
     for s in range(6):
         assert capi.strerror(s)
     assert capi.strerror(99) == "unknown status"

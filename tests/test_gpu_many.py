@@ -67,8 +67,10 @@ def test_advect_many_equals_single_and_rejects_any_bad_set(dev):
     bad[3][100, 0] = float("nan")
     before = [b.clone() for b in bad]
     ws = capi.workspace(256, dev)
-    capi.advect_many(field, bad, ws=ws)
+    capi.advect_many(field, bad, ws=ws, check=False)
     assert capi.sync_status(ws) == capi.EDOMAIN
+    with pytest.raises(capi.DomainError):
+        capi.advect_many(field, bad, ws=ws)
     for q in range(len(bad)):  # no set moved, the bad sample's NaN included
         assert np.array_equal(bad[q].cpu().numpy(), before[q].cpu().numpy(), equal_nan=True), q
 
