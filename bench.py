@@ -348,36 +348,34 @@ def bench_splom(dev, reps: int = 5) -> dict:
             "speedup_vs_sequential": round(t_seq / best, 2)}
 
 
-def bench_surrogate(dev, train_sets: int = 1024, steps: int = 3000, held_out: int = 16, net_res: int = 64,
-                    batch: int = 16) -> dict:
-    """Learned surrogate of the 256 x 256, 8-iteration regularisation with the
-    network on a net_res x net_res raster: trained here on the GPU by the
-    project's kernels from point sets of 2-12 Gaussian components (10k-500k
-    points) labelled by the method itself (its composite map at the coarse
-    texel centres), then compared with the method on held-out point sets
-    (uniformity, folds, gate decisions) and timed per raster with events
-    around the calls: eagerly, as captured graph replays (both the method's
-    and the surrogate's), and batched over the held-out sets."""
+def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: int = 16, batch: int = 16,
+                    workers: int = 16, save_dir: str | None = None) -> dict:
+    """The learned surrogate of the 256 x 256, 8-iteration regularisation: a
+    5-level U-Net (32-256 channels) reading the 256 x 256 density raster.
+    Two output lattices are trained on the same sets with the same budget:
+    the displacement on the 64 x 64 lattice (decoder up to level 2, the
+    configuration in use) and on the full 256 x 256 lattice.  Training sets
+    are point sets of 2-12 Gaussian components (10k-500k points) drawn by
+    worker processes and labelled by the method itself (its composite map at
+    the lattice's texel centres).  On held-out sets: uniformity, folds, gate
+    decisions (the gate asks for 90% of the method's own mean bin-std gain,
+    calibrated on training sets), and times per raster -- single and batched,
+    ungated and gated -- against the method, also at equal final uniformity
+    (the method's time at the fractional iteration count whose bin std equals
+    the surrogate's)."""
     import numpy as np
     import torch
 
     from paper_2408_06513_amd import capi, datagen
     from paper_2408_06513_amd import surrogate as S
-    res, iters = 256, 8
-    log(f"surrogate: {train_sets} training sets (method {res}^2, network {net_res}^2)")
+    res, iters, net_res = 256, 8, 256
+    log(f"surrogate: {train_sets} training sets, labels on the 64^2 and 256^2 lattices")
     t0 = time.perf_counter()
-    X, T = S.dataset(range(train_sets), res, iters, dev, net_res=net_res)
+    sets = S.dataset_compact(range(train_sets), res, iters, dev, net_res=net_res, out_levels=(2, 0),
+                             workers=workers, log=log)
     t_data = time.perf_counter() - t0
-    net = S.UNet(dev, seed=0)
-    log(f"surrogate: {steps} training steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    losses = S.train(net, X, T, steps=steps, batch=batch, lr=1e-3)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    del X, T
-    seeds = range(100_000, 100_000 + held_out)
-    ev = S.evaluate(net, seeds, res, iters, dev, net_res=net_res)
+    seeds = list(range(100_000, 100_000 + held_out))
+    calib = list(range(train_sets, train_sets + 8))  # fresh training-distribution sets for the gate
 
     def ev_time(fn, reps=5):
         a = torch.cuda.Event(enable_timing=True)
@@ -391,71 +389,121 @@ def bench_surrogate(dev, train_sets: int = 1024, steps: int = 3000, held_out: in
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
-    plain_ms, plain_graph_ms, sur_ms, sur_graph_ms, gated_ms = [], [], [], [], []
-    for s in seeds:
-        xy0 = torch.from_numpy(datagen.surrogate_mixture(s)).to(dev)
-        xy = xy0.clone()
-        ws = capi.workspace(capi.workspace_size(res, xy.shape[0]), dev)
-        plain_ms.append(ev_time(lambda: (xy.copy_(xy0), capi.regularize(xy, res, iters, ws=ws, check=False))))
-        graph = capi.Graph()
-        plain_graph_ms.append(ev_time(lambda: (xy.copy_(xy0), capi.regularize_graph(xy, res, iters, graph, ws))))
-        graph.close()
-
-        def sur():
-            xy.copy_(xy0)
-            capi.advect(S.predict_field(net, xy, res, net_res=net_res), xy)
-        sur_ms.append(ev_time(sur))
-        gated_ms.append(ev_time(lambda: (xy.copy_(xy0), S.regularize(net, xy, res, iters, net_res=net_res))))
-        sg = S.SurrogateGraph(net, xy.shape[0], res, net_res, xy=xy)  # moves xy in place, as the method's graph
-        sur_graph_ms.append(ev_time(lambda: (xy.copy_(xy0), sg())))
-        del sg
-    # the held-out sets together: one batched forward pass
+    # the method on the held-out sets: bin std after 0..8 iterations and the
+    # graph-replayed time of 1..8 iterations, per raster
     xs0 = [torch.from_numpy(datagen.surrogate_mixture(s)).to(dev) for s in seeds]
-    xs = [x.clone() for x in xs0]
+    bs_k = np.zeros(iters + 1)
+    t_k = np.zeros(iters + 1)
+    for x0 in xs0:
+        xy = x0.clone()
+        bs_k[0] += S.bin_std(xy, res)
+        ws = capi.workspace(capi.workspace_size(res, xy.shape[0]), dev)
+        for k in range(1, iters + 1):
+            graph = capi.Graph()
+            t_k[k] += ev_time(lambda: (xy.copy_(x0), capi.regularize_graph(xy, res, k, graph, ws)))
+            graph.close()
+            xy.copy_(x0)
+            capi.regularize(xy, res, k, ws=ws)
+            bs_k[k] += S.bin_std(xy, res)
+    bs_k /= len(xs0)
+    t_k /= len(xs0)
+    gain_cal = []
+    for s in calib:
+        x = torch.from_numpy(datagen.surrogate_mixture(s)).to(dev)
+        b0 = S.bin_std(x, res)
+        capi.regularize(x, res, iters)
+        gain_cal.append(1.0 - S.bin_std(x, res) / b0)
+    min_gain = 0.9 * float(np.mean(gain_cal))
 
-    def many():
-        for x, x0 in zip(xs, xs0):
-            x.copy_(x0)
-        S.regularize_many(net, xs, res, net_res=net_res)
-    t_batch = ev_time(many, 3) / len(xs)
-    sgm = S.SurrogateManyGraph(net, xs, res, net_res)
+    def at_equal_uniformity(bs):
+        """The method's time per raster at the fractional iteration count
+        where its mean bin std equals bs (capped at the full count)."""
+        for k in range(1, iters + 1):
+            if bs_k[k] <= bs:
+                f = (bs_k[k - 1] - bs) / max(bs_k[k - 1] - bs_k[k], 1e-12)
+                tk0 = t_k[k - 1] if k > 1 else 0.0
+                return (k - 1) + f, tk0 + f * (t_k[k] - tk0)
+        return float(iters), float(t_k[iters])
 
-    def many_graph():
-        for x, x0 in zip(xs, xs0):
-            x.copy_(x0)
-        sgm()
-    t_batch_graph = ev_time(many_graph, 3) / len(xs)
-    del sgm
-    # the method on the same sets in one batched call (its scatterplot-matrix entry point)
-    wsb = capi.workspace(capi.batch_workspace_size(xs, [res] * len(xs)), dev)
-    cfg, _ = capi.batch_autotune(xs, [res] * len(xs), iters, ws=wsb)
-    bgraph = capi.Graph()
+    def run_variant(out_level: int) -> dict:
+        X = sets[out_level]
+        net = S.UNet(dev, seed=0, out_level=out_level)
+        log(f"surrogate (field {net_res >> out_level}^2): {steps} steps x {batch}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = S.train(net, X, None, steps=steps, batch=batch, lr=1e-3)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        if save_dir:
+            os.makedirs(save_dir, exist_ok=True)
+            net.save(os.path.join(save_dir, f"surrogate_256_field{net_res >> out_level}.npz"), optimizer=False)
+        ev = S.evaluate(net, seeds, res, iters, dev, net_res=net_res, min_gain=min_gain)
+        sur_bs = float(np.mean([r["surrogate"] for r in ev["rows"]]))
+        # per raster, single: the method's graph, the surrogate's graph (ungated), the gated call
+        plain, sur, gated = [], [], []
+        for x0 in xs0:
+            xy = x0.clone()
+            ws = capi.workspace(capi.workspace_size(res, xy.shape[0]), dev)
+            graph = capi.Graph()
+            plain.append(ev_time(lambda: (xy.copy_(x0), capi.regularize_graph(xy, res, iters, graph, ws))))
+            graph.close()
+            sg = S.SurrogateGraph(net, xy.shape[0], res, net_res, xy=xy)
+            sur.append(ev_time(lambda: (xy.copy_(x0), sg())))
+            del sg
+            gated.append(ev_time(lambda: (xy.copy_(x0), S.regularize(net, xy, res, iters, min_gain, net_res=net_res)),
+                                 3))
+        # batched over the held-out sets
+        xs = [x.clone() for x in xs0]
 
-    def plain_many():
-        for x, x0 in zip(xs, xs0):
-            x.copy_(x0)
-        capi.regularize_batch(xs, [res] * len(xs), iters, cfg=cfg, ws=wsb, graph=bgraph, check=False)
-    t_plain_batch = ev_time(plain_many, 3) / len(xs)
-    bgraph.close()
-    mean = lambda v: float(np.mean(v))
-    rec = {"res": res, "net_res": net_res, "iters": iters, "train_sets": train_sets, "train_steps": steps,
-           "batch": batch, "data_s": round(t_data, 1), "train_s": round(t_train, 1),
-           "loss_first10": round(mean(losses[:10]), 4), "loss_last10": round(mean(losses[-10:]), 4),
-           "held_out": held_out, "explained_variance": round(ev["explained"], 4),
-           "bin_std_gain_plain": round(ev["plain_gain"], 4), "bin_std_gain_surrogate": round(ev["surrogate_gain"], 4),
-           "folded_triangles": ev["folds"], "gate_fallbacks": ev["fallbacks"],
-           "plain_ms_per_raster": round(mean(plain_ms), 4), "plain_graph_ms_per_raster": round(mean(plain_graph_ms), 4),
-           "surrogate_ms_per_raster": round(mean(sur_ms), 4),
-           "surrogate_graph_ms_per_raster": round(mean(sur_graph_ms), 4),
-           "surrogate_gated_ms_per_raster": round(mean(gated_ms), 4),
-           f"surrogate_ms_per_raster_batch{held_out}": round(t_batch, 4),
-           f"surrogate_graph_ms_per_raster_batch{held_out}": round(t_batch_graph, 4),
-           f"plain_batched_ms_per_raster_batch{held_out}": round(t_plain_batch, 4)}
-    best_plain = min(rec["plain_ms_per_raster"], rec["plain_graph_ms_per_raster"])
-    rec["speedup_vs_plain"] = round(best_plain / rec["surrogate_graph_ms_per_raster"], 3)
-    rec["speedup_vs_plain_eager"] = round(rec["plain_ms_per_raster"] / rec["surrogate_ms_per_raster"], 3)
-    rec[f"speedup_vs_plain_batch{held_out}"] = round(min(best_plain, t_plain_batch) / min(t_batch, t_batch_graph), 3)
-    return rec
+        def reset():
+            for x, x0 in zip(xs, xs0):
+                x.copy_(x0)
+        sgm = S.SurrogateManyGraph(net, xs, res, net_res)
+        t_b_sur = ev_time(lambda: (reset(), sgm()), 3) / len(xs)
+        del sgm
+        wsb = capi.workspace(capi.batch_workspace_size(xs, [res] * len(xs)), dev)
+        cfg, _ = capi.batch_autotune(xs, [res] * len(xs), iters, ws=wsb)
+        bgraph = capi.Graph()
+        t_b_plain = ev_time(lambda: (reset(), capi.regularize_batch(xs, [res] * len(xs), iters, cfg=cfg, ws=wsb,
+                                                                    graph=bgraph, check=False)), 3) / len(xs)
+        bgraph.close()
+        reset()
+        dec = S.regularize_many_gated(net, xs, res, iters, min_gain, net_res=net_res, ws_batch=wsb)
+        bs_gated = float(np.mean([S.bin_std(x, res) for x in xs]))
+        t_b_gated = ev_time(lambda: (reset(), S.regularize_many_gated(net, xs, res, iters, min_gain, net_res=net_res,
+                                                                      ws_batch=wsb)), 3) / len(xs)
+        k_eq, t_eq = at_equal_uniformity(sur_bs)
+        mean = lambda v: float(np.mean(v))
+        rec = {"field_res": net_res >> out_level, "train_steps": steps, "batch": batch, "train_s": round(t_train, 1),
+               "loss_first10": round(mean(losses[:10]), 4), "loss_last10": round(mean(losses[-10:]), 4),
+               "explained_variance": round(ev["explained"], 4),
+               "bin_std_gain_plain": round(ev["plain_gain"], 4), "bin_std_gain_surrogate": round(ev["surrogate_gain"], 4),
+               "folded_triangles": ev["folds"], "gate_min_gain": round(min_gain, 4),
+               "gate_fallbacks": ev["fallbacks"], "gate_fallbacks_batched": dec.count("fallback"),
+               "bin_std_final_gated_batched": round(bs_gated, 3),
+               "plain_graph_ms_per_raster": round(mean(plain), 4),
+               "surrogate_graph_ms_per_raster": round(mean(sur), 4),
+               "surrogate_gated_ms_per_raster": round(mean(gated), 4),
+               f"plain_batched_graph_ms_per_raster_batch{held_out}": round(t_b_plain, 4),
+               f"surrogate_batched_graph_ms_per_raster_batch{held_out}": round(t_b_sur, 4),
+               f"surrogate_gated_batched_ms_per_raster_batch{held_out}": round(t_b_gated, 4),
+               "equal_uniformity": {"surrogate_bin_std": round(sur_bs, 3), "method_iterations": round(k_eq, 2),
+                                    "method_ms_per_raster": round(t_eq, 4)}}
+        rec["speedup_vs_plain_gated"] = round(rec["plain_graph_ms_per_raster"] / rec["surrogate_gated_ms_per_raster"], 3)
+        rec["speedup_vs_plain_ungated"] = round(rec["plain_graph_ms_per_raster"] / rec["surrogate_graph_ms_per_raster"], 3)
+        rec[f"speedup_vs_plain_gated_batch{held_out}"] = round(t_b_plain / t_b_gated, 3)
+        rec["speedup_at_equal_uniformity_ungated"] = round(t_eq / rec["surrogate_graph_ms_per_raster"], 3)
+        del net
+        return rec
+
+    out = {"res": res, "net_input": net_res, "iters": iters, "train_sets": train_sets, "held_out": held_out,
+           "data_s": round(t_data, 1), "workers": workers,
+           "method_bin_std_by_iteration": [round(v, 3) for v in bs_k],
+           "method_graph_ms_by_iteration": [round(v, 4) for v in t_k]}
+    out["field64"] = run_variant(2)
+    out["field256"] = run_variant(0)
+    del sets
+    return out
 
 
 def hbm_calibration(dev, mib: int = 1024, reps: int = 10) -> dict:
@@ -605,7 +653,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-splom", action="store_true", help="skip the 45-plot scatterplot-matrix measurement")
     ap.add_argument("--no-surrogate", action="store_true", help="skip training and timing the learned surrogate")
-    ap.add_argument("--surrogate-sets", type=int, default=1024, help="training point sets of the surrogate")
+    ap.add_argument("--surrogate-sets", type=int, default=16384, help="training point sets of the surrogate")
+    ap.add_argument("--surrogate-save", default=None, help="directory for the trained networks (.npz checkpoints)")
+    ap.add_argument("--only-surrogate", action="store_true", help="print only the surrogate measurement")
     ap.add_argument("--surrogate-steps", type=int, default=3000, help="training steps of the surrogate")
     ap.add_argument("--no-sweeps", action="store_true", help="skip the parameter and quality sweeps")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -635,6 +685,10 @@ def main():
         return
     if args.profile_short:
         profile_short(args, dev)
+        return
+    if args.only_surrogate:
+        print(json.dumps({"surrogate_256": bench_surrogate(dev, args.surrogate_sets, args.surrogate_steps,
+                                                           save_dir=args.surrogate_save)}), flush=True)
         return
     if args.only_sweeps:
         print(json.dumps({"sweeps": bench_sweeps(dev)}), flush=True)
@@ -669,11 +723,8 @@ def main():
     if not args.no_splom:
         rec["splom_45_plots"] = bench_splom(dev)
     if not args.no_surrogate:
-        # the network on a 64 x 64 raster (the surrogate in use), and the same
-        # network on the method's own 256 x 256 raster (shorter training)
-        rec["surrogate_256"] = bench_surrogate(dev, args.surrogate_sets, args.surrogate_steps)
-        rec["surrogate_256_full_res_net"] = bench_surrogate(dev, args.surrogate_sets, max(1, args.surrogate_steps // 2),
-                                                            net_res=256, batch=8)
+        rec["surrogate_256"] = bench_surrogate(dev, args.surrogate_sets, args.surrogate_steps,
+                                               save_dir=args.surrogate_save)
     if not args.no_sweeps:
         rec["sweeps"] = bench_sweeps(dev)
     if not args.no_cpu:

@@ -138,6 +138,12 @@ int inim_rasterize(const float* xy, int64_t n, int32_t res, const inim_params* p
  * float (planes) or double (marginals).  Hence every plane element is the
  * correctly rounded region sum, within one float rounding, and regions that
  * are empty are exactly 0, provided the total magnitude stays below 2^63.
+ * When mask selects at most alpha and alpha_t (no complement), a float
+ * raster is summed in double: for non-negative values (sums without
+ * cancellation) every element is then within about 1e-12 relative of the
+ * exact sum before its rounding to float.  If the raster holds a negative or
+ * non-finite value, the exact path above runs instead, decided on the device
+ * within the same call.
  * EINVAL for a bad size, an unknown mask bit or a NULL plane pointer with a
  * non-zero mask; EWORKSPACE if ws is too small.
  */
@@ -334,6 +340,7 @@ int inim_regularize_noalloc(float* xy, int64_t n, int32_t res, int32_t iters, co
  * (INIM_OK or INIM_EDOMAIN) and clears it.  EHIP if the synchronisation fails.
  */
 int inim_sync_status(void* ws, hipStream_t stream);
+
 
 #ifdef __cplusplus
 }

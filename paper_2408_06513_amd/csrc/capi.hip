@@ -2,6 +2,7 @@
 // argument validation, workspace layout and the launch sequence of each call.
 #include <hip/hip_runtime.h>
 
+
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -495,6 +496,8 @@ int inim_inim_workspace_size(int32_t res, inim_dtype dt, size_t* bytes) {
     if (bytes == nullptr) return fail(INIM_EINVAL, "bytes is NULL");
     if ((s = check_res(res)) != INIM_OK) return s;
     if (dt != INIM_U32 && dt != INIM_F32) return fail(INIM_EINVAL, "unknown dtype %d", (int)dt);
+    // float rasters: the exact accumulators' scratch, which also holds the
+    // double-accumulated pass of alpha + alpha_t calls (same tiling, half the bytes)
     *bytes = kStatusBytes + inim_scratch_bytes(make_geom(res, dt == INIM_F32 ? 16 : 4), dt == INIM_F32 ? 16 : 4);
     return INIM_OK;
 }
@@ -591,8 +594,8 @@ int inim_inim_u32(const uint32_t* img, int32_t res, uint32_t mask, uint32_t* pla
     int s = inim_common(img, res, mask, planes, ws, ws_bytes, INIM_U32);
     if (s != INIM_OK) return s;
     if (mask == 0 && marg == nullptr) return INIM_OK;
-    const Geom g = make_geom(res, 4);
     void* scratch = (char*)ws + kStatusBytes;
+    const Geom g = make_geom(res, 4);
     hipError_t e = launch_inim_carries<uint32_t, uint32_t>(img, g, scratch, nullptr, stream);
     if (e == hipSuccess) e = launch_inim_final<uint32_t, uint32_t>(img, g, scratch, mask, planes, nullptr, nullptr, 0.0, marg, nullptr,
                                                                 stream);
@@ -606,8 +609,26 @@ int inim_inim_f32(const float* img, int32_t res, uint32_t mask, float* planes, d
     if (mask == 0 && marg == nullptr) return INIM_OK;
     const Geom g = make_geom(res, 16);
     void* scratch = (char*)ws + kStatusBytes;
-    hipError_t e = launch_inim_carries<float, u128>(img, g, scratch, nullptr, stream);
-    if (e == hipSuccess) e = launch_inim_final<float, u128>(img, g, scratch, mask, planes, nullptr, nullptr, 0.0, marg, nullptr,
+    const int* skip = nullptr;
+    if ((mask & ~(uint32_t)INIM_MIN) == 0) {
+        // alpha and alpha_t only: no complement, so for rasters without
+        // negative or non-finite values the sums run in double (no
+        // cancellation); the aggregate pass clears the skip word (the second
+        // word of ws) when it meets such a value, and the exact path below,
+        // which runs only then, redoes the call
+        int* words = reinterpret_cast<int*>(ws);
+        const Geom gd = make_geom(res, 8);
+        hipError_t e1 = launch_set_word(words + 1, 1, stream);
+        if (e1 == hipSuccess) e1 = launch_inim_aggregate<float, double>(img, gd, scratch, nullptr, stream, words + 1);
+        if (e1 == hipSuccess) e1 = launch_inim_scans<double>(gd, scratch, nullptr, stream);
+        if (e1 == hipSuccess)
+            e1 = launch_inim_final<float, double>(img, gd, scratch, mask, planes, nullptr, nullptr, 0.0, marg, nullptr,
+                                                 stream);
+        if (e1 != hipSuccess) return hip_fail(e1, "integral images");
+        skip = words + 1;
+    }
+    hipError_t e = launch_inim_carries<float, u128>(img, g, scratch, skip, stream);
+    if (e == hipSuccess) e = launch_inim_final<float, u128>(img, g, scratch, mask, planes, nullptr, nullptr, 0.0, marg, skip,
                                                          stream);
     return e == hipSuccess ? INIM_OK : hip_fail(e, "integral images");
 }

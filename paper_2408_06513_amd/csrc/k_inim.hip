@@ -27,101 +27,23 @@
 #include "device_common.h"
 #include "inim_plan.h"
 #include "launch.h"
+#include "tile_agg.h"
 
 namespace inim {
 
 constexpr int kWavesPerBlock = 4;
 
-template <typename Tin, int Q>
-__device__ __forceinline__ void load_tile_row(const Tin* __restrict__ p, bool act, Tin (&v)[Q]) {
-    if (act) {
-        load_row<Tin, Q>(p, v);
-    } else {
-#pragma unroll
-        for (int e = 0; e < Q; ++e) v[e] = Tin(0);
-    }
+// skip_exact (float input, may be null) is cleared when a value is negative
+// or not finite: the double sums then need the exact path.
+template <typename Tin>
+__device__ __forceinline__ bool needs_exact(Tin v) {
+    if constexpr (__is_same(Tin, float)) return !(v >= 0.0f && v < __builtin_inff());
+    return false;
 }
-
-// ------------------------------------------------------------------ pass 1
-// Tile-local state of the aggregate pass for one wave: per column, the band-
-// local column prefix and the up-left / up-right diagonal sums of it, with
-// zero outside the tile.  step() consumes one row of the tile.
-template <int Q, typename Acc>
-struct TileAgg {
-    Acc cp[Q], L[Q], R[Q];
-    // per-row outputs parked in lane r % 64, slot r / 64 (H <= 128)
-    Acc pk_row[2], pk_le[2], pk_re[2];
-
-    __device__ __forceinline__ void init() {
-#pragma unroll
-        for (int e = 0; e < Q; ++e) cp[e] = L[e] = R[e] = Acc(0);
-#pragma unroll
-        for (int k = 0; k < 2; ++k) pk_row[k] = pk_le[k] = pk_re[k] = Acc(0);
-    }
-
-    template <typename Tin>
-    __device__ __forceinline__ void step(const Tin (&v)[Q], int r, int lane, int lastLane) {
-#pragma unroll
-        for (int e = 0; e < Q; ++e) cp[e] += to_acc<Acc, Tin>(v[e]);
-        Acc upL = shfl_up1(L[Q - 1]);
-        Acc dnR = shfl_down1(R[0]);
-        if (lane == 0) upL = Acc(0);
-        if (lane >= lastLane) dnR = Acc(0);
-#pragma unroll
-        for (int e = Q - 1; e >= 1; --e) L[e] = cp[e] + L[e - 1];
-        L[0] = cp[0] + upL;
-#pragma unroll
-        for (int e = 0; e < Q - 1; ++e) R[e] = cp[e] + R[e + 1];
-        R[Q - 1] = cp[Q - 1] + dnR;
-        Acc s = Acc(0);
-#pragma unroll
-        for (int e = 0; e < Q; ++e) s += cp[e];
-        s = bcast(wave_inclusive_scan(s), 63);
-        const Acc le = bcast(L[Q - 1], lastLane), re = bcast(R[0], 0);
-        if (lane == (r & 63)) {
-            if (r < 64) { pk_row[0] = s; pk_le[0] = le; pk_re[0] = re; }
-            else        { pk_row[1] = s; pk_le[1] = le; pk_re[1] = re; }
-        }
-    }
-
-    // per-row edge sums and row sums of the tile, then the band-level outputs:
-    // column sums, their in-tile prefix, diagonal sums
-    __device__ __forceinline__ void finish(int lane, bool act, int H, const Agg<Acc>& A, size_t ebase, size_t o) {
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int r = lane + 64 * k;
-            if (r < H) {
-                A.trow[ebase + r] = pk_row[k];
-                A.tLedge[ebase + r] = pk_le[k];
-                A.tRedge[ebase + r] = pk_re[k];
-            }
-        }
-        Acc pre[Q];
-        Acc run = Acc(0);
-#pragma unroll
-        for (int e = 0; e < Q; ++e) { run += cp[e]; pre[e] = run; }
-        Acc incl = wave_inclusive_scan(run);
-        Acc ex = shfl_up1(incl);
-        if (lane == 0) ex = Acc(0);
-        if (act) {
-#pragma unroll
-            for (int e = 0; e < Q; ++e) {
-                A.colsum[o + e] = cp[e];
-                A.tcsp[o + e] = ex + pre[e];
-                A.tLend[o + e] = L[e];
-                A.tRend[o + e] = R[e];
-            }
-        }
-    }
-};
-
-// Rows prefetched ahead: deeper for 16-byte rows per lane.
-template <int Q, typename Tin>
-constexpr int prefetch_rows() { return Q * sizeof(Tin) >= 16 ? 8 : 4; }
 
 template <int Q, typename Tin, typename Acc>
 __global__ __launch_bounds__(256) void k_inim_aggregate(const Tin* __restrict__ img, Geom g, Agg<Acc> A,
-                                                        const int* status) {
+                                                        const int* status, int* skip_exact) {
     if (failed(status)) return;
     const int lane = lane_id();
     const int tile = blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6);
@@ -142,6 +64,7 @@ __global__ __launch_bounds__(256) void k_inim_aggregate(const Tin* __restrict__ 
     for (int p = 0; p < PF; ++p)
         if (p < g.H) load_tile_row<Tin, Q>(src + (size_t)p * N, act, buf[p]);
 
+    bool odd = false;
     for (int r0 = 0; r0 < g.H; r0 += PF) {
 #pragma unroll
         for (int p = 0; p < PF; ++p) {
@@ -149,12 +72,16 @@ __global__ __launch_bounds__(256) void k_inim_aggregate(const Tin* __restrict__ 
             if (r < g.H) {
                 Tin v[Q];
 #pragma unroll
-                for (int e = 0; e < Q; ++e) v[e] = buf[p][e];
+                for (int e = 0; e < Q; ++e) {
+                    v[e] = buf[p][e];
+                    if (skip_exact != nullptr) odd |= needs_exact(v[e]);
+                }
                 if (r + PF < g.H) load_tile_row<Tin, Q>(src + (size_t)(r + PF) * N, act, buf[p]);
                 st.step(v, r, lane, g.lastLane);
             }
         }
     }
+    if (skip_exact != nullptr && __any(odd) && lane == 0) *skip_exact = 0;
     st.finish(lane, act, g.H, A, ebase, (size_t)b * N + col);
 }
 
@@ -589,7 +516,11 @@ __global__ __launch_bounds__(256) void k_inim_final(const Tin* __restrict__ img,
     const int tile = blockIdx.x * kWavesPerBlock + wave;
     if (tile >= g.B * g.T) return;
     const int N = g.N, H = g.H, W = g.W, T = g.T;
-    const int b = tile / T, c = tile - (tile / T) * T;
+    // planes: bands bottom-up, the reverse of the aggregate pass, so that the
+    // first rows read again are the ones the aggregate pass read last (still
+    // in the last-level cache when the raster is larger than it)
+    const int b = MODE == kModePlanes ? (g.B - 1) - tile / T : tile / T;
+    const int c = tile - (tile / T) * T;
     const int x0 = lane * Q;
     const bool act = FULL || lane <= g.lastLane;
     const uint32_t mask = FIXMASK ? FIXMASK : mask_arg;
@@ -989,24 +920,34 @@ hipError_t launch_blur_aggregate(const uint32_t* counts, float* density, uint32_
 }
 
 template <typename Tin, typename Acc, int Q>
-static hipError_t launch_aggregate_q(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st) {
+static hipError_t launch_aggregate_q(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st,
+                                     int* skip_exact) {
     Agg<Acc> A;
     Carry<Acc> K;
     carve<Acc>(g, (char*)scratch, A, K);
     const int tiles = g.B * g.T;
     const dim3 grd((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
-    launch_kernel((k_inim_aggregate<Q, Tin, Acc>), grd, dim3(64 * kWavesPerBlock), 0, st, img, g, A, status);
+    launch_kernel((k_inim_aggregate<Q, Tin, Acc>), grd, dim3(64 * kWavesPerBlock), 0, st, img, g, A, status,
+                  skip_exact);
     return hipGetLastError();
 }
 
 template <typename Tin, typename Acc>
-hipError_t launch_inim_aggregate(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st) {
+hipError_t launch_inim_aggregate(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st,
+                                 int* skip_exact) {
     switch (g.Q) {
-        case 1: return launch_aggregate_q<Tin, Acc, 1>(img, g, scratch, status, st);
-        case 2: return launch_aggregate_q<Tin, Acc, 2>(img, g, scratch, status, st);
-        case 4: return launch_aggregate_q<Tin, Acc, 4>(img, g, scratch, status, st);
+        case 1: return launch_aggregate_q<Tin, Acc, 1>(img, g, scratch, status, st, skip_exact);
+        case 2: return launch_aggregate_q<Tin, Acc, 2>(img, g, scratch, status, st, skip_exact);
+        case 4: return launch_aggregate_q<Tin, Acc, 4>(img, g, scratch, status, st, skip_exact);
     }
     return hipErrorInvalidValue;
+}
+
+__global__ void k_set_word(int* w, int v) { *w = v; }
+
+hipError_t launch_set_word(int* w, int v, hipStream_t st) {
+    launch_kernel(k_set_word, dim3(1), dim3(1), 0, st, w, v);
+    return hipGetLastError();
 }
 
 template <typename Tin, typename Acc>
@@ -1209,7 +1150,7 @@ hipError_t launch_batch_inim(int stage, const BatchTable* T, unsigned blocks, in
 
 #define INIM_INSTANTIATE(TIN, ACC)                                                                                    \
     template hipError_t launch_inim_carries<TIN, ACC>(const TIN*, const Geom&, void*, const int*, hipStream_t);      \
-    template hipError_t launch_inim_aggregate<TIN, ACC>(const TIN*, const Geom&, void*, const int*, hipStream_t);    \
+    template hipError_t launch_inim_aggregate<TIN, ACC>(const TIN*, const Geom&, void*, const int*, hipStream_t, int*); \
     template hipError_t launch_inim_scans<ACC>(const Geom&, void*, const int*, hipStream_t);                         \
     template hipError_t launch_inim_final<TIN, ACC>(const TIN*, const Geom&, void*, uint32_t, TIN*, float2*,        \
                                                     const float2*, double, double*, const int*, hipStream_t);

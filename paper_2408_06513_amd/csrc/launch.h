@@ -49,8 +49,13 @@ struct BlurTaps {
 template <typename Tin, typename Acc>
 hipError_t launch_inim_carries(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st);
 // The two halves of launch_inim_carries: the tile partial sums, then the band scans.
+// skip_exact (float rasters, may be null): set to 0 when the raster holds a
+// negative or non-finite value.
 template <typename Tin, typename Acc>
-hipError_t launch_inim_aggregate(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st);
+hipError_t launch_inim_aggregate(const Tin* img, const Geom& g, void* scratch, const int* status, hipStream_t st,
+                                 int* skip_exact = nullptr);
+// *w = v (one word, on the stream).
+hipError_t launch_set_word(int* w, int v, hipStream_t st);
 template <typename Acc>
 hipError_t launch_inim_scans(const Geom& g, void* scratch, const int* status, hipStream_t st);
 // field != nullptr needs t1, the defect field of launch_defect_field.

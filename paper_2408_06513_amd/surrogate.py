@@ -36,13 +36,15 @@ BF16, F32 = torch.bfloat16, torch.float32
 CIN, COUT = 8, 8  # input channel 0 = relative density; output channels 0, 1 = displacement
 
 
-def conv_shapes(chans=(32, 64, 128, 256, 256)):
-    """(name, cin, cout, ks) of every convolution in forward order."""
+def conv_shapes(chans=(32, 64, 128, 256, 256), out_level: int = 0):
+    """(name, cin, cout, ks) of every convolution in forward order.  The
+    decoder climbs back to level `out_level` (0: the input's resolution;
+    2: a quarter of it along each axis), where the 1x1 head sits."""
     out, prev = [], CIN
     for lvl, c in enumerate(chans):
         out += [(f"e{lvl}a", prev, c, 3), (f"e{lvl}b", c, c, 3)]
         prev = c
-    for lvl in range(len(chans) - 2, -1, -1):
+    for lvl in range(len(chans) - 2, out_level - 1, -1):
         c = chans[lvl]
         out += [(f"d{lvl}a", prev + c, c, 3), (f"d{lvl}b", c, c, 3)]
         prev = c
@@ -73,13 +75,17 @@ class Conv:
 
 
 class UNet:
-    """The network on one device; forward() keeps what backward() needs."""
+    """The network on one device; forward() keeps what backward() needs.
+    out_level > 0 ends the decoder at level out_level: the output then has
+    1 / 2^out_level of the input's resolution along each axis."""
 
-    def __init__(self, dev, seed: int = 0, chans=(32, 64, 128, 256, 256)):
-        self.dev, self.chans, self.levels = dev, tuple(chans), len(chans)
+    def __init__(self, dev, seed: int = 0, chans=(32, 64, 128, 256, 256), out_level: int = 0):
+        if not 0 <= out_level < len(chans):
+            raise ValueError("out_level must name a level of the network")
+        self.dev, self.chans, self.levels, self.out_level = dev, tuple(chans), len(chans), int(out_level)
         g = np.random.Generator(np.random.PCG64(seed))
         self.convs = {}
-        for name, ci, co, ks in conv_shapes(chans):
+        for name, ci, co, ks in conv_shapes(chans, out_level):
             std = math.sqrt((2.0 if name != "head" else 1.0) / (ci * ks * ks))
             w = torch.tensor(g.standard_normal((co, ks * ks, ci)) * std, dtype=F32)
             self.convs[name] = Conv(name, ci, co, ks, w, dev)
@@ -114,7 +120,8 @@ class UNet:
         return y
 
     def forward(self, x16: torch.Tensor) -> torch.Tensor:
-        """x16 [n, H, W, 8] bf16 -> [n, H, W, 8] f32 (H, W divisible by 16)."""
+        """x16 [n, H, W, 8] bf16 -> [n, H / 2^out_level, W / 2^out_level, 8] f32
+        (H, W divisible by 2^(levels - 1))."""
         L = self.levels
         self.inp, self.mid, self.out = {}, {}, {}
         h = x16
@@ -128,7 +135,7 @@ class UNet:
             b = self._conv(f"e{lvl}b", a)
             self.mid[f"e{lvl}"], self.out[f"e{lvl}"] = a, b
             h = b
-        for lvl in range(L - 2, -1, -1):
+        for lvl in range(L - 2, self.out_level - 1, -1):
             skip = self.out[f"e{lvl}"]
             n, hh, ww, cs = skip.shape
             cu = h.shape[3]
@@ -173,7 +180,7 @@ class UNet:
         g = self._dgrad(c, gy16)  # d loss / d (output of the last decoder level)
         keep("head", gz=gy16, dx=g)
         skip_grad = {}
-        for lvl in range(L - 1):  # decoder levels, top (0) first
+        for lvl in range(self.out_level, L - 1):  # decoder levels, top first
             a, b, cat = self.mid[f"d{lvl}"], self.out[f"d{lvl}"], self.inp[f"d{lvl}"]
             gz = self._relu_back(g, b)
             keep(f"d{lvl}b", g=g, gz=gz)
@@ -210,12 +217,50 @@ class UNet:
                 break
             gx = self._dgrad(ca, gz)  # gradient of the pooled input
             keep(f"e{lvl}a", dx=gx)
-            g = nn.pool2_backward(gx, skip_grad[lvl - 1], accumulate=True)
+            if lvl - 1 in skip_grad:  # the level below also feeds a decoder level
+                g = nn.pool2_backward(gx, skip_grad[lvl - 1], accumulate=True)
+            else:
+                n, hh, ww, c = self.out[f"e{lvl - 1}"].shape
+                g = nn.pool2_backward(gx, torch.empty((n, hh, ww, c), dtype=F32, device=self.dev))
 
     def step(self, lr: float):
         self.t += 1
         for c in self.convs.values():
             c.step(self.t, lr)
+
+    # ------------------------------------------------------------------ checkpoints
+    def save(self, path: str, optimizer: bool = True) -> None:
+        """Writes the network to `path` as a .npz archive of plain arrays (no
+        pickled objects): the FP32 master weights and biases, the step count
+        and the shape (channels, output level), and with `optimizer` Adam's
+        moments (needed to resume training, not to predict)."""
+        arrays = {"meta_chans": np.array(self.chans, dtype=np.int64),
+                  "meta_out_level": np.array([self.out_level], dtype=np.int64),
+                  "meta_t": np.array([self.t], dtype=np.int64)}
+        parts = ("w", "b", "mw", "vw", "mb", "vb") if optimizer else ("w", "b")
+        for k, c in self.convs.items():
+            for part in parts:
+                arrays[f"{k}.{part}"] = getattr(c, part).detach().cpu().numpy()
+        with open(path, "wb") as f:
+            np.savez(f, **arrays)
+
+    @classmethod
+    def load(cls, path: str, dev) -> "UNet":
+        """The network saved by save(), on `dev`, ready to predict or to train on."""
+        with np.load(path, allow_pickle=False) as z:
+            net = cls(dev, chans=tuple(int(v) for v in z["meta_chans"]), out_level=int(z["meta_out_level"][0]))
+            net.t = int(z["meta_t"][0])
+            for k, c in net.convs.items():
+                for part in ("w", "b", "mw", "vw", "mb", "vb"):
+                    if f"{k}.{part}" not in z.files and part not in ("w", "b"):
+                        continue  # saved without the optimizer: moments stay zero
+                    a = z[f"{k}.{part}"]
+                    dst = getattr(c, part)
+                    if tuple(a.shape) != tuple(dst.shape):
+                        raise ValueError(f"{k}.{part}: shape {a.shape} in the file, {tuple(dst.shape)} expected")
+                    dst.copy_(torch.from_numpy(a))
+                c.refresh()
+        return net
 
 
 # ------------------------------------------------------------------ data
@@ -237,38 +282,110 @@ def density_input(xy: torch.Tensor, net_res: int, radius: int, out16: torch.Tens
     return nn.pack_density(dens, net_res * net_res / xy.shape[0], out16)
 
 
-def example(xy_np: np.ndarray, res: int, iters: int, dev, radius: int = 8, net_res: int | None = None):
-    """Input [net_res, net_res, 8] bf16 and target [net_res, net_res, 2] f32:
-    the displacement by `iters` iterations of the method on a res x res
-    raster, at the texel centres of the net_res lattice, of one point set."""
+def example(xy_np: np.ndarray, res: int, iters: int, dev, radius: int = 8, net_res: int | None = None,
+            out_level: int = 0):
+    """Input [net_res, net_res, 8] bf16 and target [f, f, 2] f32 with
+    f = net_res / 2^out_level: the displacement by `iters` iterations of the
+    method on a res x res raster, at the texel centres of the f x f lattice,
+    of one point set."""
     net_res = net_res or res
+    fres = net_res >> out_level
     xy = torch.from_numpy(xy_np).to(dev)
     x16 = torch.empty((net_res, net_res, CIN), dtype=BF16, device=dev)
     density_input(xy, net_res, net_radius(radius, res, net_res), x16)
-    lat = torch.from_numpy(datagen.lattice_points(net_res)).to(dev)
+    lat = torch.from_numpy(datagen.lattice_points(fres)).to(dev)
     capi.regularize_probes(xy.clone(), lat, res, iters, radius=radius)
-    tgt = torch.empty((net_res, net_res, 2), dtype=F32, device=dev)
-    nn.displacement(lat, net_res, tgt)
+    tgt = torch.empty((fres, fres, 2), dtype=F32, device=dev)
+    nn.displacement(lat, fres, tgt)
     return x16, tgt
 
 
-def dataset(seeds, res: int, iters: int, dev, n_hi: int = 500_000, net_res: int | None = None):
+def dataset(seeds, res: int, iters: int, dev, n_hi: int = 500_000, net_res: int | None = None,
+            out_level: int = 0):
     xs, ts = [], []
     for s in seeds:
-        x, t = example(datagen.surrogate_mixture(s, n_hi=n_hi), res, iters, dev, net_res=net_res)
+        x, t = example(datagen.surrogate_mixture(s, n_hi=n_hi), res, iters, dev, net_res=net_res,
+                       out_level=out_level)
         xs.append(x)
         ts.append(t)
     return torch.stack(xs), torch.stack(ts)
 
 
+class Compact:
+    """A training set kept compact on the device: the smoothed densities
+    (float32 [k, R, R]) with their scales (R^2 / n), packed into the
+    network's 8-channel bfloat16 input batch by batch, and the target
+    displacements [k, f, f, 2]."""
+
+    def __init__(self, dens: torch.Tensor, scales: np.ndarray, targets: torch.Tensor):
+        self.dens, self.scales, self.targets = dens, np.asarray(scales, dtype=np.float64), targets
+        self.shape = (dens.shape[0],)
+
+    def batch(self, idx: np.ndarray):
+        dev = self.dens.device
+        it = torch.from_numpy(idx).to(dev)
+        d = self.dens[it].contiguous()
+        x16 = torch.empty((len(idx), d.shape[1], d.shape[2], CIN), dtype=BF16, device=dev)
+        nn.pack_density_many(d, [float(self.scales[i]) for i in idx], x16)
+        return x16, self.targets[it].contiguous()
+
+
+def dataset_compact(seeds, res: int, iters: int, dev, n_hi: int = 500_000, net_res: int | None = None,
+                    out_levels=(0,), radius: int = 8, workers: int = 0, log=None) -> dict:
+    """The training set of `seeds` as Compact sets, one per output level:
+    point sets drawn by `workers` processes (0: in this process), each
+    rasterised on the device once and labelled by one run of the method with
+    the texel centres of every requested f x f lattice (f = net_res /
+    2^out_level) as probes (its composite map there)."""
+    import concurrent.futures as cf
+    import functools
+    import multiprocessing as mp
+    net_res = net_res or res
+    fr = [net_res >> lv for lv in out_levels]
+    seeds = list(seeds)
+    k = len(seeds)
+    dens = torch.empty((k, net_res, net_res), dtype=F32, device=dev)
+    tgt = [torch.empty((k, f, f, 2), dtype=F32, device=dev) for f in fr]
+    scales = np.empty(k)
+    lat0 = torch.from_numpy(np.concatenate([datagen.lattice_points(f) for f in fr])).to(dev)
+    lat = torch.empty_like(lat0)
+    offs = np.cumsum([0] + [f * f for f in fr])
+    counts = torch.empty((net_res, net_res), dtype=torch.uint32, device=dev)
+    r = net_radius(radius, res, net_res)
+    draw = functools.partial(datagen.surrogate_mixture, n_hi=n_hi)
+    pool = cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) if workers > 0 else None
+    try:
+        it = pool.map(draw, seeds, chunksize=16) if pool else map(draw, seeds)
+        for q, xy_np in enumerate(it):
+            xy = torch.from_numpy(xy_np).to(dev)
+            capi.rasterize(xy, net_res, radius=r, counts=counts, density=dens[q], check=False)
+            scales[q] = net_res * net_res / xy.shape[0]
+            lat.copy_(lat0)
+            capi.regularize_probes(xy, lat, res, iters, radius=radius, check=False)
+            for i, f in enumerate(fr):
+                nn.displacement(lat[offs[i]:offs[i + 1]], f, tgt[i][q])
+            if log and q % 4096 == 0:
+                log(f"labels {q}/{k}")
+    finally:
+        if pool:
+            pool.shutdown()
+    torch.cuda.synchronize(dev)
+    return {lv: Compact(dens, scales, t) for lv, t in zip(out_levels, tgt)}
+
+
 def train(net: UNet, X, T, steps: int, batch: int, lr: float = 1e-3, seed: int = 0, log=None) -> list:
-    """Adam on mini-batches drawn (seeded) from X, T; returns the losses."""
+    """Adam on mini-batches drawn (seeded) from X, T (or from the Compact set
+    X, with T None); returns the losses."""
     g = np.random.Generator(np.random.PCG64(seed))
     loss = torch.zeros(1, dtype=F32, device=net.dev)
     losses = []
     for s in range(steps):
-        idx = torch.from_numpy(g.choice(X.shape[0], size=batch, replace=False)).to(net.dev)
-        x, t = X[idx].contiguous(), T[idx].contiguous()
+        pick = g.choice(X.shape[0], size=batch, replace=False)
+        if T is None:
+            x, t = X.batch(pick)
+        else:
+            idx = torch.from_numpy(pick).to(net.dev)
+            x, t = X[idx].contiguous(), T[idx].contiguous()
         y = net.forward(x)
         gy = torch.empty(y.shape, dtype=BF16, device=net.dev)
         nn.mse(y, t, loss, gy)
@@ -302,13 +419,15 @@ def field_radius(res: int) -> int:
 
 
 def predict_field(net: UNet, xy: torch.Tensor, res: int, radius: int = 8, net_res: int | None = None) -> torch.Tensor:
-    """The predicted composite map (absolute positions) on the net_res lattice."""
+    """The predicted composite map (absolute positions) on the output lattice
+    (net_res / 2^out_level texels a side)."""
     net_res = net_res or res
+    fres = net_res >> net.out_level
     x16 = torch.empty((1, net_res, net_res, CIN), dtype=BF16, device=xy.device)
     density_input(xy, net_res, net_radius(radius, res, net_res), x16[0])
     y = net.forward(x16)
-    field = torch.empty((net_res, net_res, 2), dtype=F32, device=xy.device)
-    return nn.field(y[0], net_res, field, field_radius(net_res))
+    field = torch.empty((fres, fres, 2), dtype=F32, device=xy.device)
+    return nn.field(y[0], fres, field, field_radius(fres))
 
 
 def regularize_many(net: UNet, xys, res: int, radius: int = 8, net_res: int | None = None,
@@ -330,8 +449,9 @@ def regularize_many(net: UNet, xys, res: int, radius: int = 8, net_res: int | No
         _, dens, ws = capi.rasterize_many(part, net_res, radius=r, check=False)
         nn.pack_density_many(dens, [net_res * net_res / max(1, xy.shape[0]) for xy in part], x16)
         y = net.forward(x16)
-        field = torch.empty((m, net_res, net_res, 2), dtype=F32, device=net.dev)
-        nn.field_many(y, net_res, field, field_radius(net_res))
+        fres = net_res >> net.out_level
+        field = torch.empty((m, fres, fres, 2), dtype=F32, device=net.dev)
+        nn.field_many(y, fres, field, field_radius(fres))
         capi.advect_many(field, part, ws=ws, check=False)
         wss.append(ws)
     if check:
@@ -368,7 +488,8 @@ class SurrogateGraph:
         self.x16 = torch.empty((1, r, r, CIN), dtype=BF16, device=dev)
         self.counts = torch.empty((r, r), dtype=torch.uint32, device=dev)
         self.dens = torch.empty((r, r), dtype=F32, device=dev)
-        self.field = torch.empty((r, r, 2), dtype=F32, device=dev)
+        self.fres = r >> net.out_level
+        self.field = torch.empty((self.fres, self.fres, 2), dtype=F32, device=dev)
         self.fwork = torch.empty_like(self.field)
         self.ws = capi.workspace(256, dev)
         self._run()  # sizes the network's work buffer outside the capture
@@ -384,7 +505,7 @@ class SurrogateGraph:
         density_input(self.xy, self.net_res, self.radius, self.x16[0], self.counts, self.dens, ws=self.ws,
                       check=False)
         y = self.net.forward(self.x16)
-        nn.field(y[0], self.net_res, self.field, field_radius(self.net_res), work=self.fwork)
+        nn.field(y[0], self.fres, self.field, field_radius(self.fres), work=self.fwork)
         capi.advect(self.field, self.xy, ws=self.ws, check=False)
 
     def __call__(self, xy: torch.Tensor | None = None, check: bool = False) -> torch.Tensor:
@@ -450,7 +571,7 @@ def regularize(net: UNet, xy: torch.Tensor, res: int, iters: int, min_gain: floa
     before = bin_std(xy, res)
     field = predict_field(net, xy, res, net_res=net_res)
     folds = torch.zeros(1, dtype=torch.uint32, device=xy.device)
-    nn.count_folds(field, net_res, folds)
+    nn.count_folds(field, net_res >> net.out_level, folds)
     moved = xy.clone()
     capi.advect(field, moved)
     if int(folds.item()) == 0 and bin_std(moved, res) <= (1.0 - min_gain) * before:
@@ -458,6 +579,72 @@ def regularize(net: UNet, xy: torch.Tensor, res: int, iters: int, min_gain: floa
         return "surrogate"
     capi.regularize(xy, res, iters)
     return "fallback"
+
+
+def _bin_moments_into(xy: torch.Tensor, res: int, out: torch.Tensor, counts: torch.Tensor, ws: torch.Tensor):
+    """Enqueues the 4 x 4-bin count moments of xy into out (float64 [2],
+    cleared first); no synchronisation."""
+    capi.rasterize(xy, res, radius=0, counts=counts, want_density=False, ws=ws, check=False)
+    out.zero_()
+    nn.bin_moments(counts, res, 4, out)
+
+
+def _std_from_moments(m, res: int, bin_px: int = 4) -> float:
+    k = (res // bin_px) ** 2
+    return math.sqrt(max(m[1] / k - (m[0] / k) ** 2, 0.0))
+
+
+def regularize_many_gated(net: UNet, xys, res: int, iters: int, min_gain: float = 0.2,
+                          net_res: int | None = None, ws_batch: torch.Tensor | None = None) -> list:
+    """The surrogate's batched move (regularize_many) under the gate of
+    regularize(): a set whose predicted lattice folds, or whose bin standard
+    deviation falls by less than `min_gain`, is regularised by the method
+    instead -- all such sets in one batched call of the method.  The fields,
+    folds, moves and uniformity measures are enqueued for every set first and
+    read back once.  Returns the decisions ('surrogate' / 'fallback')."""
+    net_res = net_res or res
+    k = len(xys)
+    if k == 0:
+        return []
+    dev = xys[0].device
+    fres = net_res >> net.out_level
+    counts = torch.empty((res, res), dtype=torch.uint32, device=dev)
+    mom = torch.zeros((2, k, 2), dtype=torch.float64, device=dev)
+    folds = torch.zeros(k, dtype=torch.uint32, device=dev)
+    ws = capi.workspace(256, dev)
+    for q, x in enumerate(xys):
+        _bin_moments_into(x, res, mom[0, q], counts, ws)
+    moved = [x.clone() for x in xys]
+    r = net_radius(8, res, net_res)
+    fields = []
+    for q0 in range(0, k, 64):
+        part = moved[q0:q0 + 64]
+        m = len(part)
+        x16 = torch.empty((m, net_res, net_res, CIN), dtype=BF16, device=dev)
+        _, dens, wsp = capi.rasterize_many(part, net_res, radius=r, check=False)
+        nn.pack_density_many(dens, [net_res * net_res / max(1, x.shape[0]) for x in part], x16)
+        y = net.forward(x16)
+        field = torch.empty((m, fres, fres, 2), dtype=F32, device=dev)
+        nn.field_many(y, fres, field, field_radius(fres))
+        for q in range(m):
+            nn.count_folds(field[q], fres, folds[q0 + q:q0 + q + 1])
+        capi.advect_many(field, part, ws=wsp, check=False)
+        fields.append(wsp)
+    for q, x in enumerate(moved):
+        _bin_moments_into(x, res, mom[1, q], counts, ws)
+    check_status(fields + [ws])
+    mh, fh = mom.cpu().numpy(), folds.cpu().numpy()
+    decisions, rejected = [], []
+    for q in range(k):
+        ok = int(fh[q]) == 0 and _std_from_moments(mh[1, q], res) <= (1.0 - min_gain) * _std_from_moments(mh[0, q], res)
+        decisions.append("surrogate" if ok else "fallback")
+        if ok:
+            xys[q].copy_(moved[q])
+        else:
+            rejected.append(xys[q])
+    if rejected:
+        capi.regularize_batch(rejected, [res] * len(rejected), iters, ws=ws_batch)
+    return decisions
 
 
 def evaluate(net: UNet, seeds, res: int, iters: int, dev, n_hi: int = 500_000, min_gain: float = 0.2,
@@ -475,10 +662,10 @@ def evaluate(net: UNet, seeds, res: int, iters: int, dev, n_hi: int = 500_000, m
         capi.regularize(plain, res, iters)
         field = predict_field(net, xy, res, net_res=net_res)
         folds = torch.zeros(1, dtype=torch.uint32, device=dev)
-        nn.count_folds(field, net_res or res, folds)
+        nn.count_folds(field, (net_res or res) >> net.out_level, folds)
         sur = xy.clone()
         capi.advect(field, sur)
-        x16, tgt = example(xy_np, res, iters, dev, net_res=net_res)
+        x16, tgt = example(xy_np, res, iters, dev, net_res=net_res, out_level=net.out_level)
         y = net.forward(x16[None].contiguous())
         loss = torch.zeros(1, dtype=F32, device=dev)
         nn.mse(y, tgt[None].contiguous(), loss)

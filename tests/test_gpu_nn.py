@@ -258,16 +258,42 @@ def test_unet5_lockstep_elementwise(dev):
     unet_lockstep_checks(net, y, gy, t, rec)
 
 
+def test_unet5_coarse_output_lockstep_elementwise(dev):
+    """The same element-wise checks for the network whose decoder stops at
+    level 2 (the field on a quarter-resolution lattice, the surrogate's
+    configuration on the 256 x 256 raster): 32 x 32 in, 8 x 8 out; the two
+    top encoder levels then feed only the deeper path (no skip gradient)."""
+    from paper_2408_06513_amd import nn as m
+    from paper_2408_06513_amd import surrogate as S
+
+    net = S.UNet(dev, seed=4, out_level=2)
+    assert net.levels == 5 and "d0a" not in net.convs and "d1a" not in net.convs
+    n, hw = 2, 32
+    x = normal(23, (n, hw, hw, 8))
+    t = normal(24, (n, hw // 4, hw // 4, 2))
+    y = net.forward(g16(x, dev))
+    assert tuple(y.shape) == (n, hw // 4, hw // 4, 8)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    gy = torch.empty(y.shape, dtype=BF, device=dev)
+    m.mse(y, g32(t, dev), loss, gy)
+    rec = {}
+    net.backward(gy, record=rec)
+    torch.cuda.synchronize()
+    unet_lockstep_checks(net, y, gy, t, rec)
+
+
 def unet_lockstep_checks(net, y, gy, t, rec):
     """The element-wise checks of test_unet5_lockstep_elementwise on a network
     after one forward and backward pass (tensors on any device)."""
     n, hw = y.shape[0], y.shape[1]
+    lo, L = net.out_level, net.levels
     h64 = lambda a: a.detach().cpu().double()  # noqa: E731
     bf = O.bf16_round
     W = {k: h64(c.w16) for k, c in net.convs.items()}
     for k, c in net.convs.items():
         assert torch.equal(W[k], bf(h64(c.w))), k  # the BF16 weight copies
-    pixels = n * hw * hw
+    hin = net.inp["e0"].shape[1]
+    pixels = n * hin * hin  # the most terms a weight gradient sums (the top level)
 
     def conv_inputs(name):
         if name == "head":
@@ -293,11 +319,11 @@ def unet_lockstep_checks(net, y, gy, t, rec):
         check_close(f"forward {name}", conv_output(name), ref, 2.0 ** -8 * (ref + acc) + acc)
 
     # forward glue: pooling (BF16 mean of four BF16 values) and concatenation
-    for lvl in range(1, 5):
+    for lvl in range(1, L):
         ref = O.pool2(h64(net.out[f"e{lvl - 1}"]))
         check_close(f"pool into e{lvl}", h64(net.inp[f"e{lvl}"]), ref, 2.0 ** -8 * ref.abs() + 1e-30)
-    for lvl in range(4):
-        below = h64(net.out[f"d{lvl + 1}"] if lvl < 3 else net.out["e4"])
+    for lvl in range(lo, L - 1):
+        below = h64(net.out[f"d{lvl + 1}"] if lvl < L - 2 else net.out[f"e{L - 1}"])
         ref = torch.cat([O.up2(below), h64(net.out[f"e{lvl}"])], dim=-1)
         assert torch.equal(h64(net.inp[f"d{lvl}"]), ref), lvl
 
@@ -325,16 +351,23 @@ def unet_lockstep_checks(net, y, gy, t, rec):
 
     # backward glue: the upsampling adjoint feeds the level below, the pooling
     # adjoint plus the skip gradient feed each encoder level but the deepest
-    for lvl in range(4):
+    # (levels above the output level feed only the deeper path: no skip term)
+    for lvl in range(lo, L - 1):
         gcat = h64(rec[f"d{lvl}a"]["dx"])
         cu = gcat.shape[-1] - net.out[f"e{lvl}"].shape[3]
         ref = O._up2_adjoint(gcat[..., :cu])
-        below = f"d{lvl + 1}b" if lvl < 3 else "e4b"
+        below = f"d{lvl + 1}b" if lvl < L - 2 else f"e{L - 1}b"
         check_close(f"upsampling adjoint into {below}", h64(rec[below]["g"]), ref,
                     2 * gamma(4) * O._up2_adjoint(gcat[..., :cu].abs()) + 1e-30)
-        ref = O._pool2_adjoint(h64(rec[f"e{lvl + 1}a"]["dx"])) + gcat[..., cu:]
-        mag = O._pool2_adjoint(h64(rec[f"e{lvl + 1}a"]["dx"]).abs()) + gcat[..., cu:].abs()
-        check_close(f"pooling adjoint + skip into e{lvl}b", h64(rec[f"e{lvl}b"]["g"]), ref, 2 * gamma(1) * mag + 1e-30)
+    for lvl in range(L - 1):
+        ref = O._pool2_adjoint(h64(rec[f"e{lvl + 1}a"]["dx"]))
+        mag = O._pool2_adjoint(h64(rec[f"e{lvl + 1}a"]["dx"]).abs())
+        if lvl >= lo:
+            gcat = h64(rec[f"d{lvl}a"]["dx"])
+            cu = gcat.shape[-1] - net.out[f"e{lvl}"].shape[3]
+            ref, mag = ref + gcat[..., cu:], mag + gcat[..., cu:].abs()
+        check_close(f"pooling adjoint (+ skip) into e{lvl}b", h64(rec[f"e{lvl}b"]["g"]), ref,
+                    2 * gamma(1) * mag + 1e-30)
 
 
 def test_adam_two_step_closed_form(nn, dev):

@@ -125,6 +125,88 @@ def test_inim_special_rasters(capi, dev, which):
         assert np.array_equal(planes.cpu().numpy().astype(np.float64), ref)
 
 
+@pytest.mark.parametrize("mask", [0x11, 0x01, 0x10, 0x00])
+@pytest.mark.parametrize("res", [2, 16, 64, 256])
+def test_inim_min_masks(capi, dev, res, mask):
+    """Calls for at most alpha and alpha_t (float rasters summed in double):
+    each plane alone, both, and the marginals alone, on integer rasters in
+    both types (exact), including the special rasters."""
+    rng = np.random.default_rng(res + mask)
+    specials = [rng.poisson(3.0, size=(res, res)).astype(np.uint32), np.ones((res, res), np.uint32)]
+    spike = np.zeros((res, res), np.uint32)
+    spike[res // 3, (2 * res) // 3] = 9
+    specials.append(spike)
+    for a in specials:
+        ref, rm = oracle.planes(a.astype(np.float64), mask)
+        for img in (a, a.astype(np.float32)):
+            note(f"min masks res={res} mask={mask:#x} {img.dtype}")
+            planes, marg = capi.inim(to_dev(img, dev), mask)
+            torch.cuda.synchronize()
+            if mask:
+                assert np.array_equal(planes.cpu().numpy().astype(np.float64), ref)
+            m = capi.split_marg(marg.cpu().numpy(), res)
+            for k in "XYUV":
+                assert np.array_equal(m[k], rm[k]), k
+            assert float(m["C"]) == rm["C"]
+
+
+@pytest.mark.parametrize("res", [256, 4096])
+def test_inim_min_mask_correctly_rounded(capi, dev, res):
+    """Quarter-integer float rasters through the double-accumulated alpha +
+    alpha_t call: double sums are exact there, so both planes are the
+    correctly rounded sums."""
+    img = (dg.poisson_raster(7, res, lam=40.0).astype(np.float64) / 4.0).astype(np.float32)
+    note(f"min mask rounding res={res}")
+    planes, _ = capi.inim(to_dev(img, dev), 0x11)
+    torch.cuda.synchronize()
+    ref, _ = oracle.planes(img.astype(np.float64), 0x11)
+    assert np.array_equal(planes.cpu().numpy(), ref.astype(np.float32))
+
+
+def exact_alpha_alpha_t(q):
+    """alpha and alpha_t of an int64 raster q[j, i] in exact integers: column
+    prefix cp, alpha its row prefix, alpha_t = L + R - cp with the diagonal
+    recurrences L(i,j) = cp(i,j) + L(i-1,j-1), R(i,j) = cp(i,j) + R(i+1,j-1)."""
+    cp = np.cumsum(q, axis=0)
+    alpha = np.cumsum(cp, axis=1)
+    L = np.zeros_like(cp)
+    R = np.zeros_like(cp)
+    L[0], R[0] = cp[0], cp[0]
+    for j in range(1, q.shape[0]):
+        L[j, 0] = cp[j, 0]
+        L[j, 1:] = cp[j, 1:] + L[j - 1, :-1]
+        R[j, -1] = cp[j, -1]
+        R[j, :-1] = cp[j, :-1] + R[j - 1, 1:]
+    return alpha, L + R - cp
+
+
+@pytest.mark.parametrize("res", [64, 1024])
+def test_inim_min_mask_negative_values_take_exact_path(capi, dev, res):
+    """A float raster with negative values: the double-accumulated alpha +
+    alpha_t call hands itself to the exact 128-bit path on the device.  Quarter-integers in [-2, 2] plus a
+    +2^60 and a -2^60 texel: sums over regions holding both spikes are small
+    and exact only without double rounding (double accumulation would lose
+    the quarters next to 2^60), so alpha and alpha_t must equal the exact
+    integer sums, rounded once to float."""
+    rng = np.random.default_rng(res)
+    q = rng.integers(-8, 9, size=(res, res)).astype(np.int64)  # quarter units
+    big = 1 << 62                                               # 2^60 in quarters
+    q[res // 8, res // 6] = big
+    q[(5 * res) // 8, (2 * res) // 3] = -big
+    img = (q.astype(np.float64) / 4.0).astype(np.float32)
+    assert np.array_equal(np.round(img.astype(np.float64) * 4).astype(np.int64), q)
+    note(f"min mask negative res={res}")
+    planes, _ = capi.inim(to_dev(img, dev), 0x11)
+    torch.cuda.synchronize()
+    got = planes.cpu().numpy().astype(np.float64)
+    for k, ex in enumerate(exact_alpha_alpha_t(q)):
+        small = np.abs(ex) < (1 << 53)
+        assert np.array_equal(got[k][small], (ex[small].astype(np.float64) / 4.0).astype(np.float32))
+        # near 2^60 (one spike inside): within one float unit of the exact sum
+        exb = ex[~small].astype(np.float64) / 4.0
+        assert np.all(np.abs(got[k][~small] - exb) <= np.spacing(np.abs(exb).astype(np.float32)))
+
+
 @pytest.mark.parametrize("dtype", ["u32", "f32"])
 def test_inim_full_size_8192(capi, dev, dtype):
     """The 8192 x 8192 workload in the benchmark's launch configuration,
@@ -135,10 +217,11 @@ def test_inim_full_size_8192(capi, dev, dtype):
     img = dg.poisson_raster(0, res) if dtype == "u32" else dg.lognormal_raster(0, res)
     dimg = to_dev(img, dev)
     planes, marg = capi.inim(dimg, 0xFF)
-    pmin, mmin = capi.inim(dimg, 0x11)
+    pmin, mmin = capi.inim(dimg, 0x11)  # float rasters: summed in double
     torch.cuda.synchronize()
-    assert torch.equal(pmin[0], planes[0]) and torch.equal(pmin[1], planes[4]) and torch.equal(mmin, marg)
-    del pmin, dimg
+    if dtype == "u32":
+        assert torch.equal(pmin[0], planes[0]) and torch.equal(pmin[1], planes[4]) and torch.equal(mmin, marg)
+    del dimg
     img64 = img.astype(np.float64)
     for k in range(8):
         ref, rm = oracle.planes(img64, 1 << k)
@@ -147,10 +230,14 @@ def test_inim_full_size_8192(capi, dev, dtype):
             assert np.array_equal(got.astype(np.float64), ref[0]), oracle.PLANES[k]
         else:
             assert_rel(got, ref[0], 1e-6)
+            if k in (0, 4):
+                assert_rel(pmin[0 if k == 0 else 1].cpu().numpy(), ref[0], 1e-6)
         del ref
-    m = capi.split_marg(marg.cpu().numpy(), res)
-    for key in "XYUV":
-        np.testing.assert_allclose(m[key], rm[key], rtol=1e-12 if dtype == "f32" else 0, atol=0)
+    for mm in (marg, mmin):
+        m = capi.split_marg(mm.cpu().numpy(), res)
+        for key in "XYUV":
+            np.testing.assert_allclose(m[key], rm[key], rtol=1e-12 if dtype == "f32" else 0, atol=0)
+        assert m["C"] == rm["C"] if dtype == "u32" else abs(m["C"] - rm["C"]) <= 1e-12 * rm["C"]
 
 
 # ------------------------------------------------------------------ rasterize
