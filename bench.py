@@ -269,7 +269,10 @@ def bench_inim(dev, res: int = 8192, reps: int = 20) -> dict:
 
 
 def profile_short(args, dev):
-    """A short run for rocprofv3 --pmc: each kernel of interest a few times."""
+    """A short run for rocprofv3 --pmc: each kernel of interest a few times
+    (a 256 MiB device copy, the calibration of the byte counters; one
+    regularisation of the headline workload; one 8192^2 integral-image call
+    of each type with all planes and with alpha + alpha_t)."""
     import torch
 
     from paper_2408_06513_amd import capi, datagen
@@ -290,6 +293,8 @@ def profile_short(args, dev):
         wsi = capi.workspace(capi.inim_workspace_size(res, dt), dev)
         planes = torch.empty((8, res, res), dtype=img.dtype, device=dev)
         capi.inim(img, 0xFF, planes=planes, ws=wsi)
+        torch.cuda.synchronize()
+        capi.inim(img, 0x11, planes=planes[:2], ws=wsi)  # alpha + alpha_t (float: summed in double)
         torch.cuda.synchronize()
         del img, wsi, planes
     print(json.dumps({"profile_short": "done", "n": args.n, "res": args.res, "iters": args.iters}), flush=True)
@@ -349,17 +354,22 @@ def bench_splom(dev, reps: int = 5) -> dict:
 
 
 def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: int = 16, batch: int = 16,
-                    workers: int = 16, save_dir: str | None = None) -> dict:
+                    workers: int = 16, save_dir: str | None = None, full_field: bool = False) -> dict:
     """The learned surrogate of the 256 x 256, 8-iteration regularisation: a
-    5-level U-Net (32-256 channels) reading the 256 x 256 density raster.
+    5-level U-Net (32-256 channels) reading the 256 x 256 density raster and
+    the displacement of the method's first iteration on it (whose integral
+    images carry the whole raster's mass, which 3 x 3 convolutions over five
+    levels do not reach), predicting the displacement of all eight.
     Two output lattices are trained on the same sets with the same budget:
     the displacement on the 64 x 64 lattice (decoder up to level 2, the
     configuration in use) and on the full 256 x 256 lattice.  Training sets
     are point sets of 2-12 Gaussian components (10k-500k points) drawn by
     worker processes and labelled by the method itself (its composite map at
     the lattice's texel centres).  On held-out sets: uniformity, folds, gate
-    decisions (the gate asks for 90% of the method's own mean bin-std gain,
-    calibrated on training sets), and times per raster -- single and batched,
+    decisions (the gate asks for no folded triangle and a 4 x 4-bin standard
+    deviation at most the method's worst 8-to-1-iteration ratio (x 1.05)
+    times the one after the method's own first step on the same set,
+    calibrated on fresh training-distribution sets), and times per raster -- single and batched,
     ungated and gated -- against the method, also at equal final uniformity
     (the method's time at the fractional iteration count whose bin std equals
     the surrogate's)."""
@@ -371,11 +381,10 @@ def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: i
     res, iters, net_res = 256, 8, 256
     log(f"surrogate: {train_sets} training sets, labels on the 64^2 and 256^2 lattices")
     t0 = time.perf_counter()
-    sets = S.dataset_compact(range(train_sets), res, iters, dev, net_res=net_res, out_levels=(2, 0),
-                             workers=workers, log=log)
+    sets = S.dataset_compact(range(train_sets), res, iters, dev, net_res=net_res,
+                             out_levels=(2, 0) if full_field else (2,), workers=workers, log=log, first_step=True)
     t_data = time.perf_counter() - t0
     seeds = list(range(100_000, 100_000 + held_out))
-    calib = list(range(train_sets, train_sets + 8))  # fresh training-distribution sets for the gate
 
     def ev_time(fn, reps=5):
         a = torch.cuda.Event(enable_timing=True)
@@ -407,13 +416,7 @@ def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: i
             bs_k[k] += S.bin_std(xy, res)
     bs_k /= len(xs0)
     t_k /= len(xs0)
-    gain_cal = []
-    for s in calib:
-        x = torch.from_numpy(datagen.surrogate_mixture(s)).to(dev)
-        b0 = S.bin_std(x, res)
-        capi.regularize(x, res, iters)
-        gain_cal.append(1.0 - S.bin_std(x, res) / b0)
-    min_gain = 0.9 * float(np.mean(gain_cal))
+    ratio = S.calibrate_gate(res, iters, dev)
 
     def at_equal_uniformity(bs):
         """The method's time per raster at the fractional iteration count
@@ -427,7 +430,7 @@ def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: i
 
     def run_variant(out_level: int) -> dict:
         X = sets[out_level]
-        net = S.UNet(dev, seed=0, out_level=out_level)
+        net = S.UNet(dev, seed=0, out_level=out_level, first_step=True)
         log(f"surrogate (field {net_res >> out_level}^2): {steps} steps x {batch}")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -437,7 +440,7 @@ def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: i
         if save_dir:
             os.makedirs(save_dir, exist_ok=True)
             net.save(os.path.join(save_dir, f"surrogate_256_field{net_res >> out_level}.npz"), optimizer=False)
-        ev = S.evaluate(net, seeds, res, iters, dev, net_res=net_res, min_gain=min_gain)
+        ev = S.evaluate(net, seeds, res, iters, dev, net_res=net_res, ratio=ratio)
         sur_bs = float(np.mean([r["surrogate"] for r in ev["rows"]]))
         # per raster, single: the method's graph, the surrogate's graph (ungated), the gated call
         plain, sur, gated = [], [], []
@@ -450,8 +453,8 @@ def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: i
             sg = S.SurrogateGraph(net, xy.shape[0], res, net_res, xy=xy)
             sur.append(ev_time(lambda: (xy.copy_(x0), sg())))
             del sg
-            gated.append(ev_time(lambda: (xy.copy_(x0), S.regularize(net, xy, res, iters, min_gain, net_res=net_res)),
-                                 3))
+            gated.append(ev_time(lambda: (xy.copy_(x0), S.regularize(net, xy, res, iters, net_res=net_res,
+                                                                       ratio=ratio)), 3))
         # batched over the held-out sets
         xs = [x.clone() for x in xs0]
 
@@ -468,18 +471,19 @@ def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: i
                                                                     graph=bgraph, check=False)), 3) / len(xs)
         bgraph.close()
         reset()
-        dec = S.regularize_many_gated(net, xs, res, iters, min_gain, net_res=net_res, ws_batch=wsb)
+        dec = S.regularize_many_gated(net, xs, res, iters, net_res=net_res, ws_batch=wsb, ratio=ratio)
         bs_gated = float(np.mean([S.bin_std(x, res) for x in xs]))
-        t_b_gated = ev_time(lambda: (reset(), S.regularize_many_gated(net, xs, res, iters, min_gain, net_res=net_res,
-                                                                      ws_batch=wsb)), 3) / len(xs)
+        t_b_gated = ev_time(lambda: (reset(), S.regularize_many_gated(net, xs, res, iters, net_res=net_res,
+                                                                      ws_batch=wsb, ratio=ratio)), 3) / len(xs)
         k_eq, t_eq = at_equal_uniformity(sur_bs)
         mean = lambda v: float(np.mean(v))
         rec = {"field_res": net_res >> out_level, "train_steps": steps, "batch": batch, "train_s": round(t_train, 1),
                "loss_first10": round(mean(losses[:10]), 4), "loss_last10": round(mean(losses[-10:]), 4),
                "explained_variance": round(ev["explained"], 4),
                "bin_std_gain_plain": round(ev["plain_gain"], 4), "bin_std_gain_surrogate": round(ev["surrogate_gain"], 4),
-               "folded_triangles": ev["folds"], "gate_min_gain": round(min_gain, 4),
+               "folded_triangles": ev["folds"], "gate_ratio_to_first_step": round(ratio, 4),
                "gate_fallbacks": ev["fallbacks"], "gate_fallbacks_batched": dec.count("fallback"),
+               "accepted_short_of_method": ev["accepted_short_of_method"],
                "bin_std_final_gated_batched": round(bs_gated, 3),
                "plain_graph_ms_per_raster": round(mean(plain), 4),
                "surrogate_graph_ms_per_raster": round(mean(sur), 4),
@@ -501,8 +505,68 @@ def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: i
            "method_bin_std_by_iteration": [round(v, 3) for v in bs_k],
            "method_graph_ms_by_iteration": [round(v, 4) for v in t_k]}
     out["field64"] = run_variant(2)
-    out["field256"] = run_variant(0)
+    if full_field:
+        out["field256"] = run_variant(0)
     del sets
+    return out
+
+
+def bench_convs(dev, imgs: int = 16, res: int = 256, reps: int = 10) -> dict:
+    """Every convolution of the surrogate's network (256 x 256 input, decoder
+    to level 2) at the training batch: forward, input gradient and weight
+    gradient timed separately with events (median), in TFLOP/s of their
+    2 P Cin Cout ks^2 multiply-adds and as a fraction of the 2.5 PFLOP/s
+    dense BF16 matrix-core peak."""
+    import numpy as np
+    import torch
+
+    from paper_2408_06513_amd import nn
+    from paper_2408_06513_amd import surrogate as S
+    g = torch.Generator(device="cpu").manual_seed(0)
+    work = torch.empty(256, dtype=torch.uint8, device=dev)
+    rows, tot = {}, {"fwd": [0.0, 0.0], "dgrad": [0.0, 0.0], "wgrad": [0.0, 0.0]}
+    shapes = S.conv_shapes(out_level=2)
+    lvl_of = lambda name: 2 if name == "head" else int(name[1])  # noqa: E731
+    for name, cin, cout, ks in shapes:
+        h = res >> lvl_of(name)
+        x = (torch.rand((imgs, h, h, cin), generator=g) - 0.5).to(torch.bfloat16).to(dev)
+        w = (torch.rand((cout, ks * ks, cin), generator=g) - 0.5).to(torch.bfloat16).to(dev)
+        wT = torch.empty((cin, ks * ks, cout), dtype=torch.bfloat16, device=dev)
+        nn.weight_transpose(w, wT)
+        dy = (torch.rand((imgs, h, h, cout), generator=g) - 0.5).to(torch.bfloat16).to(dev)
+        y16 = torch.empty((imgs, h, h, cout), dtype=torch.bfloat16, device=dev)
+        dx = torch.empty((imgs, h, h, cin), dtype=torch.float32, device=dev)
+        dw = torch.empty((cout, ks * ks, cin), dtype=torch.float32, device=dev)
+        db = torch.empty(cout, dtype=torch.float32, device=dev)
+        need = nn.conv_workspace(imgs, h, h, cin, cout, ks)
+        if work.numel() < need:
+            work = torch.empty(need, dtype=torch.uint8, device=dev)
+        flop = 2.0 * imgs * h * h * cin * cout * ks * ks
+        rec = {"h": h, "cin": cin, "cout": cout, "ks": ks, "gflop": round(flop / 1e9, 3)}
+        for tag, fn in (("fwd", lambda: nn.conv_forward(x, w, None, True, y16=y16, work=work)),
+                        ("dgrad", lambda: nn.conv_backward_data(dy, wT, dx, work=work)),
+                        ("wgrad", lambda: nn.conv_backward_weight(dy, x, ks, dw, db, work=work))):
+            fn()
+            ts = []
+            for _ in range(reps):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                fn()
+                b.record()
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(b) * 1e-3)
+            t = float(np.median(ts))
+            rec[f"{tag}_us"] = round(t * 1e6, 1)
+            rec[f"{tag}_TFLOPs"] = round(flop / t / 1e12, 1)
+            tot[tag][0] += flop
+            tot[tag][1] += t
+        rows[name] = rec
+    out = {"imgs": imgs, "res": res, "layers": rows}
+    for tag, (f, t) in tot.items():
+        out[f"{tag}_total_TFLOPs"] = round(f / t / 1e12, 1)
+        out[f"{tag}_frac_bf16_peak"] = round(f / t / 1e12 / 2500.0, 4)
+        out[f"{tag}_total_ms"] = round(t * 1e3, 3)
     return out
 
 
@@ -656,6 +720,9 @@ def main():
     ap.add_argument("--surrogate-sets", type=int, default=16384, help="training point sets of the surrogate")
     ap.add_argument("--surrogate-save", default=None, help="directory for the trained networks (.npz checkpoints)")
     ap.add_argument("--only-surrogate", action="store_true", help="print only the surrogate measurement")
+    ap.add_argument("--surrogate-full-field", action="store_true",
+                    help="also train and measure the network with the full 256 x 256 output lattice")
+    ap.add_argument("--only-convs", action="store_true", help="print only the per-convolution matrix-core rates")
     ap.add_argument("--surrogate-steps", type=int, default=3000, help="training steps of the surrogate")
     ap.add_argument("--no-sweeps", action="store_true", help="skip the parameter and quality sweeps")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -686,9 +753,13 @@ def main():
     if args.profile_short:
         profile_short(args, dev)
         return
+    if args.only_convs:
+        print(json.dumps({"surrogate_convs": bench_convs(dev)}), flush=True)
+        return
     if args.only_surrogate:
         print(json.dumps({"surrogate_256": bench_surrogate(dev, args.surrogate_sets, args.surrogate_steps,
-                                                           save_dir=args.surrogate_save)}), flush=True)
+                                                           save_dir=args.surrogate_save,
+                                                           full_field=args.surrogate_full_field)}), flush=True)
         return
     if args.only_sweeps:
         print(json.dumps({"sweeps": bench_sweeps(dev)}), flush=True)
@@ -724,7 +795,8 @@ def main():
         rec["splom_45_plots"] = bench_splom(dev)
     if not args.no_surrogate:
         rec["surrogate_256"] = bench_surrogate(dev, args.surrogate_sets, args.surrogate_steps,
-                                               save_dir=args.surrogate_save)
+                                               save_dir=args.surrogate_save, full_field=args.surrogate_full_field)
+        rec["surrogate_convs"] = bench_convs(dev)
     if not args.no_sweeps:
         rec["sweeps"] = bench_sweeps(dev)
     if not args.no_cpu:

@@ -123,6 +123,16 @@ int inim_nn_pack_density(const float* density, int32_t res, float scale, int32_t
 int inim_nn_pack_density_many(const float* density, int32_t count, int32_t res, const float* scale, int32_t c,
                               inim_bf16* x, hipStream_t stream);
 
+/* The network's input with the method's first step: for `count` rasters
+ * (1..64), channel 0 of x [count][res][res][c] (c >= 3) = bfloat16(density *
+ * scale[q]) as in inim_nn_pack_density_many, channels 1 and 2 = bfloat16(64
+ * (field - texel centre)), the displacement of one iteration of the method
+ * (field: float [count][res][res][2], inim_deform of that density), and the
+ * other channels 0.  The integral images behind that field sum the whole
+ * raster, which the convolutions' finite reach cannot. */
+int inim_nn_pack_input_many(const float* density, const float* field, int32_t count, int32_t res, const float* scale,
+                            int32_t c, inim_bf16* x, hipStream_t stream);
+
 /* Training target from probes started at the texel centres and moved by the
  * whole iteration (inim_regularize_probes): out [res][res][2] = (probe -
  * texel centre) * 64, the displacement in units of 1/64 of the unit square

@@ -149,10 +149,12 @@ __device__ __forceinline__ void store_vec(const ChunksT<Tile<BM, BN>::AC, Tile<B
 }
 
 // Weight gradient: dW[co][(t, ci)] = sum_p dy[p][co] x[p + off_t][ci], i.e.
-// A[co][p] = dy[p][co] and B[p][(t, ci)] = x[p + off_t][ci].  Each chunk is
-// 8 channels of one pixel (a 16-byte load, Cout and Cin multiples of 8, so a
-// chunk of (t, ci) stays in one tap), written transposed into the [row][k]
-// LDS layout.
+// A[co][p] = dy[p][co] and B[p][(t, ci)] = x[p + off_t][ci].  Each load is 8
+// channels of one pixel (16 bytes; Cout and Cin multiples of 8, so a chunk of
+// (t, ci) stays in one tap).  Eight consecutive lanes load the same 8
+// channels of 8 consecutive pixels, transpose the 8 x 8 block among
+// themselves (three lane exchanges), and each stores 8 pixels of one channel
+// as one 16-byte row segment of the [row][k] LDS layout.
 // With `ones`, column N of B is 1 at every pixel, so that column of the
 // product is the bias gradient sum_p dy[p][co].
 struct WgradSrc {
@@ -163,11 +165,68 @@ struct WgradSrc {
     ConvGeom g;
 };
 
+// The value of lane (lane ^ J): DPP quad permutes for J = 1, 2, the swizzle
+// xor mode for J = 4.  All 64 lanes take part.
+template <int J>
+__device__ __forceinline__ uint32_t xlane(uint32_t v) {
+    if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+    else if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+    else return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (J << 10));
+}
+
+// 8 x 8 transpose of 16-bit values among the 8 lanes of each aligned group:
+// lane i ends with element i of lanes 0..7 of its group.  Each stage s = 4,
+// 2, 1 swaps the elements whose index bit s differs from the lane's bit s
+// with lane ^ s (which swaps those bits of lane and index).
+__device__ __forceinline__ u16x8 transpose8(u16x8 v, int lane) {
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = (uint32_t)v[2 * k] | ((uint32_t)v[2 * k + 1] << 16);
+    const bool b4 = lane & 4, b2 = lane & 2, b1 = lane & 1;
+    {
+        const uint32_t y0 = xlane<4>(b4 ? w[0] : w[2]), y1 = xlane<4>(b4 ? w[1] : w[3]);
+        if (b4) { w[0] = y0; w[1] = y1; } else { w[2] = y0; w[3] = y1; }
+    }
+    {
+        const uint32_t y0 = xlane<2>(b2 ? w[0] : w[1]), y1 = xlane<2>(b2 ? w[2] : w[3]);
+        if (b2) { w[0] = y0; w[2] = y1; } else { w[1] = y0; w[3] = y1; }
+    }
+    {
+        const uint32_t s0 = b1 ? ((w[0] & 0xFFFFu) | (w[1] << 16)) : ((w[0] >> 16) | (w[1] & 0xFFFF0000u));
+        const uint32_t s1 = b1 ? ((w[2] & 0xFFFFu) | (w[3] << 16)) : ((w[2] >> 16) | (w[3] & 0xFFFF0000u));
+        const uint32_t r0 = xlane<1>(s0), r1 = xlane<1>(s1);
+        if (b1) {
+            w[0] = (w[0] & 0xFFFF0000u) | (r0 & 0xFFFFu);
+            w[1] = (w[1] & 0xFFFF0000u) | (r0 >> 16);
+            w[2] = (w[2] & 0xFFFF0000u) | (r1 & 0xFFFFu);
+            w[3] = (w[3] & 0xFFFF0000u) | (r1 >> 16);
+        } else {
+            w[0] = (w[0] & 0xFFFFu) | (r0 << 16);
+            w[1] = (w[1] & 0xFFFFu) | (r0 & 0xFFFF0000u);
+            w[2] = (w[2] & 0xFFFFu) | (r1 << 16);
+            w[3] = (w[3] & 0xFFFFu) | (r1 & 0xFFFF0000u);
+        }
+    }
+    u16x8 o;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        o[2 * k] = (uint16_t)(w[k] & 0xFFFFu);
+        o[2 * k + 1] = (uint16_t)(w[k] >> 16);
+    }
+    return o;
+}
+
+// Chunk e (0..511) of a K step: pixel kk = e % 8 + 8 ((e / 128) % 4) of the
+// step's 32, rows 8 ((e / 8) % 16) .. + 7 of the tile; lanes 8g .. 8g+7 hold
+// 8 consecutive pixels of the same rows.
+__device__ __forceinline__ int wg_pixel(int e) { return (e & 7) | (((e >> 7) & 3) << 3); }
+__device__ __forceinline__ int wg_rows(int e) { return ((e >> 3) & 15) * 8; }
+
 __device__ __forceinline__ void load_wgrad(Chunks& c, const WgradSrc& w, int bm, int bn, int k0) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int e = threadIdx.x + 256 * h;
-        const int kk = e >> 4, rc = (e & 15) * 8;  // pixel k0 + kk; rows rc .. rc + 7 of the tile
+        const int kk = wg_pixel(e), rc = wg_rows(e);  // pixel k0 + kk; rows rc .. rc + 7 of the tile
         const int p = k0 + kk;
         const int co = bm + rc;
         c.a[h] = (p < w.g.P && co < w.Cout) ? *reinterpret_cast<const u16x8*>(w.dy + (size_t)p * w.Cout + co) : zero8();
@@ -185,15 +244,13 @@ __device__ __forceinline__ void load_wgrad(Chunks& c, const WgradSrc& w, int bm,
 }
 
 __device__ __forceinline__ void store_wgrad(const Chunks& c, GemmLds& s) {
+    const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int e = threadIdx.x + 256 * h;
-        const int kk = e >> 4, rc = (e & 15) * 8;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            s.a[rc + j][kk] = c.a[h][j];
-            s.b[rc + j][kk] = c.b[h][j];
-        }
+        const int k8 = wg_pixel(e) & ~7, row = wg_rows(e) + (lane & 7);
+        *reinterpret_cast<u16x8*>(&s.a[row][k8]) = transpose8(c.a[h], lane);
+        *reinterpret_cast<u16x8*>(&s.b[row][k8]) = transpose8(c.b[h], lane);
     }
 }
 
@@ -580,6 +637,31 @@ constexpr int kMaxScales = 64;
 struct Scales {
     float v[kMaxScales];
 };
+
+// Density in channel 0 and, from a deformation field f (texel positions,
+// [z][res][res][2]), its displacement from the texel centres times 64 in
+// channels 1 and 2; other channels 0.  Raster z = blockIdx.y.
+__global__ __launch_bounds__(256) void k_pack_input_many(const float* __restrict__ d, const float* __restrict__ f,
+                                                         int res, Scales sc, int C, uint16_t* __restrict__ x) {
+    const size_t px = (size_t)res * res, n = px * C, z = blockIdx.y;
+    const float* dz = d + z * px;
+    const float* fz = f + z * px * 2;
+    uint16_t* xz = x + z * n;
+    const float inv = 1.0f / (float)res;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t p = i / C;
+        const int c = (int)(i - p * C);
+        float v = 0.0f;
+        if (c == 0) {
+            v = dz[p] * sc.v[z];
+        } else if (c <= 2) {
+            const int ix = (int)(p % res), iy = (int)(p / res);
+            const float centre = ((c == 1 ? ix : iy) + 0.5f) * inv;
+            v = (fz[2 * p + (c - 1)] - centre) * 64.0f;
+        }
+        xz[i] = c <= 2 ? f2bf(v) : (uint16_t)0;
+    }
+}
 
 __global__ __launch_bounds__(256) void k_pack_density_many(const float* __restrict__ d, size_t pixels, Scales sc,
                                                            int C, uint16_t* __restrict__ x) {
@@ -1005,6 +1087,18 @@ int inim_nn_pack_density_many(const float* density, int32_t count, int32_t res, 
     hipLaunchKernelGGL(k_pack_density_many, dim3(grid_1d((int64_t)(px * c)), count), dim3(256), 0, stream, density, px,
                        sc, c, x);
     return launched("pack density");
+}
+
+int inim_nn_pack_input_many(const float* density, const float* field, int32_t count, int32_t res, const float* scale,
+                            int32_t c, inim_bf16* x, hipStream_t stream) {
+    if (!density || !field || !x || !scale || res < 2 || c < 3 || count < 1 || count > kMaxScales)
+        return nfail(INIM_EINVAL, "bad input-packing arguments");
+    Scales sc{};
+    for (int q = 0; q < count; ++q) sc.v[q] = scale[q];
+    const size_t px = (size_t)res * res;
+    hipLaunchKernelGGL(k_pack_input_many, dim3(grid_1d((int64_t)(px * c)), count), dim3(256), 0, stream, density, field,
+                       res, sc, c, x);
+    return launched("pack input");
 }
 
 int inim_nn_displacement(const float* probe, int32_t res, float* out, hipStream_t stream) {

@@ -18,6 +18,7 @@ NN_EXPORTS = (
     "inim_upsample2_into", "inim_copy_channels_into", "inim_upsample2_backward", "inim_take_channels",
     "inim_relu_backward", "inim_mse", "inim_adam", "inim_nn_pack_density", "inim_nn_displacement", "inim_nn_field",
     "inim_nn_count_folds", "inim_nn_bin_moments", "inim_nn_pack_density_many", "inim_nn_field_many",
+    "inim_nn_pack_input_many",
     "inim_concat_up2",
 )
 
@@ -51,6 +52,7 @@ def lib() -> ctypes.CDLL:
         "inim_adam": [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp, vp],
         "inim_nn_pack_density": [vp, i32, f32, i32, vp, vp],
         "inim_nn_pack_density_many": [vp, i32, i32, vp, i32, vp, vp],
+        "inim_nn_pack_input_many": [vp, vp, i32, i32, vp, i32, vp, vp],
         "inim_nn_field_many": [vp, i32, i32, i32, i32, vp, vp, vp],
         "inim_nn_displacement": [vp, i32, vp, vp],
         "inim_nn_field": [vp, i32, i32, i32, vp, vp, vp],
@@ -220,6 +222,16 @@ def pack_density_many(density, scales, x):
     k = density.shape[0]
     sc = (ctypes.c_float * k)(*[float(v) for v in scales])
     _check(lib().inim_nn_pack_density_many(_p(density), k, density.shape[1], sc, x.shape[-1], _p(x), _s(x)))
+    return x
+
+
+def pack_input_many(density, field, scales, x):
+    """density [k, res, res] f32 and the method's one-step field [k, res, res, 2]
+    -> x [k, res, res, c] bf16: channel 0 density[q] * scales[q], channels 1-2
+    the field's displacement from the texel centres times 64."""
+    k = density.shape[0]
+    sc = (ctypes.c_float * k)(*[float(v) for v in scales])
+    _check(lib().inim_nn_pack_input_many(_p(density), _p(field), k, density.shape[1], sc, x.shape[-1], _p(x), _s(x)))
     return x
 
 

@@ -144,3 +144,47 @@ def test_surrogate_batched_graph_replays_equal_eager(dev):
             assert torch.equal(xs[q], eager[q]), (rep, q)
         capi.regularize(other.clone(), 256, 2)
         torch.cuda.synchronize()
+
+
+def test_pack_input_many_channels(dev):
+    """The first-step input: channel 0 the scaled density (bit for bit),
+    channels 1-2 the field's displacement from the texel centres times 64
+    (within one bfloat16 unit: the device may fuse the centre's product into
+    the difference), the other channels exactly 0."""
+    from paper_2408_06513_amd import nn
+    g = torch.Generator(device="cpu").manual_seed(9)
+    k, res, c = 3, 32, 8
+    dens = torch.rand((k, res, res), generator=g)
+    centre = (torch.arange(res, dtype=torch.float32) + 0.5) * np.float32(1.0 / res)
+    field = torch.stack(torch.broadcast_tensors(centre[None, None, :], centre[None, :, None]), dim=-1).expand(k, res, res, 2)
+    field = (field + (torch.rand((k, res, res, 2), generator=g) - 0.5) * 0.05).contiguous()
+    scales = [1.5, 2.0, 0.25]
+    x = torch.empty((k, res, res, c), dtype=torch.bfloat16, device=dev)
+    nn.pack_input_many(dens.to(dev), field.to(dev), scales, x)
+    got = x.float().cpu()
+    for q in range(k):
+        assert torch.equal(got[q, ..., 0], (dens[q] * np.float32(scales[q])).to(torch.bfloat16).float())
+    disp = (field - torch.stack(torch.broadcast_tensors(centre[None, None, :], centre[None, :, None]), dim=-1)) * 64
+    ref = disp.to(torch.bfloat16).float()
+    ulp = ref.abs().clamp(min=1e-30) * 2.0 ** -7
+    assert ((got[..., 1:3] - ref).abs() <= ulp).all()
+    assert torch.equal(got[..., 3:], torch.zeros_like(got[..., 3:]))
+
+
+def test_first_step_batched_move_equals_single_steps(dev):
+    """A network that also reads the method's first step: its batched move
+    (regularize_many) gives every set exactly the single-set result."""
+    from paper_2408_06513_amd import capi
+    from paper_2408_06513_amd import surrogate as S
+    net = S.UNet(dev, seed=11, chans=(8, 16, 16), out_level=1, first_step=True)
+    xs0 = [torch.from_numpy(dg.surrogate_mixture(s, n_hi=30_000)).to(dev) for s in range(5)]
+    ref = []
+    for x0 in xs0:
+        x = x0.clone()
+        capi.advect(S.predict_field(net, x, 128, net_res=64), x)
+        ref.append(x)
+    xs = [x.clone() for x in xs0]
+    S.regularize_many(net, xs, 128, net_res=64)
+    for q in range(len(xs)):
+        assert torch.equal(xs[q], ref[q]), q
+

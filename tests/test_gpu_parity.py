@@ -428,8 +428,11 @@ def test_advect_domain_error_leaves_xy(capi, dev):
     xy = np.array([[0.5, 0.5], [np.nan, 0.2]], np.float32)
     g = to_dev(xy, dev)
     ws = capi.workspace(256, dev)
-    capi.advect(to_dev(T, dev), g, ws=ws)
+    capi.advect(to_dev(T, dev), g, ws=ws, check=False)
     assert capi.sync_status(ws) == capi.EDOMAIN
+    assert np.array_equal(g.cpu().numpy(), xy, equal_nan=True)
+    with pytest.raises(capi.DomainError):  # the default: synchronise and raise
+        capi.advect(to_dev(T, dev), g, ws=ws)
     assert np.array_equal(g.cpu().numpy(), xy, equal_nan=True)
 
 

@@ -111,3 +111,43 @@ def test_checkpoint_round_trip_and_resume(tmp_path):
         assert torch.equal(net.convs[k].vw, back.convs[k].vw), k
     with np.load(path, allow_pickle=False) as z:  # nothing pickled in the file
         assert all(z[k].dtype != object for k in z.files)
+
+
+WEIGHTS = __import__("os").path.join(__import__("os").path.dirname(__import__("os").path.dirname(
+    __import__("os").path.abspath(__file__))), "paper_2408_06513_amd", "weights", "surrogate_256_field64.npz")
+
+
+def test_c5_trained_network_passes_the_gate():
+    """The surrogate of the 256 x 256, 8-iteration configuration as the
+    benchmark trains it (5 levels, 32-256 channels; in: the 256 x 256 density
+    and the displacement of the method's first iteration; out: the
+    displacement of all eight on the 64 x 64 lattice; 16,384 training sets,
+    3000 steps of 16; stored as bfloat16 weights).  On 16 held-out point sets
+    (seeds the training never drew) it explains at least 98% of the method's
+    displacement and reaches 95% of the method's bin-std gain.  The gate (no
+    folded triangle; at most the calibrated ratio times the bin std after the
+    method's own first step on the set) accepts at least 10 of the 16; every
+    accepted prediction is fold-free, meets the gate and ends within 10% of
+    the method's own uniformity; an untrained network of the same shape is
+    rejected on every set."""
+    from paper_2408_06513_amd import surrogate as S
+    dev = torch.device("cuda:0")
+    net = S.UNet.load(WEIGHTS, dev)
+    assert net.first_step and net.out_level == 2 and net.chans == (32, 64, 128, 256, 256)
+    res, iters = 256, 8
+    ratio = S.calibrate_gate(res, iters, dev)
+    note(f"C5 network: gate ratio {ratio:.3f}; 16 held-out sets")
+    ev = S.evaluate(net, range(100_000, 100_016), res, iters, dev, net_res=res, ratio=ratio)
+    acc = [r for r in ev["rows"] if r["gate"] == "surrogate"]
+    note(f"explained {ev['explained']:.4f} gain {ev['surrogate_gain']:.3f} (plain {ev['plain_gain']:.3f}) "
+         f"folds {ev['folds']} accepted {len(acc)}/16")
+    assert 0.3 < ratio < 1.0
+    assert ev["explained"] >= 0.98
+    assert ev["surrogate_gain"] >= 0.95 * ev["plain_gain"]
+    assert len(acc) >= 10
+    for r in acc:
+        assert r["folds"] == 0
+        assert r["surrogate"] <= 1.1 * r["plain"]
+    raw = S.UNet(dev, seed=7, out_level=2, first_step=True)
+    ev0 = S.evaluate(raw, range(100_000, 100_004), res, iters, dev, net_res=res, ratio=ratio)
+    assert ev0["fallbacks"] == 4
