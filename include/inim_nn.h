@@ -40,7 +40,10 @@ const char* inim_nn_last_error(void);
 /* Device work buffer for the three calls below on a layer of this shape:
  * FP32 partial sums of the K range split into slices when the output alone
  * has too few 128 x 128 tiles to fill the GPU.  The slices are added in a
- * fixed order, so results do not depend on timing. */
+ * fixed order, so results do not depend on timing.  When h and w are powers
+ * of two and w is a multiple of 8, it also holds channel-major copies of the
+ * weight gradient's operands x and dy (2 (cin + cout) bytes per pixel).  The
+ * buffer must be 256-byte aligned (as hipMalloc returns it). */
 int inim_conv_workspace(int32_t imgs, int32_t h, int32_t w, int32_t cin, int32_t cout, int32_t ks, size_t* bytes);
 
 /* y[p][co] = act(bias[co] + sum over taps t and cin of x[p + off_t][ci] w[co][t][ci]);

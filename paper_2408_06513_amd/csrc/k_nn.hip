@@ -425,14 +425,233 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvArgs a, int kslice, floa
     });
 }
 
-// Sum of `parts` partial arrays of length len (fixed order), optional bias
-// gradient rows: out[i] = sum_s part[s][i].
-__global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int parts, size_t len,
-                                                   float* __restrict__ out) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (size_t)gridDim.x * blockDim.x) {
-        float s = 0.0f;
-        for (int q = 0; q < parts; ++q) s += part[(size_t)q * len + i];
-        out[i] = s;
+// Channel-major copies for the weight gradient: out[c][p] = in[p][c] for two
+// tensors of the same pixels in one launch (blockIdx.y below the first
+// tensor's channel blocks: the first), one block per 64 pixels x 64 channels
+// through LDS (C and P multiples of 8).  Loads: 8 lanes read 64 channels (128
+// contiguous bytes) of one pixel; stores: 8 lanes write 64 pixels of one
+// channel.
+struct CmajorSeg {
+    const uint16_t* in;  // [P][C]
+    int C;
+    uint16_t* out;       // [C][P]
+};
+
+__global__ __launch_bounds__(256) void k_cmajor(CmajorSeg s0, CmajorSeg s1, int64_t P) {
+    __shared__ uint16_t t[64][64 + kPad];
+    const int cb0 = (s0.C + 63) / 64;
+    const bool first = (int)blockIdx.y < cb0;
+    const uint16_t* __restrict__ in = first ? s0.in : s1.in;
+    uint16_t* __restrict__ out = first ? s0.out : s1.out;
+    const int C = first ? s0.C : s1.C;
+    const int64_t p0 = (int64_t)blockIdx.x * 64;
+    const int c0 = (first ? (int)blockIdx.y : (int)blockIdx.y - cb0) * 64;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int e = threadIdx.x + 256 * h;
+        const int cc = (e & 7) * 8, px = e >> 3;
+        if (p0 + px < P && c0 + cc < C) {
+            const u16x8 v = *reinterpret_cast<const u16x8*>(in + (size_t)(p0 + px) * C + c0 + cc);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) t[cc + j][px] = v[j];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int e = threadIdx.x + 256 * h;
+        const int pp = (e & 7) * 8, c = e >> 3;
+        if (c0 + c < C && p0 + pp < P)
+            *reinterpret_cast<u16x8*>(out + (size_t)(c0 + c) * P + p0 + pp) = *reinterpret_cast<const u16x8*>(&t[c][pp]);
+    }
+}
+
+// Weight gradient from channel-major operands dyT [Cout][P] and xT [Cin][P]
+// (images with power-of-two sides, W a multiple of 8): every 8-element chunk
+// of a K step is 8 consecutive pixels of one image row, so A and B chunks are
+// plain 16-byte loads stored to LDS as they are, with no lane transposes.
+// A tap's column shift kx = +-1 moves the chunk by one element: the
+// neighbouring chunk of the same row supplies the element that enters (zero
+// past the row's end).  The K order (pixel k0 + k at LDS column k) is that of
+// k_conv_wgrad, so both give the same sums.
+// Without SWAP the block tile is Cout rows (A = dyT) by (tap, ci) columns
+// (B = xT); with SWAP (narrow Cout) it is (tap, ci) rows (A = xT) by Cout
+// columns (B = dyT) on a 256 x BN tile, so that a 32- or 64-channel layer
+// does not leave three quarters of a 128-row tile empty.
+struct WgradRow {
+    const uint16_t* src;  // dyT or xT row
+    int ky, kx;
+    int kind;             // 0 zero, 1 plain, 2 tap-shifted, 3 the column of ones
+};
+
+__device__ __forceinline__ u16x8 ones8() {
+    const uint16_t o = 0x3F80u;  // 1.0 in bfloat16
+    return u16x8{o, o, o, o, o, o, o, o};
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ u16x8 shifted8(const uint16_t* row, int p, int ky, int kx, int wlog, int wmask,
+                                          int hmask) {
+    const int x = p & wmask, y = (p >> wlog) & hmask;
+    const int ny = y + ky;
+    if (ny < 0 || ny > hmask) return zero8();
+    const uint16_t* src = row + p + ky * (wmask + 1);
+    const u32x4 v = __builtin_bit_cast(u32x4, *reinterpret_cast<const u16x8*>(src));
+    if (kx == 0) return __builtin_bit_cast(u16x8, v);
+    u32x4 o;
+    if (kx > 0) {  // element j is pixel j + 1; the last enters from the next chunk
+        const uint32_t nb = x + 8 <= wmask ? *reinterpret_cast<const uint32_t*>(src + 8) : 0u;
+        o[0] = (v[0] >> 16) | (v[1] << 16);
+        o[1] = (v[1] >> 16) | (v[2] << 16);
+        o[2] = (v[2] >> 16) | (v[3] << 16);
+        o[3] = (v[3] >> 16) | (nb << 16);
+    } else {  // element j is pixel j - 1; the first enters from the previous chunk
+        const uint32_t pb = x > 0 ? *reinterpret_cast<const uint32_t*>(src - 2) : 0u;
+        o[0] = (pb >> 16) | (v[0] << 16);
+        o[1] = (v[0] >> 16) | (v[1] << 16);
+        o[2] = (v[1] >> 16) | (v[2] << 16);
+        o[3] = (v[2] >> 16) | (v[3] << 16);
+    }
+    return __builtin_bit_cast(u16x8, o);
+}
+
+struct WgradGeo {
+    int wlog, wmask, hmask;
+};
+
+__device__ __forceinline__ u16x8 wgrad_chunk(const WgradRow& r, int p, bool in, const WgradGeo& g) {
+    if (!in || r.kind == 0) return zero8();
+    if (r.kind == 1) return *reinterpret_cast<const u16x8*>(r.src + p);
+    if (r.kind == 2) return shifted8(r.src, p, r.ky, r.kx, g.wlog, g.wmask, g.hmask);
+    return ones8();
+}
+
+// Row n of the (tap, ci) side: a tap-shifted xT row, the column of ones, or zero.
+__device__ __forceinline__ WgradRow xrow(const ConvArgs& a, const uint16_t* xT, int n, int N, bool ones) {
+    WgradRow r{xT, 0, 0, 0};
+    if (n < N) {
+        const int t = n / a.Cin, ci = n - t * a.Cin, half = a.ks / 2;
+        r.src = xT + (size_t)ci * a.P;
+        r.ky = t / a.ks - half;
+        r.kx = t % a.ks - half;
+        r.kind = a.ks == 1 ? 1 : 2;
+    } else if (ones && n == N) {
+        r.kind = 3;
+    }
+    return r;
+}
+
+__device__ __forceinline__ WgradRow dyrow(const ConvArgs& a, const uint16_t* dyT, int co) {
+    return WgradRow{co < a.Cout ? dyT + (size_t)co * a.P : dyT, 0, 0, co < a.Cout ? 1 : 0};
+}
+
+template <int BM, int BN, bool SWAP>
+__global__ __launch_bounds__(256) void k_conv_wgrad_t(ConvArgs a, const uint16_t* __restrict__ dyT,
+                                                      const uint16_t* __restrict__ xT, int wlog, int kslice,
+                                                      float* bias_part) {
+    using T = Tile<BM, BN>;
+    using C = ChunksT<T::AC, T::BC>;
+    __shared__ GemmLdsT<BM, BN> s[2];
+    const int bm = blockIdx.x * BM, bn = blockIdx.y * BN;
+    const int N = a.ks * a.ks * a.Cin;
+    const bool ones = bias_part != nullptr;
+    const WgradGeo geo{wlog, a.W - 1, a.H - 1};
+    WgradRow ra[T::AC], rb[T::BC];
+#pragma unroll
+    for (int h = 0; h < T::AC; ++h) {
+        const int row = bm + (int)(threadIdx.x >> 2) + 64 * h;
+        ra[h] = SWAP ? xrow(a, xT, row, N, ones) : dyrow(a, dyT, row);
+    }
+#pragma unroll
+    for (int h = 0; h < T::BC; ++h) {
+        const int e = threadIdx.x + 256 * h;
+        const int row = bn + (e >> 2);
+        rb[h] = e < BN * 4 ? (SWAP ? dyrow(a, dyT, row) : xrow(a, xT, row, N, ones)) : WgradRow{xT, 0, 0, 0};
+    }
+    int kbeg, kend;
+    k_range(a.P, kslice, kbeg, kend);
+    f32x16 acc[T::TI][T::TJ] = {};
+    gemm_loop<BM, BN, C>(
+        s, acc, kbeg, kend,
+        [&](C& c, int k0) {
+            const int p = k0 + (int)(threadIdx.x & 3) * 8;
+            const bool in = p < kend;
+#pragma unroll
+            for (int h = 0; h < T::AC; ++h) c.a[h] = wgrad_chunk(ra[h], p, in, geo);
+#pragma unroll
+            for (int h = 0; h < T::BC; ++h) c.b[h] = wgrad_chunk(rb[h], p, in, geo);
+        },
+        [&](const C& c, GemmLdsT<BM, BN>& l) { store_vec<BM, BN>(c, l); });
+    float* out = a.dw + (size_t)blockIdx.z * a.Cout * N;
+    for_each_result<BM, BN>(acc, bm, bn, [&](int m, int n, float v) {
+        const int co = SWAP ? n : m, k = SWAP ? m : n;
+        if (co >= a.Cout) return;
+        if (k < N) out[(size_t)co * N + k] = v;
+        else if (k == N && bias_part) bias_part[(size_t)blockIdx.z * a.Cout + co] = v;
+    });
+}
+
+// Sums of split partials, out[i] = sum over q of part[q][i], for one or two
+// arrays (the weight and bias gradients) in one launch.  A block takes 64
+// consecutive elements, one per lane; its four waves sum consecutive quarters
+// of the parts in order (eight loads in flight), and the quarters are added
+// in order through LDS, so the result does not depend on timing.
+struct SumSeg {
+    const float* part;  // [parts][len]
+    size_t len;
+    float* out;
+};
+
+__global__ __launch_bounds__(256) void k_sum_parts(SumSeg s0, SumSeg s1, int parts) {
+    __shared__ float qs[4][64];
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    const size_t blocks0 = (s0.len + 63) / 64, blocks = blocks0 + (s1.len + 63) / 64;
+    const int per = (parts + 3) / 4;
+    const int q0 = min(parts, wave * per), q1 = min(parts, q0 + per);
+    for (size_t blk = blockIdx.x; blk < blocks; blk += gridDim.x) {
+        const bool first = blk < blocks0;
+        const float* __restrict__ part = first ? s0.part : s1.part;
+        const size_t len = first ? s0.len : s1.len;
+        const size_t i = (first ? blk : blk - blocks0) * 64 + lane;
+        float acc = 0.0f;
+        if (i < len) {
+            int q = q0;
+            for (; q + 8 <= q1; q += 8) {
+                float v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(q + u) * len + i];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc += v[u];
+            }
+            for (; q < q1; ++q) acc += part[(size_t)q * len + i];
+        }
+        qs[wave][lane] = acc;
+        __syncthreads();
+        if (wave == 0 && i < len) (first ? s0.out : s1.out)[i] = ((qs[0][lane] + qs[1][lane]) + qs[2][lane]) + qs[3][lane];
+        __syncthreads();
+    }
+}
+
+// The same sums one element per thread, the parts in order (for few parts or
+// long arrays).
+__global__ __launch_bounds__(256) void k_sum_parts_flat(SumSeg s0, SumSeg s1, int parts) {
+    const size_t len = s0.len + s1.len;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < len; t += (size_t)gridDim.x * blockDim.x) {
+        const bool first = t < s0.len;
+        const float* __restrict__ part = first ? s0.part : s1.part;
+        const size_t n = first ? s0.len : s1.len, i = first ? t : t - s0.len;
+        float acc = 0.0f;
+        int q = 0;
+        for (; q + 8 <= parts; q += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(q + u) * n + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u];
+        }
+        for (; q < parts; ++q) acc += part[(size_t)q * n + i];
+        (first ? s0.out : s1.out)[i] = acc;
     }
 }
 
@@ -848,11 +1067,12 @@ TileShape conv_tile(int64_t n) {
     return {kTile, kTile};
 }
 
-int split_slices(int64_t rows, int64_t cols, int64_t klen, TileShape t = {kTile, kTile}) {
+int split_slices(int64_t rows, int64_t cols, int64_t klen, TileShape t = {kTile, kTile}, int blocks = 512,
+                 int min_steps = 4) {
     const int64_t tiles = ((rows + t.bm - 1) / t.bm) * ((cols + t.bn - 1) / t.bn);
-    int64_t s = (512 + tiles - 1) / tiles;
+    int64_t s = (blocks + tiles - 1) / tiles;
     const int64_t steps = (klen + kStepK - 1) / kStepK;
-    if (s > steps / 4) s = steps / 4;
+    if (s > steps / min_steps) s = steps / min_steps;
     return (int)(s < 1 ? 1 : s);
 }
 
@@ -861,7 +1081,38 @@ int slice_len(int64_t klen, int slices) {
     return (int)((steps + slices - 1) / slices) * kStepK;
 }
 
-int wgrad_slices(int64_t P, int cout, int cin, int ks) { return split_slices(cout, (int64_t)ks * ks * cin + 1, P); }
+// The weight gradient reads channel-major copies of its operands when the
+// images have power-of-two sides and rows of whole 8-pixel chunks; then
+// layers of at most 64 output channels take the swapped 256 x BN tile.
+struct WgradPlan {
+    bool cmajor, swap;
+    int bn, slices;
+};
+WgradPlan wgrad_plan(int h, int w, int64_t P, int cout, int cin, int ks) {
+    WgradPlan p;
+    p.cmajor = (h & (h - 1)) == 0 && (w & (w - 1)) == 0 && w % 8 == 0;
+    p.swap = p.cmajor && cout <= 64;
+    p.bn = cout <= 32 ? 32 : 64;
+    const int64_t ncols = (int64_t)ks * ks * cin + 1;
+    // 512 blocks, at least 4 K steps each (a sweep of 256 to 1536 blocks on
+    // the surrogate's layers found no better count overall)
+    p.slices = p.swap ? split_slices(ncols, cout, P, TileShape{256, p.bn}) : split_slices(cout, ncols, P);
+    return p;
+}
+size_t align_up256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// The completion of split sums: few long partials (one thread per element)
+// or many short ones (four waves per 64 elements).
+void launch_sum_parts(const SumSeg& s0, const SumSeg& s1, int parts, hipStream_t stream) {
+    const size_t len = s0.len + s1.len;
+    if (parts <= 16 || len >= ((size_t)1 << 18)) {
+        hipLaunchKernelGGL(k_sum_parts_flat, dim3(grid_1d((int64_t)len)), dim3(256), 0, stream, s0, s1, parts);
+    } else {
+        size_t b = (s0.len + 63) / 64 + (s1.len + 63) / 64;
+        b = b < 1 ? 1 : (b > 8192 ? 8192 : b);
+        hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)b), dim3(256), 0, stream, s0, s1, parts);
+    }
+}
 int fwd_slices(int64_t P, int cin, int cout, int ks) {
     return split_slices(P, cout, (int64_t)ks * ks * cin, conv_tile(cout));
 }
@@ -907,11 +1158,13 @@ int inim_conv_workspace(int32_t imgs, int32_t h, int32_t w, int32_t cin, int32_t
     if (!bytes) return nfail(INIM_EINVAL, "bytes NULL");
     const int64_t P = (int64_t)imgs * h * w;
     const size_t wlen = (size_t)cout * ks * ks * cin;
-    size_t need = (size_t)wgrad_slices(P, cout, cin, ks) * (wlen + cout);
+    const WgradPlan wp = wgrad_plan(h, w, P, cout, cin, ks);
+    size_t need = (size_t)wp.slices * (wlen + cout);
     const int fs = fwd_slices(P, cin, cout, ks), ds = dgrad_slices(P, cin, cout, ks);
     if (fs > 1 && (size_t)fs * P * cout > need) need = (size_t)fs * P * cout;
     if (ds > 1 && (size_t)ds * P * cin > need) need = (size_t)ds * P * cin;
-    *bytes = need * sizeof(float);
+    *bytes = align_up256(need * sizeof(float));
+    if (wp.cmajor) *bytes += align_up256((size_t)P * cin * 2) + align_up256((size_t)P * cout * 2);
     return INIM_OK;
 }
 
@@ -950,8 +1203,8 @@ int inim_conv_backward_data(const inim_bf16* dy, int32_t imgs, int32_t h, int32_
     launch_conv_gemm<DgradKernel>(a.P, cin, slices, stream, a, slices > 1 ? slice_len(K, slices) : K,
                                   static_cast<float*>(work));
     if (slices > 1)
-        hipLaunchKernelGGL(k_sum_parts, dim3(grid_1d((int64_t)a.P * cin)), dim3(256), 0, stream,
-                           static_cast<const float*>(work), slices, (size_t)a.P * cin, dx);
+        launch_sum_parts(SumSeg{static_cast<const float*>(work), (size_t)a.P * cin, dx}, SumSeg{nullptr, 0, nullptr},
+                         slices, stream);
     return launched("conv input gradient");
 }
 
@@ -966,17 +1219,42 @@ int inim_conv_backward_weight(const inim_bf16* dy, const inim_bf16* x, int32_t i
     ConvArgs a{};
     a.dy = dy; a.x = x;
     a.H = h; a.W = w; a.P = imgs * h * w; a.Cin = cin; a.Cout = cout; a.ks = ks;
-    const int slices = wgrad_slices(a.P, cout, cin, ks);
+    const WgradPlan wp = wgrad_plan(h, w, a.P, cout, cin, ks);
+    const int slices = wp.slices;
     const int kslice = slice_len(a.P, slices);
     const size_t wlen = (size_t)cout * ks * ks * cin;
     a.dw = static_cast<float*>(work);
     float* bp = dbias ? a.dw + (size_t)slices * wlen : nullptr;  // [slices][cout]
     const int ncols = ks * ks * cin + (dbias ? 1 : 0);               // the bias gradient is the column of ones
-    hipLaunchKernelGGL(k_conv_wgrad, dim3((cout + kTile - 1) / kTile, (unsigned)((ncols + kTile - 1) / kTile), slices),
-                       dim3(256), 0, stream, a, kslice, bp);
-    hipLaunchKernelGGL(k_sum_parts, dim3(grid_1d((int64_t)wlen)), dim3(256), 0, stream, a.dw, slices, wlen, dweight);
-    if (dbias)
-        hipLaunchKernelGGL(k_sum_parts, dim3(grid_1d(cout)), dim3(256), 0, stream, bp, slices, (size_t)cout, dbias);
+    const dim3 grd((cout + kTile - 1) / kTile, (unsigned)((ncols + kTile - 1) / kTile), slices);
+    if (wp.cmajor) {
+        // partials, then the channel-major copies of x and dy (sizes as in inim_conv_workspace)
+        size_t parts = (size_t)slices * (wlen + cout);
+        const int fs = fwd_slices(a.P, cin, cout, ks), ds = dgrad_slices(a.P, cin, cout, ks);
+        if (fs > 1 && (size_t)fs * a.P * cout > parts) parts = (size_t)fs * a.P * cout;
+        if (ds > 1 && (size_t)ds * a.P * cin > parts) parts = (size_t)ds * a.P * cin;
+        uint16_t* xT = reinterpret_cast<uint16_t*>(static_cast<char*>(work) + align_up256(parts * sizeof(float)));
+        uint16_t* dyT = xT + align_up256((size_t)a.P * cin * 2) / 2;
+        int wlog = 0;
+        while ((1 << wlog) < w) ++wlog;
+        hipLaunchKernelGGL(k_cmajor, dim3((unsigned)((a.P + 63) / 64), (unsigned)((cin + 63) / 64 + (cout + 63) / 64)),
+                           dim3(256), 0, stream, CmajorSeg{x, cin, xT}, CmajorSeg{dy, cout, dyT}, (int64_t)a.P);
+        if (wp.swap) {
+            const dim3 gs((unsigned)((ncols + 255) / 256), (unsigned)((cout + wp.bn - 1) / wp.bn), slices);
+            if (wp.bn == 32)
+                hipLaunchKernelGGL((k_conv_wgrad_t<256, 32, true>), gs, dim3(256), 0, stream, a, dyT, xT, wlog, kslice,
+                                   bp);
+            else
+                hipLaunchKernelGGL((k_conv_wgrad_t<256, 64, true>), gs, dim3(256), 0, stream, a, dyT, xT, wlog, kslice,
+                                   bp);
+        } else {
+            hipLaunchKernelGGL((k_conv_wgrad_t<128, 128, false>), grd, dim3(256), 0, stream, a, dyT, xT, wlog, kslice,
+                               bp);
+        }
+    } else {
+        hipLaunchKernelGGL(k_conv_wgrad, grd, dim3(256), 0, stream, a, kslice, bp);
+    }
+    launch_sum_parts(SumSeg{a.dw, wlen, dweight}, SumSeg{bp, dbias ? (size_t)cout : 0, dbias}, slices, stream);
     return launched("conv weight gradient");
 }
 
@@ -1066,7 +1344,7 @@ int inim_mse(const float* pred, int32_t cp, const float* target, int32_t ct, int
     if (!work || work_bytes < kMsePartials * sizeof(float)) return nfail(INIM_EWORKSPACE, "loss work too small");
     float* parts = static_cast<float*>(work);
     hipLaunchKernelGGL(k_mse, dim3(kMsePartials), dim3(256), 0, stream, pred, cp, target, ct, (size_t)pixels, parts, grad);
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, stream, parts, kMsePartials, (size_t)1, loss);
+    launch_sum_parts(SumSeg{parts, 1, loss}, SumSeg{nullptr, 0, nullptr}, kMsePartials, stream);
     return launched("loss");
 }
 
