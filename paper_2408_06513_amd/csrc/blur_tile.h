@@ -34,8 +34,12 @@ __host__ __device__ inline size_t blur_smem_floats(int r) {
 // (16+2r) x (64+2r) window of counts is staged in `lds` as float, filtered
 // along x into a second LDS buffer, then along y; emit(row, col, value) is
 // called once for every output texel of the tile inside the raster.
-// R > 0 fixes the radius at compile time (window sizes are constants, the
-// taps sit in registers and the tap loops unroll); R == 0 takes taps.r.
+// R > 0 fixes the radius at compile time: the window sizes are constants, the
+// taps sit in registers, and each thread computes four neighbouring outputs
+// from one register window (4 + 2R values read once: as float4 along x,
+// column-wise along y) instead of reading 2R + 1 values per output.  Every
+// output is the same fmaf chain over the taps in the same order as with
+// R == 0, which takes taps.r and one output per thread.
 template <int R, typename Emit>
 __device__ __forceinline__ void blur_tile_r(const uint32_t* __restrict__ counts, int N, const BlurTaps& taps, int ox,
                                             int oy, float* lds, Emit emit) {
@@ -43,43 +47,68 @@ __device__ __forceinline__ void blur_tile_r(const uint32_t* __restrict__ counts,
     const int IW = kBX + 2 * r, IH = kBY + 2 * r;
     float* in = lds;             // IH x IW
     float* mid = lds + IH * IW;  // IH x kBX
-    constexpr int NW = R > 0 ? 2 * R + 1 : 1;
-    float w[NW];
-    if constexpr (R > 0) {
-#pragma unroll
-        for (int m = 0; m < NW; ++m) w[m] = taps.w[m];
-    }
     for (int k = threadIdx.x; k < IH * IW; k += blockDim.x) {
         const int row = k / IW, cc = k - row * IW;
         const int gj = mirror(oy + row - r, N), gi = mirror(ox + cc - r, N);
         in[k] = (float)counts[(size_t)gj * N + gi];
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < IH * kBX; k += blockDim.x) {
-        const int row = k / kBX, cc = k - row * kBX;
-        const float* s = in + row * IW + cc;
-        float a = 0.0f;
-        if constexpr (R > 0) {
+    if constexpr (R > 0) {
+        static_assert(R % 2 == 0, "window rows of whole float4s");
+        constexpr int NW = 2 * R + 1, WIN = 4 + 2 * R;
+        float w[NW];
 #pragma unroll
-            for (int m = 0; m < NW; ++m) a = fmaf(w[m], s[m], a);
-        } else {
+        for (int m = 0; m < NW; ++m) w[m] = taps.w[m];
+        constexpr int IWc = kBX + 2 * R, IHc = kBY + 2 * R;
+        for (int k = threadIdx.x; k < IHc * (kBX / 4); k += blockDim.x) {
+            const int row = k / (kBX / 4), c4 = (k - row * (kBX / 4)) * 4;
+            const float* s = in + row * IWc + c4;
+            float x[WIN];
+#pragma unroll
+            for (int q = 0; q < WIN / 4; ++q) {
+                const float4 t = *reinterpret_cast<const float4*>(s + 4 * q);
+                x[4 * q] = t.x; x[4 * q + 1] = t.y; x[4 * q + 2] = t.z; x[4 * q + 3] = t.w;
+            }
+            float a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int m = 0; m < NW; ++m)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) a[e] = fmaf(w[m], x[m + e], a[e]);
+            *reinterpret_cast<float4*>(mid + row * kBX + c4) = make_float4(a[0], a[1], a[2], a[3]);
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < (kBY / 4) * kBX; k += blockDim.x) {
+            const int r4 = (k / kBX) * 4, cc = k - (k / kBX) * kBX;
+            const float* s = mid + r4 * kBX + cc;
+            float y[WIN];
+#pragma unroll
+            for (int q = 0; q < WIN; ++q) y[q] = s[q * kBX];
+            float a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int m = 0; m < NW; ++m)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) a[e] = fmaf(w[m], y[m + e], a[e]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (ox + cc < N && oy + r4 + e < N) emit(r4 + e, cc, a[e]);
+        }
+    } else {
+        for (int k = threadIdx.x; k < IH * kBX; k += blockDim.x) {
+            const int row = k / kBX, cc = k - row * kBX;
+            const float* s = in + row * IW + cc;
+            float a = 0.0f;
             for (int m = 0; m <= 2 * r; ++m) a = fmaf(taps.w[m], s[m], a);
+            mid[k] = a;
         }
-        mid[k] = a;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < kBY * kBX; k += blockDim.x) {
-        const int row = k / kBX, cc = k - row * kBX;
-        if (ox + cc >= N || oy + row >= N) continue;
-        const float* s = mid + row * kBX + cc;
-        float a = 0.0f;
-        if constexpr (R > 0) {
-#pragma unroll
-            for (int m = 0; m < NW; ++m) a = fmaf(w[m], s[m * kBX], a);
-        } else {
+        __syncthreads();
+        for (int k = threadIdx.x; k < kBY * kBX; k += blockDim.x) {
+            const int row = k / kBX, cc = k - row * kBX;
+            if (ox + cc >= N || oy + row >= N) continue;
+            const float* s = mid + row * kBX + cc;
+            float a = 0.0f;
             for (int m = 0; m <= 2 * r; ++m) a = fmaf(taps.w[m], s[m * kBX], a);
+            emit(row, cc, a);
         }
-        emit(row, cc, a);
     }
 }
 

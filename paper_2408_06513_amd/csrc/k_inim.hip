@@ -158,7 +158,7 @@ template <typename Acc>
 __global__ __launch_bounds__(256) void k_blur_aggregate(const uint32_t* __restrict__ counts, float* __restrict__ density,
                                                         uint32_t* __restrict__ zero_next, BlurTaps taps, Geom g,
                                                         Agg<Acc> A, const int* status) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];  // read as float4 by the blur
     __shared__ float tile[kBY][kBX];
     if (failed(status)) return;
     blur_aggregate_body<Acc>(counts, density, zero_next, taps, g, A, lds, tile, blockIdx.x, blockIdx.y);
@@ -1083,7 +1083,7 @@ __global__ __launch_bounds__(256) void kb_defect(const BatchTable* __restrict__ 
 
 __global__ __launch_bounds__(256) void kb_blur_agg(const BatchTable* __restrict__ T, BlurTaps taps, int it, int iters,
                                                    const int* status) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];  // read as float4 by the blur
     __shared__ float tile[kBY][kBX];
     if (failed(status)) return;
     int64_t bid, nblk;

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_validate(const float2* __restrict__ xy,
 // selects the raster of a stack of N x N rasters.
 __global__ __launch_bounds__(256) void k_blur(const uint32_t* __restrict__ counts, float* __restrict__ out, int N,
                                               BlurTaps taps, const int* status) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];  // read as float4 by the blur
     if (failed(status)) return;
     counts += (size_t)blockIdx.z * N * N;
     out += (size_t)blockIdx.z * N * N;
