@@ -354,7 +354,8 @@ def bench_splom(dev, reps: int = 5) -> dict:
 
 
 def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: int = 16, batch: int = 16,
-                    workers: int = 16, save_dir: str | None = None, full_field: bool = False) -> dict:
+                    workers: int = 16, save_dir: str | None = None, full_field: bool = False,
+                    train: bool = False) -> dict:
     """The learned surrogate of the 256 x 256, 8-iteration regularisation: a
     5-level U-Net (32-256 channels) reading the 256 x 256 density raster and
     the displacement of the method's first iteration on it (whose integral
@@ -372,18 +373,24 @@ def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: i
     calibrated on fresh training-distribution sets), and times per raster -- single and batched,
     ungated and gated -- against the method, also at equal final uniformity
     (the method's time at the fractional iteration count whose bin std equals
-    the surrogate's)."""
+    the surrogate's).
+    Without `train`, the 64 x 64 variant is the committed checkpoint
+    (surrogate.C5_WEIGHTS, trained this way) and nothing is trained."""
     import numpy as np
     import torch
 
     from paper_2408_06513_amd import capi, datagen
     from paper_2408_06513_amd import surrogate as S
     res, iters, net_res = 256, 8, 256
-    log(f"surrogate: {train_sets} training sets, labels on the 64^2 and 256^2 lattices")
-    t0 = time.perf_counter()
-    sets = S.dataset_compact(range(train_sets), res, iters, dev, net_res=net_res,
-                             out_levels=(2, 0) if full_field else (2,), workers=workers, log=log, first_step=True)
-    t_data = time.perf_counter() - t0
+    full_field = full_field and train
+    sets, t_data = None, None
+    if train:
+        log(f"surrogate: {train_sets} training sets, labels on the 64^2 and 256^2 lattices")
+        t0 = time.perf_counter()
+        sets = S.dataset_compact(range(train_sets), res, iters, dev, net_res=net_res,
+                                 out_levels=(2, 0) if full_field else (2,), workers=workers, log=log,
+                                 first_step=True)
+        t_data = time.perf_counter() - t0
     seeds = list(range(100_000, 100_000 + held_out))
 
     def ev_time(fn, reps=5):
@@ -429,15 +436,20 @@ def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: i
         return float(iters), float(t_k[iters])
 
     def run_variant(out_level: int) -> dict:
-        X = sets[out_level]
-        net = S.UNet(dev, seed=0, out_level=out_level, first_step=True)
-        log(f"surrogate (field {net_res >> out_level}^2): {steps} steps x {batch}")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        losses = S.train(net, X, None, steps=steps, batch=batch, lr=1e-3)
-        torch.cuda.synchronize()
-        t_train = time.perf_counter() - t0
-        if save_dir:
+        if not train:
+            net = S.UNet.load(S.C5_WEIGHTS, dev)
+            assert net.out_level == out_level and net.first_step
+            log(f"surrogate (field {net_res >> out_level}^2): committed checkpoint, {net.t} steps")
+            losses, t_train = None, None
+        else:
+            net = S.UNet(dev, seed=0, out_level=out_level, first_step=True)
+            log(f"surrogate (field {net_res >> out_level}^2): {steps} steps x {batch}")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            losses = S.train(net, sets[out_level], None, steps=steps, batch=batch, lr=1e-3)
+            torch.cuda.synchronize()
+            t_train = time.perf_counter() - t0
+        if save_dir and train:
             os.makedirs(save_dir, exist_ok=True)
             net.save(os.path.join(save_dir, f"surrogate_256_field{net_res >> out_level}.npz"), optimizer=False)
         ev = S.evaluate(net, seeds, res, iters, dev, net_res=net_res, ratio=ratio)
@@ -477,8 +489,13 @@ def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: i
                                                                       ws_batch=wsb, ratio=ratio)), 3) / len(xs)
         k_eq, t_eq = at_equal_uniformity(sur_bs)
         mean = lambda v: float(np.mean(v))
-        rec = {"field_res": net_res >> out_level, "train_steps": steps, "batch": batch, "train_s": round(t_train, 1),
-               "loss_first10": round(mean(losses[:10]), 4), "loss_last10": round(mean(losses[-10:]), 4),
+        rec = {"field_res": net_res >> out_level,
+               "network": "trained in this run" if train else "committed checkpoint (weights/surrogate_256_field64.npz)",
+               "train_steps": steps if train else net.t,
+               "batch": batch if train else S.C5_TRAINING["batch"],
+               "train_s": round(t_train, 1) if train else None,
+               "loss_first10": round(mean(losses[:10]), 4) if train else None,
+               "loss_last10": round(mean(losses[-10:]), 4) if train else None,
                "explained_variance": round(ev["explained"], 4),
                "bin_std_gain_plain": round(ev["plain_gain"], 4), "bin_std_gain_surrogate": round(ev["surrogate_gain"], 4),
                "folded_triangles": ev["folds"], "gate_ratio_to_first_step": round(ratio, 4),
@@ -500,8 +517,9 @@ def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: i
         del net
         return rec
 
-    out = {"res": res, "net_input": net_res, "iters": iters, "train_sets": train_sets, "held_out": held_out,
-           "data_s": round(t_data, 1), "workers": workers,
+    out = {"res": res, "net_input": net_res, "iters": iters,
+           "train_sets": train_sets if train else S.C5_TRAINING["train_sets"], "held_out": held_out,
+           "data_s": round(t_data, 1) if train else None, "workers": workers if train else None,
            "method_bin_std_by_iteration": [round(v, 3) for v in bs_k],
            "method_graph_ms_by_iteration": [round(v, 4) for v in t_k]}
     out["field64"] = run_variant(2)
@@ -717,6 +735,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-splom", action="store_true", help="skip the 45-plot scatterplot-matrix measurement")
     ap.add_argument("--no-surrogate", action="store_true", help="skip training and timing the learned surrogate")
+    ap.add_argument("--surrogate-train", action="store_true",
+                    help="train the surrogate in the run (default: time the committed checkpoint)")
     ap.add_argument("--surrogate-sets", type=int, default=16384, help="training point sets of the surrogate")
     ap.add_argument("--surrogate-save", default=None, help="directory for the trained networks (.npz checkpoints)")
     ap.add_argument("--only-surrogate", action="store_true", help="print only the surrogate measurement")
@@ -759,7 +779,8 @@ def main():
     if args.only_surrogate:
         print(json.dumps({"surrogate_256": bench_surrogate(dev, args.surrogate_sets, args.surrogate_steps,
                                                            save_dir=args.surrogate_save,
-                                                           full_field=args.surrogate_full_field)}), flush=True)
+                                                           full_field=args.surrogate_full_field,
+                                                           train=args.surrogate_train)}), flush=True)
         return
     if args.only_sweeps:
         print(json.dumps({"sweeps": bench_sweeps(dev)}), flush=True)
@@ -795,7 +816,8 @@ def main():
         rec["splom_45_plots"] = bench_splom(dev)
     if not args.no_surrogate:
         rec["surrogate_256"] = bench_surrogate(dev, args.surrogate_sets, args.surrogate_steps,
-                                               save_dir=args.surrogate_save, full_field=args.surrogate_full_field)
+                                               save_dir=args.surrogate_save, full_field=args.surrogate_full_field,
+                                               train=args.surrogate_train)
         rec["surrogate_convs"] = bench_convs(dev)
     if not args.no_sweeps:
         rec["sweeps"] = bench_sweeps(dev)

@@ -25,12 +25,20 @@ copies for the convolutions.
 from __future__ import annotations
 
 import math
+import os
 import time
 
 import numpy as np
 import torch
 
 from . import capi, datagen, nn
+
+# The trained network of the 256 x 256, 8-iteration configuration (5 levels,
+# 32-256 channels, first-step input, 64 x 64 output lattice; bfloat16 weights),
+# written by UNet.save after 3000 Adam steps of 16 on 16,384 method-labelled
+# point sets (seeds 0..16383 of datagen.surrogate_mixture).
+C5_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "surrogate_256_field64.npz")
+C5_TRAINING = {"train_sets": 16384, "train_steps": 3000, "batch": 16, "lr": 1e-3}
 
 BF16, F32 = torch.bfloat16, torch.float32
 CIN, COUT = 8, 8  # input channel 0 = relative density; output channels 0, 1 = displacement
@@ -773,7 +781,8 @@ def regularize_many_gated(net: UNet, xys, res: int, iters: int, min_gain: float 
 def evaluate(net: UNet, seeds, res: int, iters: int, dev, n_hi: int = 500_000, min_gain: float = 0.2,
              net_res: int | None = None, ratio: float | None = None) -> dict:
     """Held-out comparison on fresh point sets: bin standard deviation (4 x 4
-    texel bins) before, after the plain method, after the surrogate's field;
+    texel bins) before, after the plain method, after its first iteration,
+    after the surrogate's field;
     folds of the surrogate's deformed lattice; how often the gate (ratio /
     min_gain as in regularize) falls back, and how many accepted predictions
     end more than 5% less uniform than the method; the displacement error
@@ -785,6 +794,8 @@ def evaluate(net: UNet, seeds, res: int, iters: int, dev, n_hi: int = 500_000, m
         before = bin_std(xy, res)
         plain = xy.clone()
         capi.regularize(plain, res, iters)
+        one = xy.clone()
+        capi.regularize(one, res, 1)
         field = predict_field(net, xy, res, net_res=net_res)
         folds = torch.zeros(1, dtype=torch.uint32, device=dev)
         nn.count_folds(field, (net_res or res) >> net.out_level, folds)
@@ -801,7 +812,7 @@ def evaluate(net: UNet, seeds, res: int, iters: int, dev, n_hi: int = 500_000, m
         gated = xy.clone()
         which = regularize(net, gated, res, iters, min_gain, net_res=net_res, ratio=ratio)
         rows.append({"n": int(xy.shape[0]), "before": before, "plain": bin_std(plain, res),
-                     "surrogate": bin_std(sur, res), "folds": int(folds.item()), "gate": which,
+                     "first": bin_std(one, res), "surrogate": bin_std(sur, res), "folds": int(folds.item()), "gate": which,
                      "mse": float(loss.item()), "mse_zero": float(base.item())})
     acc = [r for r in rows if r["gate"] == "surrogate"]
     return {"rows": rows,
