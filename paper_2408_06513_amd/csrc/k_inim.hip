@@ -194,6 +194,24 @@ __device__ __forceinline__ void scan_col_body(const Geom& g, const Agg<Acc>& A, 
     const int ii = valid ? i : 0;
     const int c = (bx * 64) / g.W;  // the block's 64 columns lie in one tile
     const size_t N = (size_t)g.N;
+    // the wave's column terms are loaded first, so that their latency overlaps
+    // the tile-total phase below (for 128-bit accumulators they are loaded in
+    // rounds further down)
+    constexpr int PL = sizeof(Acc) <= 8 ? kScanMaxP : 1;
+    Acc cs[PL], tc[PL];
+    if constexpr (sizeof(Acc) <= 8) {
+        const int b0 = wave * P;
+#pragma unroll
+        for (int k = 0; k < PL; ++k) {
+            cs[k] = Acc(0);
+            tc[k] = Acc(0);
+            const int b = b0 + k;
+            if (k < P && b < g.B && valid) {
+                cs[k] = A.colsum[(size_t)b * N + ii];
+                tc[k] = A.tcsp[(size_t)b * N + ii];
+            }
+        }
+    }
     // left[b]: the totals of the tiles left of c in band b, one (band, tile)
     // pair per thread (tiles q, q + 16, ... in 16-lane row slot q), summed
     // over each 16-lane row by row shifts; the loop is uniform over the block,
@@ -217,16 +235,11 @@ __device__ __forceinline__ void scan_col_body(const Geom& g, const Agg<Acc>& A, 
     if constexpr (sizeof(Acc) <= 8) {
         // all P bands of the wave at once: wave w holds bands [w P, w P + P)
         const int b0 = wave * P;
-        Acc cs[kScanMaxP], da[kScanMaxP];
+        Acc da[kScanMaxP];
 #pragma unroll
         for (int k = 0; k < kScanMaxP; ++k) {
-            cs[k] = Acc(0);
-            da[k] = Acc(0);
             const int b = b0 + k;
-            if (k < P && b < g.B && valid) {
-                cs[k] = A.colsum[(size_t)b * N + ii];
-                da[k] = A.tcsp[(size_t)b * N + ii] + left[b];
-            }
+            da[k] = (k < P && b < g.B && valid) ? tc[k] + left[b] : Acc(0);
         }
         Acc rc = Acc(0), ra = Acc(0);
 #pragma unroll
@@ -348,12 +361,29 @@ __device__ __forceinline__ void scan_diag_body(const Geom& g, const Agg<Acc>& A,
         const Acc* ainb = K.ain + (size_t)b * N;
         const Acc* tr = A.trow + (size_t)b * T * H + r;
         Acc* ac = K.AC + (size_t)b * (T + 1) * H + r;
+        // the terms of a group of tiles are loaded before their stores (the
+        // stores could alias the loads as far as the compiler knows, which
+        // would otherwise serialise every load behind the previous store);
+        // groups of 32 / sizeof(Acc) x 4 tiles keep the terms in registers
+        constexpr int GT = sizeof(Acc) >= 16 ? 4 : (sizeof(Acc) == 8 ? 8 : 16);
         Acc run = Acc(0);
         ac[0] = Acc(0);
-#pragma unroll 8
-        for (int c = 1; c <= T; ++c) {
-            run += tr[(size_t)(c - 1) * H];
-            ac[(size_t)c * H] = ainb[c * W - 1] + run;
+        for (int c0 = 1; c0 <= T; c0 += GT) {
+            Acc tv[GT], av[GT];
+#pragma unroll
+            for (int k = 0; k < GT; ++k) {
+                const int c = c0 + k;
+                tv[k] = c <= T ? tr[(size_t)(c - 1) * H] : Acc(0);
+                av[k] = c <= T ? ainb[c * W - 1] : Acc(0);
+            }
+#pragma unroll
+            for (int k = 0; k < GT; ++k) {
+                const int c = c0 + k;
+                if (c <= T) {
+                    run += tv[k];
+                    ac[(size_t)c * H] = av[k] + run;
+                }
+            }
         }
         return;
     }
@@ -428,18 +458,29 @@ __global__ __launch_bounds__(1024) void k_inim_scan_diag(Geom g, Agg<Acc> A, Car
 }
 
 // ------------------------------------------------------------------ marginals
+// Both cases of each marginal read their terms from the same few arrays; the
+// loads are issued at clamped (always valid) indices before the case is
+// chosen, so that one marginal costs one round of memory latency, and the
+// terms are then added in the same order as the case's formula.
 // U(u) = sum over i'+j' <= u:  for u < N it is R(0, u); beyond, R(u-N+1, N-1)
 // misses exactly the columns left of u-N+1, i.e. X(u-N).
 template <typename Acc>
 __device__ __forceinline__ Acc marg_U(const Geom& g, const Agg<Acc>& A, const Carry<Acc>& K, int u) {
     const int N = g.N;
-    if (u <= N - 1) {
-        const int b = u / g.H, r = u - b * g.H;
-        Acc v = K.ain[(size_t)b * N + r] + A.tRedge[((size_t)b * g.T) * g.H + r];
-        if (r + 1 < N) v += K.Rin[(size_t)b * N + r + 1];
+    const bool lo = u <= N - 1;
+    const int b = lo ? u / g.H : g.B, r = lo ? u - (u / g.H) * g.H : 0;
+    const int ia = lo ? r : u - N;           // column of the alpha carry
+    const int ir = lo ? r + 1 : u - N + 1;   // column of the up-right carry
+    const bool has_r = !lo || r + 1 < N;
+    const Acc a = K.ain[(size_t)b * N + ia];
+    const Acc rin = K.Rin[(size_t)b * N + (has_r ? ir : 0)];
+    const Acc e = A.tRedge[((size_t)(lo ? b : 0) * g.T) * g.H + r];
+    if (lo) {
+        Acc v = a + e;
+        if (has_r) v += rin;
         return v;
     }
-    return K.Rin[(size_t)g.B * N + (u - N + 1)] + K.ain[(size_t)g.B * N + (u - N)];
+    return rin + a;
 }
 
 // V(v) = sum over i'-j' >= v:  for v >= 0 it is L(N-1, N-1-v); below, L(N-1+v, N-1)
@@ -447,18 +488,22 @@ __device__ __forceinline__ Acc marg_U(const Geom& g, const Agg<Acc>& A, const Ca
 template <typename Acc>
 __device__ __forceinline__ Acc marg_V(const Geom& g, const Agg<Acc>& A, const Carry<Acc>& K, int v) {
     const int N = g.N;
-    if (v >= 0) {
-        const int j = N - 1 - v;
-        const int b = j / g.H, r = j - b * g.H;
-        const int m = N - 2 - r;
-        const Acc* ainb = K.ain + (size_t)b * N;
-        Acc val = ainb[N - 1] - (m >= 0 ? ainb[m] : Acc(0));
-        val += A.tLedge[((size_t)b * g.T + (g.T - 1)) * g.H + r];
-        if (m >= 0) val += K.Lin[(size_t)b * N + m];
+    const bool lo = v >= 0;
+    const int j = lo ? N - 1 - v : 0;
+    const int b = lo ? j / g.H : g.B, r = lo ? j - (j / g.H) * g.H : 0;
+    const int m = lo ? N - 2 - r : N - 1 + v;  // column of the second alpha term and the up-left carry
+    const Acc* ainb = K.ain + (size_t)b * N;
+    const Acc a1 = ainb[N - 1];
+    const Acc a2 = ainb[m >= 0 ? m : 0];
+    const Acc lin = K.Lin[(size_t)b * N + (m >= 0 ? m : 0)];
+    const Acc e = A.tLedge[((size_t)(lo ? b : 0) * g.T + (g.T - 1)) * g.H + r];
+    if (lo) {
+        Acc val = a1 - (m >= 0 ? a2 : Acc(0));
+        val += e;
+        if (m >= 0) val += lin;
         return val;
     }
-    const Acc* ainB = K.ain + (size_t)g.B * N;
-    return K.Lin[(size_t)g.B * N + (N - 1 + v)] + (ainB[N - 1] - ainB[N - 1 + v]);
+    return lin + (a1 - a2);
 }
 
 // Y(j) = alpha(N-1, j), the last entry of the band row's alpha carries.
