@@ -167,6 +167,28 @@ int inim_deform(const void* alpha, const void* alpha_t, inim_dtype dt, const dou
                 int32_t res, double d0, float* field, hipStream_t stream);
 
 /*
+ * Steps 2 and 3 of one iteration on a given density (Sec. 4.2 eq. (map_res),
+ * Sec. 3.1 planes): the field T(p) at every texel centre of the res x res
+ * float density d_r with background d0, by the kernels of one iteration of
+ * inim_regularize after its smoothing: the integral images accumulated in
+ * double and the map evaluated in their last pass, so alpha and alpha_t never
+ * reach memory (res >= 64; smaller rasters take a separate marginals pass).
+ * The defect t(p; 1) is recomputed into the workspace by every call.
+ *   density   device, float [res*res], row-major; meant for non-negative
+ *             densities (a smoothed count raster): sums of mixed signs are
+ *             only as exact as double arithmetic makes them.
+ *   d0        background density, finite, >= 0 (the method uses n / res^2).
+ *   field     device, float [res*res][2]; written.
+ *   ws        device workspace of inim_deform_density_workspace_size(res)
+ *             bytes, 256-byte aligned; owned by the caller.
+ * Returns EINVAL for bad arguments, EWORKSPACE for a small ws, before
+ * anything is enqueued.
+ */
+int inim_deform_density_workspace_size(int32_t res, size_t* bytes);
+int inim_deform_density(const float* density, int32_t res, double d0, float* field, void* ws,
+                        size_t ws_bytes, hipStream_t stream);
+
+/*
  * Step 3, per sample (Sec. 4.2): each sample takes the bilinear interpolation
  * of `field` from the four nearest texel centres.  The cell index is clamped
  * to [0, res-2] and the fraction is not, so border samples extrapolate

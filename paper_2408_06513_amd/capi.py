@@ -32,6 +32,7 @@ EXPORTS = (
     "inim_graph_create", "inim_graph_destroy", "inim_regularize_graph", "inim_regularize_probes",
     "inim_batch_workspace_size", "inim_regularize_batch", "inim_batch_autotune",
     "inim_rasterize_many", "inim_advect_many", "inim_regularize_noalloc",
+    "inim_deform_density_workspace_size", "inim_deform_density",
 )
 
 
@@ -105,6 +106,8 @@ def lib() -> ctypes.CDLL:
     L.inim_inim_f32.argtypes = [vp, i32, u32, vp, vp, vp, sz, vp]
     L.inim_deform.argtypes = [vp, vp, ctypes.c_int, vp, i32, f64, vp, vp]
     L.inim_advect.argtypes = [vp, i32, vp, i64, vp, sz, vp]
+    L.inim_deform_density_workspace_size.argtypes = [i32, ctypes.POINTER(sz)]
+    L.inim_deform_density.argtypes = [vp, i32, f64, vp, vp, sz, vp]
     L.inim_rasterize_many.argtypes = [vp, vp, i32, i32, pp, vp, vp, vp, sz, vp]
     L.inim_advect_many.argtypes = [vp, i32, vp, vp, i32, vp, sz, vp]
     L.inim_regularize.argtypes = [vp, i64, i32, i32, pp, vp, sz, vp]
@@ -238,6 +241,27 @@ def deform(alpha: torch.Tensor, alpha_t: torch.Tensor, marg: torch.Tensor, d0: f
         field = torch.empty((res, res, 2), dtype=torch.float32, device=alpha.device)
     _check(lib().inim_deform(_ptr(alpha), _ptr(alpha_t), dt, _ptr(marg), res, float(d0), _ptr(field),
                              _stream(alpha)))
+    return field
+
+
+def deform_density_workspace_size(res: int) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().inim_deform_density_workspace_size(res, ctypes.byref(b)))
+    return b.value
+
+
+def deform_density(density: torch.Tensor, d0: float, field=None, ws=None) -> torch.Tensor:
+    """The deformation field [res, res, 2] of a float density [res, res] with
+    background d0: one iteration's integral images and map, fused."""
+    res = density.shape[-1]
+    if density.dtype != torch.float32 or not density.is_contiguous() or tuple(density.shape) != (res, res):
+        raise ValueError("density must be a contiguous float32 [res, res] tensor")
+    if field is None:
+        field = torch.empty((res, res, 2), dtype=torch.float32, device=density.device)
+    if ws is None:
+        ws = workspace(deform_density_workspace_size(res), density.device)
+    _check(lib().inim_deform_density(_ptr(density), res, float(d0), _ptr(field), _ptr(ws), ws.numel(),
+                                     _stream(density)))
     return field
 
 

@@ -646,6 +646,36 @@ int inim_deform(const void* alpha, const void* alpha_t, inim_dtype dt, const dou
     return e == hipSuccess ? INIM_OK : hip_fail(e, "deform");
 }
 
+int inim_deform_density_workspace_size(int32_t res, size_t* bytes) {
+    int s;
+    if (bytes == nullptr) return fail(INIM_EINVAL, "bytes is NULL");
+    if ((s = check_res(res)) != INIM_OK) return s;
+    const size_t NN = (size_t)res * (size_t)res;
+    *bytes = align256(NN * sizeof(float2)) + inim_scratch_bytes(make_geom(res, 8), 8);
+    return INIM_OK;
+}
+
+int inim_deform_density(const float* density, int32_t res, double d0, float* field, void* ws, size_t ws_bytes,
+                        hipStream_t stream) {
+    int s;
+    size_t need = 0;
+    if ((s = inim_deform_density_workspace_size(res, &need)) != INIM_OK) return s;
+    if (density == nullptr || field == nullptr) return fail(INIM_EINVAL, "NULL pointer argument");
+    if (!(d0 >= 0.0) || !std::isfinite(d0)) return fail(INIM_EINVAL, "d0 must be finite and >= 0");
+    if ((s = check_ws(ws, ws_bytes, need)) != INIM_OK) return s;
+    const size_t NN = (size_t)res * (size_t)res;
+    float2* defect = reinterpret_cast<float2*>(ws);
+    void* scratch = static_cast<char*>(ws) + align256(NN * sizeof(float2));
+    const Geom g = make_geom(res, 8);
+    hipError_t e = launch_defect_field(res, defect, stream);
+    if (e == hipSuccess) e = launch_inim_aggregate<float, double>(density, g, scratch, nullptr, stream);
+    if (e == hipSuccess) e = launch_inim_scans<double>(g, scratch, nullptr, stream);
+    if (e == hipSuccess)
+        e = launch_inim_final<float, double>(density, g, scratch, 0u, nullptr, reinterpret_cast<float2*>(field),
+                                             defect, d0, nullptr, nullptr, stream);
+    return e == hipSuccess ? INIM_OK : hip_fail(e, "deform density");
+}
+
 int inim_advect(const float* field, int32_t res, float* xy, int64_t n, void* ws, size_t ws_bytes,
                 hipStream_t stream) {
     int s;

@@ -297,21 +297,18 @@ def net_radius(radius: int, res: int, net_res: int) -> int:
 
 
 class FirstStep:
-    """Buffers for one iteration of the method on the network's raster: the
-    integral images of a density (alpha, alpha_t, marginals) and its
-    deformation field (inim_inim_f32, inim_deform)."""
+    """The workspace of one iteration of the method on the network's raster:
+    the deformation field of a density (inim_deform_density: its integral
+    images and map fused, the kernels of the method's own iteration)."""
 
     def __init__(self, res: int, dev):
         self.res = res
-        self.planes = torch.empty((2, res, res), dtype=F32, device=dev)
-        self.marg = torch.empty(6 * res - 1, dtype=torch.float64, device=dev)
-        self.ws = capi.workspace(capi.inim_workspace_size(res, capi.F32), dev)
+        self.ws = capi.workspace(capi.deform_density_workspace_size(res), dev)
 
     def field(self, dens: torch.Tensor, n: int, out: torch.Tensor) -> torch.Tensor:
         """The deformation field [res, res, 2] of density `dens` of n samples
         (background n / res^2, the method's default)."""
-        capi.inim(dens, capi.MASK_MIN, planes=self.planes, marg=self.marg, ws=self.ws)
-        return capi.deform(self.planes[0], self.planes[1], self.marg, n / (self.res * self.res), field=out)
+        return capi.deform_density(dens, n / (self.res * self.res), field=out, ws=self.ws)
 
 
 def density_input(xy: torch.Tensor, net_res: int, radius: int, out16: torch.Tensor, counts=None, dens=None,

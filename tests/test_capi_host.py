@@ -76,6 +76,14 @@ def test_argument_errors_return_before_launch():
     assert L.inim_inim_f32(nul, 64, 0x11, nul, nul, nul, 0, nul) == capi.EINVAL                # img NULL
     assert L.inim_inim_u32(ctypes.c_void_p(0x1000), 64, 0x1FF, nul, nul, nul, 0, nul) == capi.EINVAL
     assert L.inim_deform(nul, nul, 1, nul, 64, 1.0, nul, nul) == capi.EINVAL
+    fk = ctypes.c_void_p(0x1000)
+    assert L.inim_deform_density(nul, 64, 1.0, fk, fk, 1 << 30, nul) == capi.EINVAL              # density NULL
+    assert L.inim_deform_density(fk, 100, 1.0, fk, fk, 1 << 30, nul) == capi.EINVAL              # res
+    assert L.inim_deform_density(fk, 64, -1.0, fk, fk, 1 << 30, nul) == capi.EINVAL              # d0 < 0
+    assert L.inim_deform_density(fk, 64, float("nan"), fk, fk, 1 << 30, nul) == capi.EINVAL      # d0 NaN
+    assert L.inim_deform_density(fk, 64, 1.0, fk, nul, 1 << 30, nul) == capi.EWORKSPACE          # ws NULL
+    assert L.inim_deform_density(fk, 64, 1.0, fk, fk, 1024, nul) == capi.EWORKSPACE              # ws too small
+    assert capi.deform_density_workspace_size(1024) > 1024 * 1024 * 8
     assert L.inim_advect(nul, 64, nul, 5, nul, 0, nul) == capi.EINVAL
     fake = ctypes.c_void_p(0x1000)
     assert L.inim_regularize_probes(fake, 10, nul, 5, 64, 2, ctypes.byref(p), nul, 0, nul) == capi.EINVAL

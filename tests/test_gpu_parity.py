@@ -282,6 +282,29 @@ def test_deform_from_planes(capi, dev, res):
     np.testing.assert_allclose(field.cpu().numpy(), oracle.deform(rc, d0), rtol=0, atol=1e-6)
 
 
+@pytest.mark.parametrize("res", [2, 16, 64, 256, 1024])
+def test_deform_density_fused(capi, dev, res):
+    """inim_deform_density (the integral images in double with the map in
+    their last pass, as in one iteration of the regularisation) against the
+    oracle's map of the same float density: the bar of inim_deform."""
+    note(f"deform_density res={res}")
+    xy = dg.plain_small(2)
+    rc = oracle.counts(xy, res)
+    dr = oracle.blur(rc, 8).astype(np.float32)
+    d0 = xy.shape[0] / res / res
+    ws = capi.workspace(capi.deform_density_workspace_size(res), dev)
+    g = to_dev(dr, dev)
+    for dd in (d0, 0.0, 4.0 * d0):
+        field = capi.deform_density(g, dd, ws=ws)
+        torch.cuda.synchronize()
+        ref = oracle.deform(dr.astype(np.float64), dd)
+        np.testing.assert_allclose(field.cpu().numpy(), ref, rtol=0, atol=1e-6, err_msg=f"d0={dd}")
+    # the same field again from the reused workspace, bit for bit
+    again = capi.deform_density(g, d0, ws=ws)
+    first = capi.deform_density(g, d0)
+    assert torch.equal(again, first)
+
+
 def test_advect(capi, dev):
     res = 256
     xy = dg.plain_small(3)
