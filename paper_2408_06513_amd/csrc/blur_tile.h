@@ -34,7 +34,8 @@ __host__ __device__ inline size_t blur_smem_floats(int r) {
 // (16+2r) x (64+2r) window of counts is staged in `lds` as float, filtered
 // along x into a second LDS buffer, then along y; emit(row, col, value) is
 // called once for every output texel of the tile inside the raster.
-// R > 0 fixes the radius at compile time: the window sizes are constants, the
+// R > 0 fixes the radius at compile time: the window sizes are constants (for
+// R a multiple of 4 the window is loaded in 16-byte chunks), the
 // taps sit in registers, and each thread computes four neighbouring outputs
 // from one register window (4 + 2R values read once: as float4 along x,
 // column-wise along y) instead of reading 2R + 1 values per output.  Every
@@ -47,10 +48,34 @@ __device__ __forceinline__ void blur_tile_r(const uint32_t* __restrict__ counts,
     const int IW = kBX + 2 * r, IH = kBY + 2 * r;
     float* in = lds;             // IH x IW
     float* mid = lds + IH * IW;  // IH x kBX
-    for (int k = threadIdx.x; k < IH * IW; k += blockDim.x) {
-        const int row = k / IW, cc = k - row * IW;
-        const int gj = mirror(oy + row - r, N), gi = mirror(ox + cc - r, N);
-        in[k] = (float)counts[(size_t)gj * N + gi];
+    // the window in chunks of 4 columns: a chunk inside the raster is one
+    // 16-byte load (its first column, ox - R + 4q, is a multiple of 4; the
+    // raster's base must be 16-byte aligned, else every chunk takes the other
+    // path), a chunk over the border takes its 4 mirrored columns one by one
+    const bool vec = (reinterpret_cast<uintptr_t>(counts) & 15u) == 0u;
+    if (R > 0 && R % 4 == 0 && vec) {
+        constexpr int IWc = kBX + 2 * R, IHc = kBY + 2 * R, CW = IWc / 4;
+        for (int k = threadIdx.x; k < IHc * CW; k += blockDim.x) {
+            const int row = k / CW, q = k - row * CW;
+            const int gj = mirror(oy + row - R, N);
+            const int c0 = ox - R + 4 * q;
+            const uint32_t* src = counts + (size_t)gj * N;
+            float4 v;
+            if (c0 >= 0 && c0 + 3 < N) {
+                const uint4 u = *reinterpret_cast<const uint4*>(src + c0);
+                v = make_float4((float)u.x, (float)u.y, (float)u.z, (float)u.w);
+            } else {
+                v = make_float4((float)src[mirror(c0, N)], (float)src[mirror(c0 + 1, N)], (float)src[mirror(c0 + 2, N)],
+                                (float)src[mirror(c0 + 3, N)]);
+            }
+            *reinterpret_cast<float4*>(in + row * IWc + 4 * q) = v;
+        }
+    } else {
+        for (int k = threadIdx.x; k < IH * IW; k += blockDim.x) {
+            const int row = k / IW, cc = k - row * IW;
+            const int gj = mirror(oy + row - r, N), gi = mirror(ox + cc - r, N);
+            in[k] = (float)counts[(size_t)gj * N + gi];
+        }
     }
     __syncthreads();
     if constexpr (R > 0) {
