@@ -355,33 +355,54 @@ __device__ __forceinline__ void scan_diag_body(const Geom& g, const Agg<Acc>& A,
                                                int bx, int by) {
     const int N = g.N, H = g.H, W = g.W, T = g.T;
     if (by == 2) {
-        const int j = bx * blockDim.x + threadIdx.x;
-        if (j >= N) return;
-        const int b = j / H, r = j - b * H;
-        const Acc* ainb = K.ain + (size_t)b * N;
-        const Acc* tr = A.trow + (size_t)b * T * H + r;
-        Acc* ac = K.AC + (size_t)b * (T + 1) * H + r;
-        // the terms of a group of tiles are loaded before their stores (the
-        // stores could alias the loads as far as the compiler knows, which
-        // would otherwise serialise every load behind the previous store);
-        // groups of 32 / sizeof(Acc) x 4 tiles keep the terms in registers
+        // S consecutive lanes per raster row j, each taking GT tiles: the lane
+        // loads its tiles' terms at once (one round of memory latency; the
+        // stores could alias the loads as far as the compiler knows, so a
+        // load-add-store loop would wait for memory once per tile), then adds
+        // the totals of the row's earlier segments (a scan over the S lanes)
+        // before storing.  GT = 32 / sizeof(Acc) x 4 keeps the terms in
+        // registers; S = T / GT is a power of two of at most 64.
         constexpr int GT = sizeof(Acc) >= 16 ? 4 : (sizeof(Acc) == 8 ? 8 : 16);
-        Acc run = Acc(0);
-        ac[0] = Acc(0);
-        for (int c0 = 1; c0 <= T; c0 += GT) {
+        const int S = (T + GT - 1) / GT;
+        const int lane = lane_id();
+        const int64_t pairs = (int64_t)N * S;
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        // every lane of a wave runs the same trips (the scan moves data between lanes)
+        for (int64_t base = (int64_t)bx * blockDim.x + (threadIdx.x & ~63u); base < pairs; base += stride) {
+            const int64_t t = base + lane;
+            const bool live = t < pairs;
+            const int j = live ? (int)(t / S) : 0, seg = live ? (int)(t - (int64_t)j * S) : 0;
+            const int b = j / H, r = j - b * H;
+            const Acc* ainb = K.ain + (size_t)b * N;
+            const Acc* tr = A.trow + (size_t)b * T * H + r;
+            Acc* ac = K.AC + (size_t)b * (T + 1) * H + r;
+            const int c0 = 1 + seg * GT;
             Acc tv[GT], av[GT];
+            Acc tot = Acc(0);
 #pragma unroll
             for (int k = 0; k < GT; ++k) {
                 const int c = c0 + k;
-                tv[k] = c <= T ? tr[(size_t)(c - 1) * H] : Acc(0);
-                av[k] = c <= T ? ainb[c * W - 1] : Acc(0);
+                const bool in = live && c <= T;
+                tv[k] = in ? tr[(size_t)(c - 1) * H] : Acc(0);
+                av[k] = in ? ainb[c * W - 1] : Acc(0);
             }
 #pragma unroll
-            for (int k = 0; k < GT; ++k) {
-                const int c = c0 + k;
-                if (c <= T) {
-                    run += tv[k];
-                    ac[(size_t)c * H] = av[k] + run;
+            for (int k = 0; k < GT; ++k) tot += tv[k];
+            Acc incl = tot;  // inclusive scan of the segment totals over the row's S lanes
+            for (int d = 1; d < S; d <<= 1) {
+                const Acc o = shfl_up(incl, d);
+                if (seg >= d) incl += o;
+            }
+            Acc run = incl - tot;
+            if (live) {
+                if (seg == 0) ac[0] = Acc(0);
+#pragma unroll
+                for (int k = 0; k < GT; ++k) {
+                    const int c = c0 + k;
+                    if (c <= T) {
+                        run += tv[k];
+                        ac[(size_t)c * H] = av[k] + run;
+                    }
                 }
             }
         }
