@@ -366,7 +366,7 @@ __device__ __forceinline__ void scan_diag_body(const Geom& g, const Agg<Acc>& A,
         const int S = (T + GT - 1) / GT;
         const int lane = lane_id();
         const int64_t pairs = (int64_t)N * S;
-        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        const int64_t stride = (int64_t)((2 * N + 1 + 63) / 64) * blockDim.x;  // this raster's blocks of the slice
         // every lane of a wave runs the same trips (the scan moves data between lanes)
         for (int64_t base = (int64_t)bx * blockDim.x + (threadIdx.x & ~63u); base < pairs; base += stride) {
             const int64_t t = base + lane;

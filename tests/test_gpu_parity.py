@@ -305,6 +305,26 @@ def test_deform_density_fused(capi, dev, res):
     assert torch.equal(again, first)
 
 
+@pytest.mark.parametrize("res", [256, 1024])
+def test_deform_density_is_the_methods_first_iteration(capi, dev, res):
+    """rasterize + deform_density + advect moves the samples as one
+    iteration of regularize does (the same density; the same integral-image
+    and map kernels, the aggregate pass run apart from the smoothing): equal
+    to rounding, and the rasters bit for bit."""
+    note(f"first iteration via deform_density, res={res}")
+    xy = to_dev(dg.plain_small(4), dev)
+    one = xy.clone()
+    capi.regularize(one, res, 1)
+    counts, dens, _ = capi.rasterize(xy, res)
+    ref_counts = torch.from_numpy(oracle.counts(xy.cpu().numpy(), res).astype(np.uint32))
+    assert torch.equal(counts.cpu(), ref_counts)
+    field = capi.deform_density(dens, xy.shape[0] / (res * res))
+    moved = xy.clone()
+    capi.advect(field, moved)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(moved.cpu().numpy(), one.cpu().numpy(), rtol=0, atol=1e-6)
+
+
 def test_advect(capi, dev):
     res = 256
     xy = dg.plain_small(3)
