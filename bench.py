@@ -457,7 +457,7 @@ def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: i
         ev = S.evaluate(net, seeds, res, iters, dev, net_res=net_res, ratio=ratio)
         sur_bs = float(np.mean([r["surrogate"] for r in ev["rows"]]))
         # per raster, single: the method's graph, the surrogate's graph (ungated), the gated call
-        plain, sur, gated = [], [], []
+        plain, sur, gated, gated_eager = [], [], [], []
         for x0 in xs0:
             xy = x0.clone()
             ws = capi.workspace(capi.workspace_size(res, xy.shape[0]), dev)
@@ -467,8 +467,11 @@ def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: i
             sg = S.SurrogateGraph(net, xy.shape[0], res, net_res, xy=xy)
             sur.append(ev_time(lambda: (xy.copy_(x0), sg())))
             del sg
-            gated.append(ev_time(lambda: (xy.copy_(x0), S.regularize(net, xy, res, iters, net_res=net_res,
-                                                                       ratio=ratio)), 3))
+            gated_eager.append(ev_time(lambda: (xy.copy_(x0), S.regularize(net, xy, res, iters, net_res=net_res,
+                                                                             ratio=ratio)), 3))
+            gg = S.SurrogateGatedGraph(net, xy, res, iters, net_res=net_res, ratio=ratio)
+            gated.append(ev_time(lambda: (xy.copy_(x0), gg()), 5))
+            del gg
         # batched over the held-out sets
         xs = [x.clone() for x in xs0]
 
@@ -507,6 +510,7 @@ def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: i
                "plain_graph_ms_per_raster": round(mean(plain), 4),
                "surrogate_graph_ms_per_raster": round(mean(sur), 4),
                "surrogate_gated_ms_per_raster": round(mean(gated), 4),
+               "surrogate_gated_eager_ms_per_raster": round(mean(gated_eager), 4),
                f"plain_batched_graph_ms_per_raster_batch{held_out}": round(t_b_plain, 4),
                f"surrogate_batched_graph_ms_per_raster_batch{held_out}": round(t_b_sur, 4),
                f"surrogate_gated_batched_ms_per_raster_batch{held_out}": round(t_b_gated, 4),

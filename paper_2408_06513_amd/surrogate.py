@@ -710,6 +710,84 @@ def _std_from_moments(m, res: int, bin_px: int = 4) -> float:
     return math.sqrt(max(m[1] / k - (m[0] / k) ** 2, 0.0))
 
 
+class SurrogateGatedGraph:
+    """regularize() on one fixed tensor of samples, its GPU work captured once
+    as a HIP graph: the prediction, the fold count, the move of a copy, the
+    method's first step on another copy (the gate's reference, when the
+    network reads it) and the three bin moments.  A call replays the graph,
+    reads the fold count and the moments back once, and then either copies
+    the moved samples into the tensor or runs the method on it (its own
+    captured graph).  Same decisions and results as regularize(); nothing in
+    either graph is a memset."""
+
+    def __init__(self, net: UNet, xy: torch.Tensor, res: int, iters: int, net_res: int | None = None,
+                 ratio: float | None = None, min_gain: float = 0.2):
+        self.net, self.xy, self.res, self.iters = net, xy, res, iters
+        self.net_res = net_res or res
+        self.ratio, self.min_gain = ratio, min_gain
+        dev = xy.device
+        r = self.net_res
+        self.by_first = ratio is not None and net.first_step and self.net_res == res
+        self.radius = net_radius(8, res, r)
+        self.x16 = torch.empty((1, r, r, CIN), dtype=BF16, device=dev)
+        self.counts_r = torch.empty((r, r), dtype=torch.uint32, device=dev)
+        self.dens = torch.empty((r, r), dtype=F32, device=dev)
+        self.first = FirstStep(r, dev) if net.first_step else None
+        self.field1 = torch.empty((r, r, 2), dtype=F32, device=dev) if net.first_step else None
+        self.fres = r >> net.out_level
+        self.field = torch.empty((self.fres, self.fres, 2), dtype=F32, device=dev)
+        self.fwork = torch.empty_like(self.field)
+        self.folds = torch.zeros(1, dtype=torch.uint32, device=dev)
+        self.mom = torch.zeros((3, 2), dtype=torch.float64, device=dev)  # input, moved, after the first step
+        self.counts = torch.empty((res, res), dtype=torch.uint32, device=dev)
+        self.moved = torch.empty_like(xy)
+        self.firsts = torch.empty_like(xy)
+        self.ws = capi.workspace(256, dev)
+        self.ws_m = capi.workspace(256, dev)
+        self.ws_reg = capi.workspace(capi.workspace_size(res, xy.shape[0]), dev)
+        self.method = capi.Graph()
+        self._run()  # sizes the network's work buffer outside the capture
+        torch.cuda.synchronize(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._run()
+        torch.cuda.synchronize(dev)
+
+    def _run(self):
+        xy = self.xy
+        density_input(xy, self.net_res, self.radius, self.x16[0], self.counts_r, self.dens, ws=self.ws,
+                      check=False, first=self.first, field1=self.field1)
+        y = self.net.forward(self.x16)
+        nn.field(y[0], self.fres, self.field, field_radius(self.fres), work=self.fwork)
+        self.folds.zero_()
+        nn.count_folds(self.field, self.fres, self.folds)
+        if not self.by_first:  # the relative-gain gate measures the input
+            _bin_moments_into(xy, self.res, self.mom[0], self.counts, self.ws_m)
+        if self.by_first:
+            torch.mul(xy, 1.0, out=self.firsts)  # a copy kernel (x * 1 is exact, -0 included)
+            capi.advect(self.field1, self.firsts, ws=self.ws_m, check=False)
+            _bin_moments_into(self.firsts, self.res, self.mom[2], self.counts, self.ws_m)
+        torch.mul(xy, 1.0, out=self.moved)
+        capi.advect(self.field, self.moved, ws=self.ws_m, check=False)
+        _bin_moments_into(self.moved, self.res, self.mom[1], self.counts, self.ws_m)
+
+    def __call__(self) -> str:
+        """Moves the tensor given at construction; returns 'surrogate' or
+        'fallback'.  Raises DomainError (samples unmoved) for a NaN or
+        out-of-range sample."""
+        self.graph.replay()
+        check_status([self.ws, self.ws_m])
+        mh = self.mom.cpu().numpy()  # one readback: the stream is idle after the status check
+        folds = int(self.folds.cpu().item())
+        ref = (self.ratio * _std_from_moments(mh[2], self.res) if self.by_first
+               else (1.0 - self.min_gain) * _std_from_moments(mh[0], self.res))
+        if folds == 0 and _std_from_moments(mh[1], self.res) <= ref:
+            self.xy.copy_(self.moved)
+            return "surrogate"
+        capi.regularize_graph(self.xy, self.res, self.iters, self.method, self.ws_reg)
+        return "fallback"
+
+
 def regularize_many_gated(net: UNet, xys, res: int, iters: int, min_gain: float = 0.2,
                           net_res: int | None = None, ws_batch: torch.Tensor | None = None,
                           ratio: float | None = None) -> list:

@@ -154,3 +154,32 @@ def test_c5_trained_network_passes_the_gate():
     raw = S.UNet(dev, seed=7, out_level=2, first_step=True)
     ev0 = S.evaluate(raw, range(100_000, 100_004), res, iters, dev, net_res=res, ratio=ratio)
     assert ev0["fallbacks"] == 4
+
+
+def test_gated_graph_equals_eager_gate():
+    """SurrogateGatedGraph (the gated move captured once, one readback per
+    call) takes the same decisions as regularize() and leaves the same
+    samples, bit for bit, on every replay, with eager work between the
+    replays; sets of both outcomes are covered."""
+    from paper_2408_06513_amd import datagen
+    from paper_2408_06513_amd import surrogate as S
+    dev = torch.device("cuda:0")
+    net = S.UNet.load(WEIGHTS, dev)
+    res, iters, ratio = 256, 8, 0.5715
+    seen = set()
+    for seed in range(100_000, 100_016):
+        x0 = torch.from_numpy(datagen.surrogate_mixture(seed)).to(dev)
+        eager = x0.clone()
+        dec = S.regularize(net, eager, res, iters, net_res=res, ratio=ratio)
+        xy = x0.clone()
+        gg = S.SurrogateGatedGraph(net, xy, res, iters, net_res=res, ratio=ratio)
+        for rep in range(3):
+            xy.copy_(x0)
+            assert gg() == dec, (seed, rep)
+            assert torch.equal(xy, eager), (seed, rep)
+            torch.cuda.synchronize()
+            _ = (x0 * 2.0).sum().item()  # eager work between the replays
+        seen.add(dec)
+        note(f"gated graph seed {seed}: {dec}")
+        del gg
+    assert seen == {"surrogate", "fallback"}
