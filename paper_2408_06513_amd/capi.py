@@ -254,10 +254,14 @@ def deform_density(density: torch.Tensor, d0: float, field=None, ws=None) -> tor
     """The deformation field [res, res, 2] of a float density [res, res] with
     background d0: one iteration's integral images and map, fused."""
     res = density.shape[-1]
-    if density.dtype != torch.float32 or not density.is_contiguous() or tuple(density.shape) != (res, res):
-        raise ValueError("density must be a contiguous float32 [res, res] tensor")
+    if not (density.is_cuda and density.dtype == torch.float32 and density.is_contiguous()
+            and tuple(density.shape) == (res, res)):
+        raise ValueError("density must be a contiguous float32 [res, res] device tensor")
     if field is None:
         field = torch.empty((res, res, 2), dtype=torch.float32, device=density.device)
+    elif not (field.is_cuda and field.dtype == torch.float32 and field.is_contiguous()
+              and tuple(field.shape) == (res, res, 2)):
+        raise ValueError("field must be a contiguous float32 [res, res, 2] device tensor")
     if ws is None:
         ws = workspace(deform_density_workspace_size(res), density.device)
     _check(lib().inim_deform_density(_ptr(density), res, float(d0), _ptr(field), _ptr(ws), ws.numel(),

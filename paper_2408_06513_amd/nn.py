@@ -74,7 +74,12 @@ def _check(status: int):
 
 
 def _p(t):
-    return None if t is None else ctypes.c_void_p(t.data_ptr())
+    """The device address of a contiguous device tensor (None stays NULL)."""
+    if t is None:
+        return None
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError("the layers take contiguous device tensors")
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _s(t):
