@@ -355,7 +355,7 @@ def bench_splom(dev, reps: int = 5) -> dict:
             "speedup_vs_sequential": round(t_seq / best, 2)}
 
 
-def bench_surrogate(dev, train_sets: int = 16384, steps: int = 3000, held_out: int = 16, batch: int = 16,
+def bench_surrogate(dev, train_sets: int = 50000, steps: int = 10000, held_out: int = 16, batch: int = 16,
                     workers: int = 16, save_dir: str | None = None, full_field: bool = False,
                     train: bool = False) -> dict:
     """The learned surrogate of the 256 x 256, 8-iteration regularisation: a
@@ -743,13 +743,13 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip training and timing the learned surrogate")
     ap.add_argument("--surrogate-train", action="store_true",
                     help="train the surrogate in the run (default: time the committed checkpoint)")
-    ap.add_argument("--surrogate-sets", type=int, default=16384, help="training point sets of the surrogate")
+    ap.add_argument("--surrogate-sets", type=int, default=50000, help="training point sets of the surrogate")
     ap.add_argument("--surrogate-save", default=None, help="directory for the trained networks (.npz checkpoints)")
     ap.add_argument("--only-surrogate", action="store_true", help="print only the surrogate measurement")
     ap.add_argument("--surrogate-full-field", action="store_true",
                     help="also train and measure the network with the full 256 x 256 output lattice")
     ap.add_argument("--only-convs", action="store_true", help="print only the per-convolution matrix-core rates")
-    ap.add_argument("--surrogate-steps", type=int, default=3000, help="training steps of the surrogate")
+    ap.add_argument("--surrogate-steps", type=int, default=10000, help="training steps of the surrogate")
     ap.add_argument("--no-sweeps", action="store_true", help="skip the parameter and quality sweeps")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--only-sweeps", action="store_true",

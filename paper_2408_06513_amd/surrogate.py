@@ -35,10 +35,10 @@ from . import capi, datagen, nn
 
 # The trained network of the 256 x 256, 8-iteration configuration (5 levels,
 # 32-256 channels, first-step input, 64 x 64 output lattice; bfloat16 weights),
-# written by UNet.save after 3000 Adam steps of 16 on 16,384 method-labelled
-# point sets (seeds 0..16383 of datagen.surrogate_mixture).
+# written by UNet.save after 10,000 Adam steps of 16 on 50,000 method-labelled
+# point sets (seeds 0..49999 of datagen.surrogate_mixture).
 C5_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "surrogate_256_field64.npz")
-C5_TRAINING = {"train_sets": 16384, "train_steps": 3000, "batch": 16, "lr": 1e-3}
+C5_TRAINING = {"train_sets": 50000, "train_steps": 10000, "batch": 16, "lr": 1e-3}
 
 BF16, F32 = torch.bfloat16, torch.float32
 CIN, COUT = 8, 8  # input channel 0 = relative density; output channels 0, 1 = displacement
