@@ -383,8 +383,10 @@ __device__ __forceinline__ void scan_diag_body(const Geom& g, const Agg<Acc>& A,
             for (int k = 0; k < GT; ++k) {
                 const int c = c0 + k;
                 const bool in = live && c <= T;
-                tv[k] = in ? tr[(size_t)(c - 1) * H] : Acc(0);
-                av[k] = in ? ainb[c * W - 1] : Acc(0);
+                const int cc = in ? c : 1;  // loads at a valid index, used only where `in`
+                const Acc t_ = tr[(size_t)(cc - 1) * H], a_ = ainb[cc * W - 1];
+                tv[k] = in ? t_ : Acc(0);
+                av[k] = in ? a_ : Acc(0);
             }
 #pragma unroll
             for (int k = 0; k < GT; ++k) tot += tv[k];
@@ -428,6 +430,64 @@ __device__ __forceinline__ void scan_diag_body(const Geom& g, const Agg<Acc>& A,
     const int b0 = (q * nw + wave) * pc;
     Acc term[PC];
     int col[PC];
+    if constexpr (sizeof(Acc) <= 8) {
+        // the four loads of every term of a group of 4 bands are issued at
+        // clamped (always valid) indices before any is used, so the wave
+        // waits for memory once per group (once at most rasters), not once
+        // per band; then the terms are formed as below
+        constexpr int KG = 4;
+#pragma unroll
+        for (int kc = 0; kc < PC; kc += KG) {
+            if (kc >= pc) {  // uniform: the wave's bands end here
+#pragma unroll
+                for (int u = 0; u < KG; ++u) {
+                    term[kc + u] = Acc(0);
+                    col[kc + u] = -1;
+                }
+                continue;
+            }
+            // keeps the next group's loads behind this group's use of its own
+            // (so that only one group's terms are held in registers)
+            asm volatile("" ::: "memory");
+            Acc a1[KG], a2[KG], lt[KG], ed[KG];
+            bool has2[KG], hasE[KG];
+#pragma unroll
+            for (int u = 0; u < KG; ++u) {
+                const int k = kc + u, b = b0 + k;
+                const int i = left_chain ? s + (b + 1) * H : s - (b + 1) * H;
+                const bool ok = tval && k < pc && b < g.B && i >= 0 && i < N;
+                col[k] = ok ? i : -1;
+                const int ii = ok ? i : 0, bb = ok ? b : 0;
+                const int c = ii / W, x = ii - c * W;
+                const Acc* ainb = K.ain + (size_t)bb * N;
+                int i1, i2, ie;
+                if (left_chain) {
+                    i1 = ii;
+                    has2[u] = ii >= H;
+                    i2 = has2[u] ? ii - H : 0;
+                    hasE[u] = x < H - 1 && c > 0;
+                    ie = hasE[u] ? (int)(((size_t)bb * T + (c - 1)) * H + (H - 2 - x)) : 0;
+                } else {
+                    i1 = (ii + H - 1 < N - 1) ? ii + H - 1 : N - 1;
+                    has2[u] = ii >= 1;
+                    i2 = has2[u] ? ii - 1 : 0;
+                    hasE[u] = x > W - H && c < T - 1;
+                    ie = hasE[u] ? (int)(((size_t)bb * T + (c + 1)) * H + (H - 2 - (W - 1 - x))) : 0;
+                }
+                a1[u] = ainb[i1];
+                a2[u] = ainb[i2];
+                lt[u] = (left_chain ? A.tLend : A.tRend)[(size_t)bb * N + ii];
+                ed[u] = (left_chain ? A.tLedge : A.tRedge)[ie];
+            }
+#pragma unroll
+            for (int u = 0; u < KG; ++u) {
+                Acc v = a1[u] - (has2[u] ? a2[u] : Acc(0));
+                v += lt[u];
+                if (hasE[u]) v += ed[u];
+                term[kc + u] = col[kc + u] >= 0 ? v : Acc(0);
+            }
+        }
+    } else {
 #pragma unroll
     for (int k = 0; k < PC; ++k) {
         term[k] = Acc(0);
@@ -451,6 +511,7 @@ __device__ __forceinline__ void scan_diag_body(const Geom& g, const Agg<Acc>& A,
             if (x > W - H && c < T - 1) v += A.tRedge[((size_t)b * T + (c + 1)) * H + (H - 2 - (W - 1 - x))];
         }
         term[k] = v;
+    }
     }
     Acc run = Acc(0);
 #pragma unroll
