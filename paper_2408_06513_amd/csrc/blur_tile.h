@@ -11,6 +11,7 @@
 namespace inim {
 
 constexpr int kBX = 64, kBY = 16;
+constexpr int kBlurThreads = 256;  // threads of every block that blurs a tile
 
 // Half-sample symmetric continuation: index -1-t reads t, N+t reads N-1-t
 // (period 2N).  Indices within one raster width of the border are reflected
@@ -30,7 +31,7 @@ __host__ __device__ inline size_t blur_smem_floats(int r) {
     return (size_t)(kBY + 2 * r) * (kBX + 2 * r) + (size_t)(kBY + 2 * r) * kBX;
 }
 
-// Blurs the output tile at (ox, oy) with a block of 256 threads: the
+// Blurs the output tile at (ox, oy) with a block of kBlurThreads threads: the
 // (16+2r) x (64+2r) window of counts is staged in `lds` as float, filtered
 // along x into a second LDS buffer, then along y; emit(row, col, value) is
 // called once for every output texel of the tile inside the raster.
@@ -51,24 +52,36 @@ __device__ __forceinline__ void blur_tile_r(const uint32_t* __restrict__ counts,
     // the window in chunks of 4 columns: a chunk inside the raster is one
     // 16-byte load (its first column, ox - R + 4q, is a multiple of 4; the
     // raster's base must be 16-byte aligned, else every chunk takes the other
-    // path), a chunk over the border takes its 4 mirrored columns one by one
+    // path), a chunk over the border takes its 4 mirrored columns one by one.
+    // Each thread loads all its chunks before storing any, so the window costs
+    // one round of memory latency (a thread past the last chunk reloads the
+    // last one and stores nothing).
     const bool vec = (reinterpret_cast<uintptr_t>(counts) & 15u) == 0u;
     if (R > 0 && R % 4 == 0 && vec) {
-        constexpr int IWc = kBX + 2 * R, IHc = kBY + 2 * R, CW = IWc / 4;
-        for (int k = threadIdx.x; k < IHc * CW; k += blockDim.x) {
+        constexpr int IWc = kBX + 2 * R, IHc = kBY + 2 * R, CW = IWc / 4, ITEMS = IHc * CW;
+        constexpr int PER = (ITEMS + kBlurThreads - 1) / kBlurThreads;
+        uint4 u[PER];
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int k0 = (int)threadIdx.x + t * kBlurThreads, k = k0 < ITEMS ? k0 : ITEMS - 1;
             const int row = k / CW, q = k - row * CW;
             const int gj = mirror(oy + row - R, N);
             const int c0 = ox - R + 4 * q;
             const uint32_t* src = counts + (size_t)gj * N;
-            float4 v;
-            if (c0 >= 0 && c0 + 3 < N) {
-                const uint4 u = *reinterpret_cast<const uint4*>(src + c0);
-                v = make_float4((float)u.x, (float)u.y, (float)u.z, (float)u.w);
-            } else {
-                v = make_float4((float)src[mirror(c0, N)], (float)src[mirror(c0 + 1, N)], (float)src[mirror(c0 + 2, N)],
-                                (float)src[mirror(c0 + 3, N)]);
+            if (c0 >= 0 && c0 + 3 < N)
+                u[t] = *reinterpret_cast<const uint4*>(src + c0);
+            else
+                u[t] = make_uint4(src[mirror(c0, N)], src[mirror(c0 + 1, N)], src[mirror(c0 + 2, N)],
+                                  src[mirror(c0 + 3, N)]);
+        }
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int k = (int)threadIdx.x + t * kBlurThreads;
+            if (k < ITEMS) {
+                const int row = k / CW, q = k - row * CW;
+                *reinterpret_cast<float4*>(in + row * IWc + 4 * q) =
+                    make_float4((float)u[t].x, (float)u[t].y, (float)u[t].z, (float)u[t].w);
             }
-            *reinterpret_cast<float4*>(in + row * IWc + 4 * q) = v;
         }
     } else {
         for (int k = threadIdx.x; k < IH * IW; k += blockDim.x) {
