@@ -433,13 +433,27 @@ __device__ __forceinline__ void row_hist_body(const float2* __restrict__ xy, int
     for (int j = threadIdx.x; j < N; j += kRowThreads) bins[j] = 0u;
     __syncthreads();
     const int64_t tile = row_tile(n), p0 = b * tile, p1 = min(n, p0 + tile);
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += kRowThreads) {
-        const float2 q = xy[p];
-        if (!in_unit_square(q)) {
-            flag_domain(status);
-            continue;
+    // kHistPer samples per thread and round, all loaded before any is counted
+    // (a thread past p1 reloads sample p0 and discards it)
+    constexpr int kHistPer = 8;
+    for (int64_t base = p0; base < p1; base += (int64_t)kRowThreads * kHistPer) {
+        float2 q[kHistPer];
+#pragma unroll
+        for (int k = 0; k < kHistPer; ++k) {
+            if (base + (int64_t)k * kRowThreads >= p1) break;  // uniform: no sample left for any thread
+            const int64_t p = base + threadIdx.x + (int64_t)k * kRowThreads;
+            q[k] = xy[p < p1 ? p : p0];
         }
-        atomicAdd(&bins[texel_of(q.y, N)], 1u);
+#pragma unroll
+        for (int k = 0; k < kHistPer; ++k) {
+            const int64_t p = base + threadIdx.x + (int64_t)k * kRowThreads;
+            if (p >= p1) continue;
+            if (!in_unit_square(q[k])) {
+                flag_domain(status);
+                continue;
+            }
+            atomicAdd(&bins[texel_of(q[k].y, N)], 1u);
+        }
     }
     __syncthreads();
     for (int j = threadIdx.x; j < N; j += kRowThreads) hist[(size_t)b * N + j] = bins[j];
@@ -526,11 +540,17 @@ __device__ __forceinline__ void row_bucket_body(const float2* __restrict__ xy, i
     constexpr int kPer = CHUNK / kRowThreads, kRowsPer = kRowSortMaxN / kRowThreads;
     const int per = (N + kRowThreads - 1) / kRowThreads, r0 = threadIdx.x * per;
     {
-        uint32_t v[kRowsPer];
+        // the row totals and this tile's prefixes are loaded together (one
+        // round of memory latency) at valid indices, the unused ones discarded
+        uint32_t v[kRowsPer], pf[kRowsPer];
         uint32_t sum = 0;
 #pragma unroll
         for (int k = 0; k < kRowsPer; ++k) {
-            v[k] = (k < per && r0 + k < N) ? rowtot[r0 + k] : 0u;
+            const bool in = k < per && r0 + k < N;
+            const int j = in ? r0 + k : 0;
+            const uint32_t t_ = rowtot[j];
+            pf[k] = prefix[(size_t)b * N + j];
+            v[k] = in ? t_ : 0u;
             sum += v[k];
         }
         uint32_t total;
@@ -539,7 +559,7 @@ __device__ __forceinline__ void row_bucket_body(const float2* __restrict__ xy, i
         for (int k = 0; k < kRowsPer; ++k)
             if (k < per && r0 + k < N) {
                 const int j = r0 + k;
-                L.next[j] = run + prefix[(size_t)b * N + j];
+                L.next[j] = run + pf[k];
                 if (b == 0) rowstart[j] = run;
                 run += v[k];
             }
@@ -549,13 +569,20 @@ __device__ __forceinline__ void row_bucket_body(const float2* __restrict__ xy, i
         const int m = (int)min((int64_t)CHUNK, p1 - c0);
         for (int j = threadIdx.x; j < N; j += kRowThreads) L.cnt[j] = 0u;
         __syncthreads();
+        // the chunk's samples are all loaded before any is counted (one round
+        // of memory latency; a thread past m reloads sample c0 and discards it)
         float2 q[kPer];
         uint32_t row[kPer], rk[kPer];
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
+            if (k * kRowThreads >= m) break;  // uniform: no sample left for any thread
+            const int s = threadIdx.x + k * kRowThreads;
+            q[k] = xy[c0 + (s < m ? s : 0)];
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
             const int s = threadIdx.x + k * kRowThreads;
             if (s < m) {
-                q[k] = xy[c0 + s];
                 row[k] = (uint32_t)texel_of(q[k].y, N);
                 rk[k] = atomicAdd(&L.cnt[row[k]], 1u);
             }
@@ -647,12 +674,19 @@ __device__ __forceinline__ void row_sort_body(const float2* __restrict__ stage, 
     float2 v[kSortHeld];
     uint32_t col[kSortHeld], from[kSortHeld];
     if (held) {
+        // every held sample's loads first (one round of memory latency; a
+        // lane past q1 reloads sample q0 and discards it), then the counts
+#pragma unroll
+        for (int k = 0; k < kSortHeld; ++k) {
+            if (q0 + k * kSortThreads >= q1) break;  // uniform: no sample left for any lane
+            const int64_t q = q0 + t + k * kSortThreads, qq = q < q1 ? q : q0;
+            v[k] = stage[qq];
+            from[k] = idx[qq];
+        }
 #pragma unroll
         for (int k = 0; k < kSortHeld; ++k) {
             const int64_t q = q0 + t + k * kSortThreads;
             if (q < q1) {
-                v[k] = stage[q];
-                from[k] = idx[q];
                 col[k] = key(v[k]);
                 atomicAdd(&L.bins[col[k]], 1u);
             }
