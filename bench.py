@@ -50,13 +50,13 @@ PAPER_ITERS_PER_S = 8 / 12.63e-3  # Table 1: 8 iterations, 1M points, 1024^2, r 
 # that hold the kernels (k_inim.hip, k_raster.hip) and every header;
 # otherwise traffic is null.
 TRAFFIC = {
-    "src_sha256": "a22f36c41b457ad58cb7c18edb48b498bac41ee92fe5ae620170a9fae0d9eab7",
+    "src_sha256": "64c654500b4bb1210459632f574d9f3c7931fa8c2009f5394c13f32fe3f89fe4",
     # k_blur_aggregate: FETCH_SIZE 4129.1 KiB x 1.99982 + WRITE_SIZE 10112.0 KiB x 1.000
     "smooth_aggregate": 18810324,
-    # k_inim_deform16x2: FETCH_SIZE 7840.0 KiB x 1.99982 + WRITE_SIZE 8192.0 KiB x 1.000
-    "inim_deform": 24443483,
-    # k_advect (1M samples): FETCH_SIZE 18650.5 KiB x 1.99982 + WRITE_SIZE 15538.1 KiB x 1.000
-    "advect_splat": 54103801,
+    # k_inim_deform16x2: FETCH_SIZE 7840.1 KiB x 1.99982 + WRITE_SIZE 8192.0 KiB x 1.000
+    "inim_deform": 24443688,
+    # k_advect (1M samples): FETCH_SIZE 18650.1 KiB x 1.99982 + WRITE_SIZE 15536.7 KiB x 1.000
+    "advect_splat": 54101548,
 }
 
 
