@@ -397,12 +397,13 @@ def test_regularize_edge_sizes(capi, dev, res, n, radius):
     assert np.abs(got - ref).max() <= 1e-5
 
 
-@pytest.mark.parametrize("res,n,iters", [(256, 1, 2), (256, 70_001, 2), (512, 1_100_003, 1), (2048, 5, 2),
-                                         (2048, 3_000, 2), (4096, 20_000, 1)])
+@pytest.mark.parametrize("res,n,iters", [(256, 1, 2), (256, 70_001, 2), (512, 1_100_003, 1), (1024, 2_200_003, 1),
+                                         (2048, 5, 2), (2048, 3_000, 2), (4096, 20_000, 1)])
 def test_regularize_row_sorted_sizes(capi, dev, res, n, iters):
     """Rasters of 256^2 to 4096^2, where the samples are put in texel order by
     row buckets and a per-row sort in LDS: a single sample, a ragged count
-    over the 256 sample tiles, tiles of more than one 4096-sample chunk, few
+    over the 256 sample tiles, tiles of more than one 4096-sample chunk, tiles
+    of more than one round of the row histogram's loads (8192 samples), few
     samples on a large raster (the per-row sort takes two rows a block), the
     largest raster of that path."""
     xy = dg.plain_small(8)[:n] if n <= 20_000 else dg.plain_large(2, n=n)
