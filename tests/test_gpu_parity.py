@@ -240,6 +240,27 @@ def test_inim_full_size_8192(capi, dev, dtype):
         assert m["C"] == rm["C"] if dtype == "u32" else abs(m["C"] - rm["C"]) <= 1e-12 * rm["C"]
 
 
+def test_inim_u32_largest_raster_16384(capi, dev):
+    """The largest raster the library accepts, 16384 x 16384 uint32 (counts
+    0..3, total below 2^32): all eight planes and the marginals bit-exact
+    against the oracle."""
+    res = 16384
+    g = np.random.Generator(np.random.PCG64(16384))
+    img = g.integers(0, 4, size=(res, res), dtype=np.uint32)
+    note("inim 16384 u32")
+    planes, marg = capi.inim(to_dev(img, dev), 0xFF)
+    torch.cuda.synchronize()
+    img64 = img.astype(np.float64)
+    m = capi.split_marg(marg.cpu().numpy(), res)
+    for k in range(8):
+        ref, rm = oracle.planes(img64, 1 << k)
+        assert np.array_equal(planes[k].cpu().numpy().astype(np.float64), ref[0]), oracle.PLANES[k]
+        del ref
+    for key in "XYUV":
+        assert np.array_equal(m[key], rm[key]), key
+    assert m["C"] == rm["C"]
+
+
 # ------------------------------------------------------------------ rasterize
 @pytest.mark.parametrize("res,radius", [(2, 8), (64, 3), (256, 8), (1024, 8), (256, 0), (512, 32)])
 def test_rasterize(capi, dev, res, radius):
