@@ -433,6 +433,16 @@ def test_regularize_row_sorted_sizes(capi, dev, res, n, iters):
     assert np.abs(got - oracle.regularize(xy, res, iters)).max() <= 1e-5
 
 
+def test_regularize_large_raster_8192(capi, dev):
+    """8192^2, past the row-sorted range: the texel order from global ranks,
+    the blur and the integral images in separate passes on 128 x 32 tiles,
+    and the deformation from the general final pass."""
+    xy = dg.plain_large(3, n=200_000)
+    note("regularize res=8192 (oracle takes tens of seconds)")
+    got = gpu_regularize(capi, dev, xy, 8192, 1)
+    assert np.abs(got - oracle.regularize(xy, 8192, 1)).max() <= 1e-5
+
+
 def test_regularize_crowded_row_and_texel(capi, dev):
     """150k samples in one texel row and 50k in one texel (512^2): the row and
     texel buckets far larger than a block."""
